@@ -1,0 +1,210 @@
+"""Seeded synthetic inputs for the wide/tall sparse product path.
+
+This package is shared by the tests, the CPU oracle checks and the benchmark.
+It holds none of the product arithmetic: it only decides sparsity patterns,
+values and dense vectors, deterministically from a seed.
+
+Workloads (all column-major / CSC; a tall row-major matrix is the same arrays
+read as CSR of the transpose):
+
+* ``c0`` -- small wide matrix, m=1,000, n=100,000, ~1.0e6 nonzeros: column
+  lengths from a truncated Zipf(1.1) law plus 5 fully dense columns, rows
+  uniform without repeats, values / x / v uniform in [-1, 1).
+* ``c1`` -- large document-term-shaped wide matrix, m=50,000, n=2e7, ~2.0e8
+  nonzeros: Zipf(1.1) column lengths plus 100 columns at 50% fill, rows drawn
+  with Zipf(0.8) popularity over a seeded permutation of the rows, values
+  lognormal(0,1) with a random sign, x / v uniform in [-1, 1).
+* ``c2`` -- batching matrix, m=20,000, n=5e6, ~5.0e7 nonzeros, c1's law.
+
+The column-length law is read as i.i.d. Zipf(1.1) truncated to {1..K}, with K
+the smallest integer whose mean reaches (nnz - dense nonzeros) / n; the long
+columns are the explicit dense ones.  These stand in for the document-term
+matrix (News20) the paper measures on, which is not available here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+
+SEED_BASE = 18120904
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.syn_fill.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p]
+        lib.syn_fill.restype = ctypes.c_int
+        lib.syn_vector.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                   ctypes.c_void_p]
+        lib.syn_vector.restype = None
+        _lib = lib
+    return _lib
+
+
+VALUE_KINDS = {"uniform": 0, "lognormal": 1, "int": 2, "ones": 3}
+
+
+@dataclass
+class Sparse:
+    """Column-major arrays of an m x n matrix (or, read as CSR, of its n x m transpose)."""
+    m: int
+    n: int
+    ptr: np.ndarray   # int64, n+1
+    idx: np.ndarray   # int32, nnz, strictly increasing within each column
+    val: np.ndarray   # float64, nnz
+
+    @property
+    def nnz(self) -> int:
+        return int(self.ptr[-1])
+
+
+def zipf_lengths_K(alpha: float, target_mean: float, kmax: int) -> int:
+    """Smallest K such that Zipf(alpha) truncated to {1..K} has mean >= target_mean."""
+    ls = np.arange(1, kmax + 1, dtype=np.float64)
+    w = ls ** (-alpha)
+    means = np.cumsum(w * ls) / np.cumsum(w)
+    hit = np.nonzero(means >= target_mean)[0]
+    return int(hit[0] + 1) if hit.size else kmax
+
+
+def _seed64(ss: np.random.SeedSequence) -> int:
+    return int(ss.generate_state(1, dtype=np.uint64)[0])
+
+
+def from_lengths(m: int, lengths: np.ndarray, seed: int, row_alpha: float | None = None,
+                 values: str = "uniform", row_perm_seed: int | None = None) -> Sparse:
+    """Fill a pattern whose column lengths are given (each <= m)."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    n = lengths.size
+    if lengths.size and (lengths.min() < 0 or lengths.max() > m):
+        raise ValueError("column lengths must lie in [0, m]")
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lengths, out=ptr[1:])
+    nnz = int(ptr[-1])
+    idx = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    ss = np.random.SeedSequence(seed)
+    s_fill, s_perm = ss.spawn(2)
+    cdf = perm = None
+    if row_alpha is not None and m > 0:
+        w = np.arange(1, m + 1, dtype=np.float64) ** (-row_alpha)
+        cdf = np.cumsum(w) / w.sum()
+        cdf[-1] = 1.0
+        rng = np.random.Generator(np.random.PCG64(s_perm if row_perm_seed is None else row_perm_seed))
+        perm = rng.permutation(m).astype(np.int32)
+    rc = _load().syn_fill(m, n, _seed64(s_fill), ptr.ctypes.data,
+                          cdf.ctypes.data if cdf is not None else None,
+                          perm.ctypes.data if perm is not None else None,
+                          VALUE_KINDS[values], idx.ctypes.data, val.ctypes.data)
+    if rc != 0:
+        raise MemoryError("syn_fill failed")
+    return Sparse(m, n, ptr, idx, val)
+
+
+def vector(length: int, seed: int, stream: int = 0, kind: str = "uniform") -> np.ndarray:
+    """Dense vector, uniform in [-1, 1) or integers in [-8, 8]."""
+    out = np.empty(length, dtype=np.float64)
+    if length:
+        _load().syn_vector(length, _seed64(np.random.SeedSequence([seed, stream])), stream,
+                           2 if kind == "int" else 0, out.ctypes.data)
+    return out
+
+
+def wide(m: int, n: int, nnz: int, seed: int, len_alpha: float = 1.1, n_dense: int = 0,
+         dense_fill: float = 1.0, row_alpha: float | None = None, values: str = "uniform") -> Sparse:
+    """Wide matrix with truncated-Zipf column lengths plus `n_dense` dense columns."""
+    ss = np.random.SeedSequence(seed)
+    s_len, s_dense, s_fill = ss.spawn(3)
+    dense_len = int(round(dense_fill * m))
+    target = max(nnz - n_dense * dense_len, 0) / max(n, 1)
+    K = min(zipf_lengths_K(len_alpha, target, max(m // 2, 1)), m)
+    ls = np.arange(1, K + 1, dtype=np.float64)
+    pmf = ls ** (-len_alpha)
+    cdf = np.cumsum(pmf) / pmf.sum()
+    cdf[-1] = 1.0
+    rng = np.random.Generator(np.random.PCG64(s_len))
+    lengths = (np.searchsorted(cdf, rng.random(n), side="right") + 1).astype(np.int64)
+    np.minimum(lengths, K, out=lengths)
+    if n_dense:
+        rd = np.random.Generator(np.random.PCG64(s_dense))
+        cols = rd.choice(n, size=min(n_dense, n), replace=False)
+        lengths[cols] = dense_len
+    return from_lengths(m, lengths, _seed64(s_fill), row_alpha=row_alpha, values=values)
+
+
+CONFIGS = {
+    "c0": dict(m=1_000, n=100_000, nnz=1_000_000, len_alpha=1.1, n_dense=5, dense_fill=1.0,
+               row_alpha=None, values="uniform"),
+    "c1": dict(m=50_000, n=20_000_000, nnz=200_000_000, len_alpha=1.1, n_dense=100, dense_fill=0.5,
+               row_alpha=0.8, values="lognormal"),
+    "c2": dict(m=20_000, n=5_000_000, nnz=50_000_000, len_alpha=1.1, n_dense=100, dense_fill=0.5,
+               row_alpha=0.8, values="lognormal"),
+}
+CONFIG_IDS = {"c0": 0, "c1": 1, "c2": 2, "c3": 3, "c4": 4}
+
+
+def config_matrix(name: str, scale: float = 1.0) -> Sparse:
+    """The named workload's matrix; `scale` < 1 shrinks n and nnz (same law) for quick runs."""
+    c = dict(CONFIGS[name])
+    if scale != 1.0:
+        c["n"] = max(int(c["n"] * scale), 1)
+        dense_nnz = c["n_dense"] * int(round(c["dense_fill"] * c["m"]))
+        c["nnz"] = int((c["nnz"] - dense_nnz) * scale) + dense_nnz
+    return wide(seed=SEED_BASE + CONFIG_IDS[name], **c)
+
+
+def config_vectors(name: str, m: int, n: int, k: int = 1):
+    """(x, v) for a workload: x has n entries (or n x k), v has m entries (or m x k)."""
+    sid = SEED_BASE + CONFIG_IDS[name]
+    if k == 1:
+        return vector(n, sid, 1), vector(m, sid, 2)
+    return vector(n * k, sid, 3).reshape(n, k), vector(m * k, sid, 4).reshape(m, k)
+
+
+def random_csc(m: int, n: int, mean_len: float, seed: int, values: str = "uniform",
+               empty_frac: float = 0.0, max_len: int | None = None,
+               row_alpha: float | None = None) -> Sparse:
+    """Small test matrices: geometric-ish lengths with a given mean, optional empty columns."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 7])))
+    cap = m if max_len is None else min(max_len, m)
+    if n == 0:
+        lengths = np.zeros(0, dtype=np.int64)
+    else:
+        lengths = np.minimum(rng.geometric(1.0 / max(mean_len, 1.0), size=n), cap).astype(np.int64)
+        if empty_frac > 0:
+            lengths[rng.random(n) < empty_frac] = 0
+    return from_lengths(m, lengths, seed, row_alpha=row_alpha, values=values)
+
+
+def to_dense(A: Sparse) -> np.ndarray:
+    """Dense m x n copy (for brute-force checks on tiny matrices only)."""
+    D = np.zeros((A.m, A.n), dtype=np.float64)
+    for j in range(A.n):
+        s, e = A.ptr[j], A.ptr[j + 1]
+        D[A.idx[s:e], j] = A.val[s:e]
+    return D
