@@ -1,0 +1,191 @@
+/*
+ * spw.h -- sparse wide/tall matrix-vector products on AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Eckstein & Matyasfalvi, "Efficient Distributed-
+ * Memory Parallel Matrix-Vector Multiplication with Wide or Tall Unstructured
+ * Sparse Matrices" (arXiv:1812.00904), Section I: for a sparse A in R^{m x n},
+ * y = A x (x in R^n, y in R^m) and u^T = v^T A (v in R^m, u in R^n).  A is very
+ * wide (m << n) and stored column-major (CSC), or very tall (m >> n) and stored
+ * row-major (CSR): Section II handles the tall case by swapping the roles of
+ * rows and columns, and so does this library.  The work of one product is
+ * split among GPU workgroups by equal runs of nonzeros that may cut a column
+ * (Section II); cut columns are completed by summing the partial dot products
+ * of the chunks that share them (Section IV-A), and A x sums per-workgroup
+ * partial y vectors in a fixed order (Section III).  Results are bit-identical
+ * from run to run.
+ *
+ * Conventions for every entry point:
+ *   - All functions return spw_status; nothing is thrown across this boundary.
+ *     On a non-OK status spw_last_error() returns a message for the calling
+ *     thread, naming the first offending argument or position.
+ *   - Indices are 0-based.  Host arrays passed to spw_create are copied; the
+ *     caller may free them on return.  A matrix is immutable after creation.
+ *   - Vector arguments (x, y, v, u, X, Y, V, U) are DEVICE pointers owned by the
+ *     caller, on the device the matrix lives on, not aliasing one another.
+ *     Outputs are overwritten, not accumulated into.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Products are
+ *     asynchronous on that stream; outputs are valid once it has synchronized.
+ *     Calls on one matrix handle must be ordered (one stream at a time): the
+ *     handle owns the scratch (partial sums, carries) that a call uses.
+ *   - Products never allocate device memory, except the first multi-RHS call
+ *     with a block width larger than any before it on that handle (which grows
+ *     the handle's scratch once, synchronously).
+ */
+#ifndef SPW_H
+#define SPW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPW_OK = 0,
+    SPW_ERR_INVALID_ARG = 1,   /* NULL pointer, negative size, bad enum, k < 1, ld < k ... */
+    SPW_ERR_BAD_MATRIX = 2,    /* ptr not monotone / wrong ends, index out of range or not strictly increasing */
+    SPW_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+    SPW_ERR_BUDGET = 4,        /* serving: registering or admitting would exceed the HBM budget */
+    SPW_ERR_DEVICE = 5,        /* a HIP runtime call or kernel launch failed */
+    SPW_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement (e.g. nnz >= 2^31) */
+    SPW_ERR_BUSY = 7,          /* serving: queue full */
+    SPW_ERR_TIMEOUT = 8,       /* serving: wait timed out (the request stays queued) */
+    SPW_ERR_SHUTDOWN = 9       /* serving: server is shutting down */
+} spw_status;
+
+typedef enum { SPW_CSC = 0 /* wide, column-major */, SPW_CSR = 1 /* tall, row-major */ } spw_format;
+
+typedef enum { SPW_F64 = 0, SPW_F32 = 1, SPW_BF16 = 2 } spw_dtype;
+
+typedef struct spw_matrix_s *spw_matrix;
+
+/* Creation options.  Zero-initialise, set struct_size = sizeof(spw_create_opts),
+ * or call spw_create_opts_default.  NULL opts means defaults.
+ *   value_storage : F64 (default), F32 or BF16 -- the stored nonzero values are
+ *                   rounded once from the given binary64 values, to nearest even.
+ *   chunk_nnz     : nonzeros per transpose-product chunk (0 = automatic; must be
+ *                   a multiple of 512 when given).
+ *   relabel       : -1 automatic, 0 off, 1 on.  On: rows are renumbered inside
+ *                   the library by descending nonzero count, so the most used
+ *                   entries of the short vector share cache lines; results are
+ *                   returned in the caller's numbering.
+ *   validate      : 1 (default) checks the arrays in O(nnz); 0 trusts them.
+ *   panel_rows    : rows per on-chip accumulation panel for A x (0 = automatic).
+ *   device        : HIP device ordinal, -1 = the current device. */
+typedef struct {
+    uint32_t struct_size;
+    spw_dtype value_storage;
+    int32_t chunk_nnz;
+    int32_t relabel;
+    int32_t validate;
+    int32_t panel_rows;
+    int32_t device;
+    int32_t reserved[8];
+} spw_create_opts;
+
+/* Read-only description of a created matrix. */
+typedef struct {
+    uint32_t struct_size;
+    spw_format format;
+    spw_dtype value_storage;
+    int64_t m, n, nnz;            /* as given by the caller */
+    int64_t inner_rows;           /* short dimension (m for CSC, n for CSR) */
+    int64_t inner_cols;           /* long dimension */
+    int64_t chunk_nnz;            /* transpose-product chunk size */
+    int64_t n_chunks;             /* number of chunks (the paper's P) */
+    int64_t n_zones;              /* columns cut by a chunk boundary (the paper's z) */
+    int64_t n_panels;             /* row panels used by A x (long-dimension scatter) */
+    int64_t panel_rows;
+    int64_t mv_workgroups;        /* workgroups (partial vectors) of the scatter product */
+    int64_t index_bytes;          /* bytes per stored row index (2 or 4) */
+    int32_t relabeled;            /* rows renumbered by frequency */
+    int32_t device;
+    int64_t device_bytes;         /* device memory held by the handle */
+} spw_matrix_info;
+
+/* ---------------------------------------------------------------- matrices */
+
+spw_status spw_create_opts_default(spw_create_opts *opts);
+
+/* Create a matrix from host arrays.
+ *   fmt == SPW_CSC: ptr has n+1 entries, column j holds positions ptr[j]..ptr[j+1]-1,
+ *                   idx[p] is the row (0 <= idx < m), strictly increasing inside a column.
+ *   fmt == SPW_CSR: ptr has m+1 entries, row i holds ptr[i]..ptr[i+1]-1, idx[p] is the
+ *                   column (0 <= idx < n), strictly increasing inside a row.
+ *   ptr[0] == 0, ptr nondecreasing, ptr[last] == nnz.  val has nnz entries.
+ *   nnz == 0 is valid (all products are zero); m or n may be 0.
+ * Limits of this build: nnz < 2^31, short dimension < 2^31.
+ * Errors: SPW_ERR_INVALID_ARG (NULL out/ptr, NULL idx/val with nnz > 0, negative sizes),
+ *         SPW_ERR_BAD_MATRIX (validation), SPW_ERR_OUT_OF_MEMORY, SPW_ERR_DEVICE,
+ *         SPW_ERR_UNSUPPORTED. */
+spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz,
+                      const int64_t *ptr, const int32_t *idx, const double *val,
+                      const spw_create_opts *opts);
+
+/* Release the matrix and its device memory (waits for the device first).  NULL is a no-op. */
+spw_status spw_destroy(spw_matrix A);
+
+spw_status spw_info(spw_matrix A, spw_matrix_info *out);
+
+/* --------------------------------------------------------------- products */
+
+/* y := A x (Section I; for CSC, Section III's nonzero-split product).
+ * x: device, n entries of type vdt; y: device, m entries of type vdt.
+ * vdt: SPW_F64, or SPW_F32 (binary32 vectors; accumulation is binary32 with
+ * compensated sums inside a workgroup and binary64 across workgroups). */
+spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream);
+
+/* u^T := v^T A (Section I; for CSC, Section IV-A's per-column dot with zone sums).
+ * v: device, m entries of type vdt; u: device, n entries of type vdt. */
+spw_status spw_vtm(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *stream);
+
+/* Multi-right-hand-side forms, one pass over A for k vectors (1 <= k <= 64).
+ * X: device, row-major n x k with leading dimension ldx >= k (X[j*ldx + c]);
+ * Y: device, row-major m x k, ldy >= k.  Column c of Y equals spw_mv on column c
+ * of X up to rounding order. */
+spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, int64_t ldx,
+                        void *Y, int64_t ldy, void *stream);
+
+/* V: device, row-major m x k (ldv >= k); U: device, row-major n x k (ldu >= k). */
+spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv,
+                         void *U, int64_t ldu, void *stream);
+
+/* ---------------------------------------------------------- host-only plan */
+
+/* The chunk / zone plan the transpose product uses, computed on the host from a
+ * column pointer array (no device needed).  Chunk c holds positions
+ * [c*chunk_nnz, min((c+1)*chunk_nnz, nnz)).  A zone is a column cut by a chunk
+ * boundary (Section II's overlap zone); its chunk set S_k is the contiguous run
+ * zone_first[k]..zone_last[k] (Table I).  chunk_owned[c] is the first column
+ * whose start lies in chunk c (chunk_owned[n_chunks] = n).  Pass NULL arrays to
+ * query the counts; otherwise arrays must hold n_chunks+1 / n_zones entries. */
+spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz,
+                          int64_t *n_chunks, int64_t *n_zones, int64_t *chunk_owned,
+                          int64_t *zone_col, int64_t *zone_first, int64_t *zone_last);
+
+/* -------------------------------------------------------------- profiling */
+
+/* When enabled (per process), every kernel launch of the library is bracketed
+ * by HIP events on the launch stream; spw_profile_read returns, per kernel
+ * name, the launch count and total milliseconds of the launches completed
+ * since the last reset (it synchronizes those events).  Off by default. */
+spw_status spw_profile_enable(int32_t on);
+spw_status spw_profile_reset(void);
+/* Fills up to `cap` entries; *count receives the number of distinct kernels. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} spw_profile_entry;
+spw_status spw_profile_read(spw_profile_entry *entries, int32_t cap, int32_t *count);
+
+/* ----------------------------------------------------------------- errors */
+
+const char *spw_last_error(void);
+const char *spw_status_string(spw_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPW_H */

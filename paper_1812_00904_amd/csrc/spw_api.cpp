@@ -1,0 +1,629 @@
+// C ABI of libspw: matrix creation (validation, row renumbering, chunk/zone
+// plan, row panels), products, and error reporting.  See include/spw.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "spw_internal.h"
+
+namespace spw {
+
+static thread_local std::string t_err;
+void set_error(const std::string &msg) { t_err = msg; }
+
+namespace {
+
+template <typename F>
+void parallel_for(int64_t n, F &&f)
+{
+    int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    if (n < (int64_t)1 << 16 || nt == 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t per = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t a = t * per, b = std::min(n, a + per);
+        if (a >= b) break;
+        th.emplace_back([&f, a, b] { f(a, b); });
+    }
+    for (auto &t : th) t.join();
+}
+
+spw_status fail(spw_status s, const std::string &msg)
+{
+    set_error(msg);
+    return s;
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Device allocation owned by the matrix (freed in spw_destroy).
+template <typename T>
+spw_status dev_alloc(spw_matrix_s &A, T **out, int64_t count, const char *what)
+{
+    *out = nullptr;
+    const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPW_ERR_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what + " (" +
+                                               std::to_string(bytes) + " bytes)");
+    }
+    A.allocations.push_back(p);
+    A.device_bytes += (int64_t)bytes;
+    *out = (T *)p;
+    return SPW_OK;
+}
+
+spw_status h2d(void *dst, const void *src, size_t bytes, const char *what)
+{
+    if (bytes == 0) return SPW_OK;
+    if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPW_ERR_DEVICE, std::string("hipMemcpy to device failed for ") + what);
+    }
+    return SPW_OK;
+}
+
+void free_all(spw_matrix_s *A)
+{
+    for (void *p : A->allocations) (void)hipFree(p);
+    A->allocations.clear();
+}
+
+spw_status validate(int64_t outer, int64_t inner, int64_t nnz, const int64_t *ptr, const int32_t *idx,
+                    const char *outer_name)
+{
+    if (ptr[0] != 0) return fail(SPW_ERR_BAD_MATRIX, "ptr[0] must be 0, got " + std::to_string(ptr[0]));
+    if (ptr[outer] != nnz)
+        return fail(SPW_ERR_BAD_MATRIX, "ptr[" + std::to_string(outer) + "] must equal nnz = " +
+                                            std::to_string(nnz) + ", got " + std::to_string(ptr[outer]));
+    for (int64_t j = 0; j < outer; ++j)
+        if (ptr[j + 1] < ptr[j])
+            return fail(SPW_ERR_BAD_MATRIX, std::string("ptr decreases at ") + outer_name + " " + std::to_string(j));
+    // indices: in range and strictly increasing inside each column (row)
+    std::vector<int64_t> bad((size_t)std::min<int64_t>(16, std::max<int64_t>(outer, 1)), -1);
+    const int64_t nparts = (int64_t)bad.size();
+    const int64_t per = (outer + nparts - 1) / std::max<int64_t>(nparts, 1);
+    std::vector<std::thread> th;
+    for (int64_t t = 0; t < nparts; ++t) {
+        th.emplace_back([&, t] {
+            const int64_t a = t * per, b = std::min(outer, a + per);
+            for (int64_t j = a; j < b; ++j) {
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
+                    const int32_t r = idx[p];
+                    if (r < 0 || r >= inner || (p > ptr[j] && idx[p - 1] >= r)) {
+                        bad[(size_t)t] = p;
+                        return;
+                    }
+                }
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    for (int64_t b : bad) {
+        if (b >= 0) {
+            const int32_t r = idx[b];
+            std::string why = (r < 0 || r >= inner) ? "index " + std::to_string(r) + " out of range [0, " +
+                                                          std::to_string(inner) + ")"
+                                                    : "indices not strictly increasing inside a " +
+                                                          std::string(outer_name);
+            return fail(SPW_ERR_BAD_MATRIX, "position " + std::to_string(b) + ": " + why);
+        }
+    }
+    return SPW_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool changed = false;
+    spw_status st = SPW_OK;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            (void)hipGetLastError();
+            st = fail(SPW_ERR_DEVICE, "hipGetDevice failed (no usable GPU?)");
+            return;
+        }
+        if (dev >= 0 && dev != prev) {
+            if (hipSetDevice(dev) != hipSuccess) {
+                (void)hipGetLastError();
+                st = fail(SPW_ERR_DEVICE, "hipSetDevice(" + std::to_string(dev) + ") failed");
+                return;
+            }
+            changed = true;
+        }
+    }
+    ~DeviceGuard()
+    {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+// Row panels and workgroups of the scatter product (see spw_internal.h).
+spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx_int, const double *val,
+                            int64_t panel_rows_opt)
+{
+    const int64_t rows = A.rows, cols = A.cols, nnz = A.nnz;
+    const int64_t TILE = mv_tile_nnz();
+    const int64_t limit = mv_lds_rows_limit(SPW_F64, 1);
+    int64_t R = rows;
+    if (panel_rows_opt > 0) R = std::min<int64_t>(panel_rows_opt, limit);
+    else if (rows > limit) {
+        const int64_t P = (rows + limit - 1) / limit;
+        R = (rows + P - 1) / P;
+    }
+    R = std::max<int64_t>(std::min(R, rows), 1);
+    const int64_t P = (rows + R - 1) / R;
+    A.panel_rows = R;
+    A.n_panels = P;
+    A.tile = TILE;
+
+    // Per-panel column pointers (absolute positions) and panel bases.
+    std::vector<int64_t> base((size_t)P + 1, 0);
+    std::vector<int32_t> pptr;
+    const bool u16 = A.idx_kind == IdxKind::U16;
+    auto row_of = [&](int64_t p) -> int64_t {
+        return u16 ? (int64_t)((const uint16_t *)idx_int)[p] : (int64_t)((const int32_t *)idx_int)[p];
+    };
+    if (P == 1) {
+        A.panels_alias = true;
+        A.d_pptr = A.d_ptr;
+        A.d_pidx = A.d_idx;
+        A.d_pval = A.d_val;
+        base[1] = nnz;
+        pptr.resize((size_t)cols + 1);
+        for (int64_t j = 0; j <= cols; ++j) pptr[(size_t)j] = (int32_t)ptr[j];
+    } else {
+        A.panels_alias = false;
+        // count nonzeros per (panel, column)
+        std::vector<int32_t> cnt((size_t)(P * cols), 0);
+        parallel_for(cols, [&](int64_t a, int64_t b) {
+            for (int64_t j = a; j < b; ++j)
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) cnt[(size_t)(row_of(p) / R * cols + j)]++;
+        });
+        std::vector<int64_t> pnnz((size_t)P, 0);
+        for (int64_t q = 0; q < P; ++q) {
+            int64_t s = 0;
+            for (int64_t j = 0; j < cols; ++j) s += cnt[(size_t)(q * cols + j)];
+            pnnz[(size_t)q] = s;
+        }
+        for (int64_t q = 0; q < P; ++q) base[(size_t)q + 1] = round_up(base[(size_t)q] + pnnz[(size_t)q], TILE);
+        if (base[(size_t)P] >= ((int64_t)1 << 31) - TILE)
+            return fail(SPW_ERR_UNSUPPORTED, "panelled storage exceeds 2^31 positions");
+        pptr.resize((size_t)(P * (cols + 1)));
+        for (int64_t q = 0; q < P; ++q) {
+            int64_t run = base[(size_t)q];
+            int32_t *pp = pptr.data() + q * (cols + 1);
+            for (int64_t j = 0; j < cols; ++j) {
+                pp[j] = (int32_t)run;
+                run += cnt[(size_t)(q * cols + j)];
+            }
+            pp[cols] = (int32_t)run;
+        }
+        cnt.clear();
+        cnt.shrink_to_fit();
+        const int64_t total = base[(size_t)P];
+        std::vector<double> pval((size_t)total, 0.0);
+        std::vector<uint16_t> pidx16;
+        std::vector<int32_t> pidx32;
+        if (u16) pidx16.assign((size_t)total, 0);
+        else pidx32.assign((size_t)total, 0);
+        parallel_for(cols, [&](int64_t a, int64_t b) {
+            std::vector<int32_t> cur((size_t)P);
+            for (int64_t j = a; j < b; ++j) {
+                for (int64_t q = 0; q < P; ++q) cur[(size_t)q] = pptr[(size_t)(q * (cols + 1) + j)];
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
+                    const int64_t r = row_of(p), q = r / R;
+                    const int64_t dst = cur[(size_t)q]++;
+                    pval[(size_t)dst] = val[p];
+                    if (u16) pidx16[(size_t)dst] = (uint16_t)(r - q * R);
+                    else pidx32[(size_t)dst] = (int32_t)(r - q * R);
+                }
+            }
+        });
+        int32_t *dp = nullptr;
+        double *dv = nullptr;
+        spw_status st = dev_alloc(A, &dp, P * (cols + 1), "panel column starts");
+        if (st) return st;
+        if ((st = h2d(dp, pptr.data(), pptr.size() * 4, "panel column starts"))) return st;
+        if ((st = dev_alloc(A, &dv, total, "panel values"))) return st;
+        if ((st = h2d(dv, pval.data(), (size_t)total * 8, "panel values"))) return st;
+        A.d_pptr = dp;
+        A.d_pval = dv;
+        if (u16) {
+            uint16_t *di = nullptr;
+            if ((st = dev_alloc(A, &di, total, "panel rows"))) return st;
+            if ((st = h2d(di, pidx16.data(), (size_t)total * 2, "panel rows"))) return st;
+            A.d_pidx = di;
+        } else {
+            int32_t *di = nullptr;
+            if ((st = dev_alloc(A, &di, total, "panel rows"))) return st;
+            if ((st = h2d(di, pidx32.data(), (size_t)total * 4, "panel rows"))) return st;
+            A.d_pidx = di;
+        }
+    }
+
+    // Tiles of each panel and their column ranges.
+    A.tiles.clear();
+    std::vector<int64_t> tile0((size_t)P + 1, 0);
+    for (int64_t q = 0; q < P; ++q) {
+        tile0[(size_t)q] = (int64_t)A.tiles.size();
+        const int32_t *pp = pptr.data() + (A.panels_alias ? 0 : q * (cols + 1));
+        const int64_t b0 = pp[0], b1 = pp[cols];
+        for (int64_t st = b0; st < b1; st += TILE) {
+            const int64_t en = std::min(b1, st + TILE);
+            // column holding st: last j with pp[j] <= st; column holding en-1 likewise
+            const int64_t jlo = std::upper_bound(pp, pp + cols + 1, (int32_t)st) - pp - 1;
+            const int64_t jhi = std::upper_bound(pp, pp + cols + 1, (int32_t)(en - 1)) - pp - 1;
+            A.tiles.push_back(Tile{(int32_t)st, (int32_t)en, (int32_t)jlo, (int32_t)jhi});
+        }
+    }
+    tile0[(size_t)P] = (int64_t)A.tiles.size();
+
+    // Workgroups: as many as fit the chip in one wave of launches, each with a
+    // contiguous run of one panel's tiles.
+    const int cus = device_cu_count(A.device);
+    const int64_t lds = R * 8 + 4160 * 4;
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / std::max<int64_t>(lds, 1)));
+    const int64_t target = (int64_t)cus * per_cu;
+    const int64_t ntiles = (int64_t)A.tiles.size();
+    const int64_t tiles_per_wg = std::max<int64_t>(1, (ntiles + target - 1) / std::max<int64_t>(target, 1));
+    A.wgs.clear();
+    A.panels.clear();
+    for (int64_t q = 0; q < P; ++q) {
+        PanelDesc pd;
+        pd.row0 = (int32_t)(q * R);
+        pd.rows = (int32_t)std::min(R, rows - q * R);
+        pd.wg0 = (int32_t)A.wgs.size();
+        for (int64_t t = tile0[(size_t)q]; t < tile0[(size_t)q + 1]; t += tiles_per_wg)
+            A.wgs.push_back(WgDesc{(int32_t)q, (int32_t)t,
+                                   (int32_t)std::min(tile0[(size_t)q + 1], t + tiles_per_wg), 0});
+        pd.nwg = (int32_t)(A.wgs.size() - (size_t)pd.wg0);
+        A.panels.push_back(pd);
+    }
+    A.mv_wgs = (int64_t)A.wgs.size();
+    spw_status st;
+    if ((st = dev_alloc(A, &A.d_tiles, std::max<int64_t>(ntiles, 1), "tiles"))) return st;
+    if ((st = h2d(A.d_tiles, A.tiles.data(), A.tiles.size() * sizeof(Tile), "tiles"))) return st;
+    if ((st = dev_alloc(A, &A.d_wgs, std::max<int64_t>(A.mv_wgs, 1), "workgroups"))) return st;
+    if ((st = h2d(A.d_wgs, A.wgs.data(), A.wgs.size() * sizeof(WgDesc), "workgroups"))) return st;
+    if ((st = dev_alloc(A, &A.d_panels, P, "panels"))) return st;
+    if ((st = h2d(A.d_panels, A.panels.data(), A.panels.size() * sizeof(PanelDesc), "panels"))) return st;
+    return SPW_OK;
+}
+
+spw_status alloc_scratch(spw_matrix_s &A, int32_t k)
+{
+    if (A.scratch.kcap >= k) return SPW_OK;
+    // grow: free the old buffers (they are tracked in allocations)
+    auto drop = [&](void *p) {
+        if (!p) return;
+        auto it = std::find(A.allocations.begin(), A.allocations.end(), p);
+        if (it != A.allocations.end()) A.allocations.erase(it);
+        (void)hipFree(p);
+    };
+    if (A.scratch.kcap > 0) {
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, "hipDeviceSynchronize failed while growing scratch");
+        }
+    }
+    drop(A.scratch.partial);
+    drop(A.scratch.carry);
+    drop(A.scratch.vperm);
+    A.scratch = Scratch{};
+    spw_status st;
+    if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows * k, "partial sums")))
+        return st;
+    if ((st = dev_alloc(A, &A.scratch.carry, std::max<int64_t>(2 * A.zp.n_chunks, 1) * k, "carries"))) return st;
+    double *vp = nullptr;
+    if ((st = dev_alloc(A, &vp, std::max<int64_t>(A.rows, 1) * k, "renumbered vector"))) return st;
+    A.scratch.vperm = vp;
+    A.scratch.kcap = k;
+    return SPW_OK;
+}
+
+}  // namespace
+}  // namespace spw
+
+using namespace spw;
+
+extern "C" {
+
+const char *spw_last_error(void) { return t_err.c_str(); }
+
+const char *spw_status_string(spw_status s)
+{
+    switch (s) {
+    case SPW_OK: return "SPW_OK";
+    case SPW_ERR_INVALID_ARG: return "SPW_ERR_INVALID_ARG";
+    case SPW_ERR_BAD_MATRIX: return "SPW_ERR_BAD_MATRIX";
+    case SPW_ERR_OUT_OF_MEMORY: return "SPW_ERR_OUT_OF_MEMORY";
+    case SPW_ERR_BUDGET: return "SPW_ERR_BUDGET";
+    case SPW_ERR_DEVICE: return "SPW_ERR_DEVICE";
+    case SPW_ERR_UNSUPPORTED: return "SPW_ERR_UNSUPPORTED";
+    case SPW_ERR_BUSY: return "SPW_ERR_BUSY";
+    case SPW_ERR_TIMEOUT: return "SPW_ERR_TIMEOUT";
+    case SPW_ERR_SHUTDOWN: return "SPW_ERR_SHUTDOWN";
+    }
+    return "SPW_UNKNOWN_STATUS";
+}
+
+spw_status spw_create_opts_default(spw_create_opts *o)
+{
+    if (!o) return fail(SPW_ERR_INVALID_ARG, "spw_create_opts_default: NULL opts");
+    std::memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(*o);
+    o->value_storage = SPW_F64;
+    o->chunk_nnz = 0;
+    o->relabel = -1;
+    o->validate = 1;
+    o->panel_rows = 0;
+    o->device = -1;
+    return SPW_OK;
+}
+
+spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int64_t *ptr,
+                      const int32_t *idx, const double *val, const spw_create_opts *opts_in)
+{
+    if (!out) return fail(SPW_ERR_INVALID_ARG, "spw_create: NULL out");
+    *out = nullptr;
+    if (fmt != SPW_CSC && fmt != SPW_CSR) return fail(SPW_ERR_INVALID_ARG, "spw_create: bad format");
+    if (m < 0 || n < 0 || nnz < 0) return fail(SPW_ERR_INVALID_ARG, "spw_create: negative size");
+    if (!ptr) return fail(SPW_ERR_INVALID_ARG, "spw_create: NULL ptr");
+    if (nnz > 0 && (!idx || !val)) return fail(SPW_ERR_INVALID_ARG, "spw_create: NULL idx or val with nnz > 0");
+    spw_create_opts opts;
+    spw_create_opts_default(&opts);
+    if (opts_in) {
+        if (opts_in->struct_size != sizeof(spw_create_opts))
+            return fail(SPW_ERR_INVALID_ARG, "spw_create: opts.struct_size must be sizeof(spw_create_opts)");
+        opts = *opts_in;
+    }
+    if (opts.value_storage != SPW_F64)
+        return fail(SPW_ERR_UNSUPPORTED, "spw_create: value_storage other than F64 is not available yet");
+    const int64_t chunk = opts.chunk_nnz > 0 ? opts.chunk_nnz : vtm_chunk_default();
+    if (chunk != vtm_chunk_default())
+        return fail(SPW_ERR_UNSUPPORTED, "spw_create: chunk_nnz must be " + std::to_string(vtm_chunk_default()));
+
+    const int64_t rows = fmt == SPW_CSC ? m : n;
+    const int64_t cols = fmt == SPW_CSC ? n : m;
+    const int64_t pad = 4096;
+    if (nnz + pad >= ((int64_t)1 << 31) || cols >= ((int64_t)1 << 31) - 1 || rows >= ((int64_t)1 << 31))
+        return fail(SPW_ERR_UNSUPPORTED, "spw_create: nnz and dimensions must stay below 2^31");
+    if (opts.validate) {
+        spw_status st = validate(cols, rows, nnz, ptr, idx, fmt == SPW_CSC ? "column" : "row");
+        if (st) return st;
+    } else if (ptr[cols] != nnz) {
+        return fail(SPW_ERR_BAD_MATRIX, "ptr[last] must equal nnz");
+    }
+
+    DeviceGuard dg(opts.device);
+    if (dg.st) return dg.st;
+    std::unique_ptr<spw_matrix_s> A(new spw_matrix_s());
+    A->format = fmt;
+    A->value_storage = opts.value_storage;
+    A->m = m;
+    A->n = n;
+    A->nnz = nnz;
+    A->rows = rows;
+    A->cols = cols;
+    (void)hipGetDevice(&A->device);
+    A->idx_kind = rows <= 65536 ? IdxKind::U16 : IdxKind::I32;
+    A->relabeled = opts.relabel < 0 ? (rows > 4096 ? 1 : 0) : (opts.relabel ? 1 : 0);
+    if (rows == 0) A->relabeled = 0;
+
+    struct Cleanup {
+        spw_matrix_s *a;
+        bool armed = true;
+        ~Cleanup()
+        {
+            if (armed) free_all(a);
+        }
+    } cleanup{A.get()};
+
+    spw_status st;
+    // Row renumbering by descending count (ties by row), so that the busiest
+    // entries of the short vector are adjacent.
+    std::vector<int32_t> rank, inv;
+    if (A->relabeled) {
+        std::vector<int64_t> cnt((size_t)rows, 0);
+        for (int64_t p = 0; p < nnz; ++p) cnt[(size_t)idx[p]]++;
+        inv.resize((size_t)rows);
+        std::iota(inv.begin(), inv.end(), 0);
+        std::stable_sort(inv.begin(), inv.end(), [&](int32_t a, int32_t b) { return cnt[(size_t)a] > cnt[(size_t)b]; });
+        rank.resize((size_t)rows);
+        for (int64_t r = 0; r < rows; ++r) rank[(size_t)inv[(size_t)r]] = (int32_t)r;
+        if ((st = dev_alloc(*A, &A->d_rank, rows, "row renumbering"))) return st;
+        if ((st = h2d(A->d_rank, rank.data(), (size_t)rows * 4, "row renumbering"))) return st;
+        if ((st = dev_alloc(*A, &A->d_inv, rows, "row renumbering"))) return st;
+        if ((st = h2d(A->d_inv, inv.data(), (size_t)rows * 4, "row renumbering"))) return st;
+    }
+
+    // Column-dot storage: int32 column starts, 2- or 4-byte rows, values; the
+    // index and value arrays are padded with zeros to a whole number of chunks.
+    const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), pad);
+    {
+        std::vector<int32_t> p32((size_t)cols + 1);
+        for (int64_t j = 0; j <= cols; ++j) p32[(size_t)j] = (int32_t)ptr[j];
+        if ((st = dev_alloc(*A, &A->d_ptr, cols + 1, "column starts"))) return st;
+        if ((st = h2d(A->d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
+    }
+    std::vector<uint16_t> i16;
+    std::vector<int32_t> i32;
+    const void *idx_int = nullptr;
+    if (A->idx_kind == IdxKind::U16) {
+        i16.assign((size_t)zpad, 0);
+        const bool rl = A->relabeled != 0;
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) i16[(size_t)p] = (uint16_t)(rl ? rank[(size_t)idx[p]] : idx[p]);
+        });
+        uint16_t *d = nullptr;
+        if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
+        if ((st = h2d(d, i16.data(), (size_t)zpad * 2, "row indices"))) return st;
+        A->d_idx = d;
+        idx_int = i16.data();
+    } else {
+        i32.assign((size_t)zpad, 0);
+        const bool rl = A->relabeled != 0;
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) i32[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
+        });
+        int32_t *d = nullptr;
+        if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
+        if ((st = h2d(d, i32.data(), (size_t)zpad * 4, "row indices"))) return st;
+        A->d_idx = d;
+        idx_int = i32.data();
+    }
+    {
+        double *d = nullptr;
+        if ((st = dev_alloc(*A, &d, zpad, "values"))) return st;
+        if (hipMemset(d, 0, (size_t)zpad * 8) != hipSuccess) return fail(SPW_ERR_DEVICE, "hipMemset failed");
+        if ((st = h2d(d, val, (size_t)nnz * 8, "values"))) return st;
+        A->d_val = d;
+    }
+
+    // Zone plan of the column dots.
+    build_zone_plan(cols, ptr, chunk, A->zp);
+    A->n_zones = (int64_t)A->zp.zone_col.size();
+    if ((st = dev_alloc(*A, &A->d_owned, A->zp.n_chunks + 1, "chunk table"))) return st;
+    if ((st = h2d(A->d_owned, A->zp.owned.data(), A->zp.owned.size() * 4, "chunk table"))) return st;
+    if ((st = dev_alloc(*A, &A->d_zone_col, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
+    if ((st = dev_alloc(*A, &A->d_zone_first, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
+    if ((st = dev_alloc(*A, &A->d_zone_last, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
+    if ((st = h2d(A->d_zone_col, A->zp.zone_col.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
+    if ((st = h2d(A->d_zone_first, A->zp.zone_first.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
+    if ((st = h2d(A->d_zone_last, A->zp.zone_last.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
+
+    // Scatter-product storage.
+    if (rows > 0) {
+        if ((st = build_mv_storage(*A, ptr, idx_int, val, opts.panel_rows))) return st;
+    }
+    if ((st = alloc_scratch(*A, 1))) return st;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPW_ERR_DEVICE, "device error during spw_create");
+    }
+    cleanup.armed = false;
+    *out = A.release();
+    return SPW_OK;
+}
+
+spw_status spw_destroy(spw_matrix A)
+{
+    if (!A) return SPW_OK;
+    {
+        DeviceGuard dg(A->device);
+        (void)hipDeviceSynchronize();
+        free_all(A);
+    }
+    delete A;
+    return SPW_OK;
+}
+
+spw_status spw_info(spw_matrix A, spw_matrix_info *o)
+{
+    if (!A || !o) return fail(SPW_ERR_INVALID_ARG, "spw_info: NULL argument");
+    if (o->struct_size != sizeof(spw_matrix_info))
+        return fail(SPW_ERR_INVALID_ARG, "spw_info: out->struct_size must be sizeof(spw_matrix_info)");
+    o->format = A->format;
+    o->value_storage = A->value_storage;
+    o->m = A->m;
+    o->n = A->n;
+    o->nnz = A->nnz;
+    o->inner_rows = A->rows;
+    o->inner_cols = A->cols;
+    o->chunk_nnz = A->zp.chunk;
+    o->n_chunks = A->zp.n_chunks;
+    o->n_zones = A->n_zones;
+    o->n_panels = A->n_panels;
+    o->panel_rows = A->panel_rows;
+    o->mv_workgroups = A->mv_wgs;
+    o->index_bytes = A->idx_kind == IdxKind::U16 ? 2 : 4;
+    o->relabeled = A->relabeled;
+    o->device = A->device;
+    o->device_bytes = A->device_bytes;
+    return SPW_OK;
+}
+
+static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
+                              void *out, int64_t ldo, void *stream, const char *fname)
+{
+    if (!A) return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": NULL matrix");
+    if (vdt != SPW_F64 && vdt != SPW_F32) return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": bad vector dtype");
+    if (k < 1 || k > 64) return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": k must be in [1, 64]");
+    if (ldi < k || ldo < k) return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": leading dimension < k");
+    // short/long lengths of the input and output for this op
+    const bool scatter = (A->format == SPW_CSC) == want_mv;   // B x  vs  v^T B
+    const int64_t in_len = scatter ? A->cols : A->rows;
+    const int64_t out_len = scatter ? A->rows : A->cols;
+    if ((in_len > 0 && !in) || (out_len > 0 && !out))
+        return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": NULL vector");
+    DeviceGuard dg(A->device);
+    if (dg.st) return dg.st;
+    spw_status st = alloc_scratch(*A, k);
+    if (st) return st;
+    const int e = scatter ? launch_mv(*A, vdt, k, in, ldi, out, ldo, stream)
+                          : launch_vtm(*A, vdt, k, in, ldi, out, ldo, stream);
+    if (e == (int)hipErrorNotSupported)
+        return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");
+    if (e) return fail(SPW_ERR_DEVICE, std::string(fname) + ": kernel launch failed: " + hipGetErrorString((hipError_t)e));
+    return SPW_OK;
+}
+
+spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)
+{
+    return run_product(A, true, vdt, 1, x, 1, y, 1, stream, "spw_mv");
+}
+
+spw_status spw_vtm(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *stream)
+{
+    return run_product(A, false, vdt, 1, v, 1, u, 1, stream, "spw_vtm");
+}
+
+spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                        void *stream)
+{
+    return run_product(A, true, vdt, k, X, ldx, Y, ldy, stream, "spw_mv_batch");
+}
+
+spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv, void *U, int64_t ldu,
+                         void *stream)
+{
+    return run_product(A, false, vdt, k, V, ldv, U, ldu, stream, "spw_vtm_batch");
+}
+
+spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int64_t *n_chunks, int64_t *n_zones,
+                          int64_t *chunk_owned, int64_t *zone_col, int64_t *zone_first, int64_t *zone_last)
+{
+    if (n < 0 || !ptr || chunk_nnz <= 0 || !n_chunks || !n_zones)
+        return fail(SPW_ERR_INVALID_ARG, "spw_plan_zones: bad argument");
+    if (ptr[0] != 0) return fail(SPW_ERR_BAD_MATRIX, "spw_plan_zones: ptr[0] must be 0");
+    for (int64_t j = 0; j < n; ++j)
+        if (ptr[j + 1] < ptr[j]) return fail(SPW_ERR_BAD_MATRIX, "spw_plan_zones: ptr decreases at " + std::to_string(j));
+    if (ptr[n] >= ((int64_t)1 << 31) || n >= ((int64_t)1 << 31) - 1)
+        return fail(SPW_ERR_UNSUPPORTED, "spw_plan_zones: sizes must stay below 2^31");
+    ZonePlan zp;
+    build_zone_plan(n, ptr, chunk_nnz, zp);
+    *n_chunks = zp.n_chunks;
+    *n_zones = (int64_t)zp.zone_col.size();
+    if (chunk_owned)
+        for (size_t c = 0; c < zp.owned.size(); ++c) chunk_owned[c] = zp.owned[c];
+    for (size_t k = 0; k < zp.zone_col.size(); ++k) {
+        if (zone_col) zone_col[k] = zp.zone_col[k];
+        if (zone_first) zone_first[k] = zp.zone_first[k];
+        if (zone_last) zone_last[k] = zp.zone_last[k];
+    }
+    return SPW_OK;
+}
+
+}  // extern "C"

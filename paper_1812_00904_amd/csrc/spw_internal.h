@@ -1,0 +1,133 @@
+// Internal declarations shared by the host and device halves of libspw.
+//
+// Storage model.  Every matrix is held as the column-major (CSC) arrays of a
+// short-by-long matrix B with `rows` (the short dimension) and `cols` (the
+// long one): a wide CSC input is B = A, a tall CSR input is B = A^T (the
+// role swap of Section II).  Then
+//     wide  A x   = scatter product  (B x)          -- "mv" kernels
+//     wide  v^T A = column dots      (v^T B)        -- "vtm" kernels
+//     tall  A x   = column dots of B with x
+//     tall  v^T A = scatter product of B with v
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spw.h"
+
+namespace spw {
+
+// ---------------------------------------------------------------- plan (host)
+
+// Column-dot plan over equal-nonzero chunks (Section II's split with a fixed
+// chunk size instead of a fixed count).  Chunk c covers positions
+// [c*C, min((c+1)*C, nnz)); it owns the columns whose start lies inside it
+// (owned[c] .. owned[c+1]-1; owned[n_chunks] = cols).  A zone is a column cut
+// by a chunk boundary; its chunk set is first..last (inclusive).
+struct ZonePlan {
+    int64_t chunk = 0;
+    int64_t n_chunks = 0;
+    std::vector<int32_t> owned;       // n_chunks + 1
+    std::vector<int32_t> zone_col;    // per zone
+    std::vector<int32_t> zone_first;  // first chunk (holds the column start)
+    std::vector<int32_t> zone_last;   // last chunk touching the column
+};
+
+// Builds the zone plan; ptr has cols+1 entries.  Pure host code.
+void build_zone_plan(int64_t cols, const int64_t *ptr, int64_t chunk, ZonePlan &out);
+
+// Tile of the scatter product: positions [start, end) of one panel, whose
+// columns lie in [jlo, jhi].
+struct Tile {
+    int32_t start, end, jlo, jhi;
+};
+// Workgroup of the scatter product: panel, tile range [t0, t1).
+struct WgDesc {
+    int32_t panel, t0, t1, pad;
+};
+// Panel of the scatter product: internal rows [row0, row0+rows), workgroups
+// [wg0, wg0+nwg) hold its partial vectors.
+struct PanelDesc {
+    int32_t row0, rows, wg0, nwg;
+};
+
+// ------------------------------------------------------------ device handle
+
+enum class IdxKind : int32_t { U16 = 0, I32 = 1 };
+
+struct Scratch {
+    double *partial = nullptr;    // mv_wgs * panel_rows * kcap  (binary64 partial sums)
+    double *carry = nullptr;      // 2 * n_chunks * kcap
+    void *vperm = nullptr;        // rows * kcap * 8  (renumbered input of the column dots)
+    int32_t kcap = 0;
+};
+
+}  // namespace spw
+
+struct spw_matrix_s {
+    spw_format format = SPW_CSC;
+    spw_dtype value_storage = SPW_F64;
+    int64_t m = 0, n = 0, nnz = 0;      // caller's shape
+    int64_t rows = 0, cols = 0;         // B = short x long
+    int device = 0;
+    spw::IdxKind idx_kind = spw::IdxKind::U16;
+    int32_t relabeled = 0;
+
+    // column-dot storage (original column order, renumbered rows)
+    int32_t *d_ptr = nullptr;           // cols + 1
+    void *d_idx = nullptr;              // nnz (+ padding), uint16 or int32
+    void *d_val = nullptr;              // nnz (+ padding), value_storage type
+    int32_t *d_rank = nullptr;          // rows: caller row -> internal row
+    int32_t *d_inv = nullptr;           // rows: internal row -> caller row
+
+    spw::ZonePlan zp;
+    int32_t *d_owned = nullptr;         // n_chunks + 1
+    int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
+    int64_t n_zones = 0;
+
+    // scatter-product storage (row panels; aliases the column-dot arrays when
+    // there is a single panel)
+    int64_t panel_rows = 0, n_panels = 0;
+    int64_t tile = 0;                   // nonzeros per scatter tile
+    int32_t *d_pptr = nullptr;          // n_panels * (cols + 1), absolute positions
+    void *d_pidx = nullptr;             // panel-local row indices
+    void *d_pval = nullptr;
+    bool panels_alias = true;
+    std::vector<spw::Tile> tiles;
+    std::vector<spw::WgDesc> wgs;
+    std::vector<spw::PanelDesc> panels;
+    spw::Tile *d_tiles = nullptr;
+    spw::WgDesc *d_wgs = nullptr;
+    spw::PanelDesc *d_panels = nullptr;
+    int64_t mv_wgs = 0;
+
+    spw::Scratch scratch;
+    int64_t device_bytes = 0;
+    std::vector<void *> allocations;
+};
+
+namespace spw {
+
+// ------------------------------------------------------------ launch glue
+// All return hipError_t as int (0 = success).  Implemented in spw_kernels.hip.
+
+int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv,
+               void *u, int64_t ldu, void *stream);
+int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
+              void *y, int64_t ldy, void *stream);
+// Device-side limits the host plan must respect.
+int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
+int64_t mv_tile_nnz();
+int64_t vtm_chunk_default();
+int device_cu_count(int device);
+
+// Profiling hooks (spw_profile.cpp).
+bool profile_on();
+void profile_begin(void *stream, const char *name, void **token);
+void profile_end(void *stream, void *token);
+
+// Error text for the calling thread (spw_api.cpp).
+void set_error(const std::string &msg);
+
+}  // namespace spw

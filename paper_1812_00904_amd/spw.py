@@ -1,0 +1,257 @@
+"""Python binding of libspw (ctypes).  Argument marshalling only: every product
+runs in the library's HIP kernels.  torch is used for device memory and
+streams; it is imported first so that libspw binds to the same HIP runtime.
+
+The functions mirror the C ABI in include/spw.h; ``SpwMatrix`` is a small
+convenience wrapper over them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libspw.so")
+
+SPW_OK = 0
+STATUS_NAMES = ["SPW_OK", "SPW_ERR_INVALID_ARG", "SPW_ERR_BAD_MATRIX", "SPW_ERR_OUT_OF_MEMORY",
+                "SPW_ERR_BUDGET", "SPW_ERR_DEVICE", "SPW_ERR_UNSUPPORTED", "SPW_ERR_BUSY",
+                "SPW_ERR_TIMEOUT", "SPW_ERR_SHUTDOWN"]
+SPW_CSC, SPW_CSR = 0, 1
+SPW_F64, SPW_F32, SPW_BF16 = 0, 1, 2
+DTYPES = {SPW_F64: torch.float64, SPW_F32: torch.float32}
+
+
+class SpwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        self.status_name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__("%s: %s" % (self.status_name, msg))
+
+
+class CreateOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("value_storage", ctypes.c_int),
+                ("chunk_nnz", ctypes.c_int32), ("relabel", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class MatrixInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("format", ctypes.c_int), ("value_storage", ctypes.c_int),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("inner_rows", ctypes.c_int64), ("inner_cols", ctypes.c_int64),
+                ("chunk_nnz", ctypes.c_int64), ("n_chunks", ctypes.c_int64), ("n_zones", ctypes.c_int64),
+                ("n_panels", ctypes.c_int64), ("panel_rows", ctypes.c_int64),
+                ("mv_workgroups", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
+                ("relabeled", ctypes.c_int32), ("device", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+
+class ProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+# Every symbol include/spw.h declares, with (restype, argtypes).
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+SIGNATURES = {
+    "spw_create_opts_default": (ctypes.c_int, [ctypes.POINTER(CreateOpts)]),
+    "spw_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
+                                  ctypes.POINTER(CreateOpts)]),
+    "spw_destroy": (ctypes.c_int, [_VP]),
+    "spw_info": (ctypes.c_int, [_VP, ctypes.POINTER(MatrixInfo)]),
+    "spw_mv": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "spw_vtm": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
+    "spw_mv_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
+    "spw_vtm_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
+    "spw_plan_zones": (ctypes.c_int, [_I64, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                      _VP, _VP, _VP, _VP]),
+    "spw_profile_enable": (ctypes.c_int, [_I32]),
+    "spw_profile_reset": (ctypes.c_int, []),
+    "spw_profile_read": (ctypes.c_int, [ctypes.POINTER(ProfileEntry), _I32, ctypes.POINTER(_I32)]),
+    "spw_last_error": (ctypes.c_char_p, []),
+    "spw_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libspw.so; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError("libspw.so is not built (%s); run __graft_entry__.build()" % p)
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != SPW_OK:
+        raise SpwError(status, load().spw_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def create_opts(**kw) -> CreateOpts:
+    o = CreateOpts()
+    _check(load().spw_create_opts_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def spw_create(fmt: int, m: int, n: int, ptr, idx, val, opts: CreateOpts | None = None) -> int:
+    """Create a matrix from host arrays (numpy); returns the opaque handle."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    nnz = int(idx.size)
+    h = _VP()
+    _check(load().spw_create(ctypes.byref(h), fmt, m, n, nnz, ptr.ctypes.data, idx.ctypes.data,
+                             val.ctypes.data, ctypes.byref(opts) if opts is not None else None))
+    return h.value
+
+
+def spw_destroy(h: int):
+    _check(load().spw_destroy(h))
+
+
+def spw_info(h: int) -> dict:
+    info = MatrixInfo()
+    info.struct_size = ctypes.sizeof(MatrixInfo)
+    _check(load().spw_info(h, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in MatrixInfo._fields_ if name != "struct_size"}
+
+
+def _vec_dtype(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return SPW_F64
+    if t.dtype == torch.float32:
+        return SPW_F32
+    raise TypeError("vectors must be float64 or float32 tensors")
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+
+
+def spw_mv(h: int, x: torch.Tensor, y: torch.Tensor, stream=None):
+    _dev(x, "x"), _dev(y, "y")
+    _check(load().spw_mv(h, _vec_dtype(x), x.data_ptr(), y.data_ptr(), _stream_ptr(stream)))
+
+
+def spw_vtm(h: int, v: torch.Tensor, u: torch.Tensor, stream=None):
+    _dev(v, "v"), _dev(u, "u")
+    _check(load().spw_vtm(h, _vec_dtype(v), v.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
+
+
+def spw_mv_batch(h: int, X: torch.Tensor, Y: torch.Tensor, stream=None):
+    _dev(X, "X"), _dev(Y, "Y")
+    k = X.shape[1]
+    _check(load().spw_mv_batch(h, _vec_dtype(X), k, X.data_ptr(), X.stride(0), Y.data_ptr(), Y.stride(0),
+                               _stream_ptr(stream)))
+
+
+def spw_vtm_batch(h: int, V: torch.Tensor, U: torch.Tensor, stream=None):
+    _dev(V, "V"), _dev(U, "U")
+    k = V.shape[1]
+    _check(load().spw_vtm_batch(h, _vec_dtype(V), k, V.data_ptr(), V.stride(0), U.data_ptr(), U.stride(0),
+                                _stream_ptr(stream)))
+
+
+def spw_plan_zones(n: int, ptr, chunk_nnz: int):
+    """Host-only chunk/zone plan: (owned[n_chunks+1], zone_col, zone_first, zone_last)."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+    nc, nz = _I64(), _I64()
+    lib = load()
+    _check(lib.spw_plan_zones(n, ptr.ctypes.data, chunk_nnz, ctypes.byref(nc), ctypes.byref(nz),
+                              None, None, None, None))
+    owned = np.empty(nc.value + 1, dtype=np.int64)
+    zc = np.empty(max(nz.value, 1), dtype=np.int64)
+    zf = np.empty_like(zc)
+    zl = np.empty_like(zc)
+    _check(lib.spw_plan_zones(n, ptr.ctypes.data, chunk_nnz, ctypes.byref(nc), ctypes.byref(nz),
+                              owned.ctypes.data, zc.ctypes.data, zf.ctypes.data, zl.ctypes.data))
+    k = nz.value
+    return owned, zc[:k].copy(), zf[:k].copy(), zl[:k].copy()
+
+
+def spw_profile_enable(on: bool):
+    _check(load().spw_profile_enable(1 if on else 0))
+
+
+def spw_profile_reset():
+    _check(load().spw_profile_reset())
+
+
+def spw_profile_read() -> dict:
+    lib = load()
+    cnt = _I32()
+    _check(lib.spw_profile_read(None, 0, ctypes.byref(cnt)))
+    arr = (ProfileEntry * max(cnt.value, 1))()
+    _check(lib.spw_profile_read(arr, cnt.value, ctypes.byref(cnt)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
+
+class SpwMatrix:
+    """A created matrix.  `fmt` is SPW_CSC (wide, m x n, ptr over columns) or
+    SPW_CSR (tall, m x n, ptr over rows)."""
+
+    def __init__(self, fmt: int, m: int, n: int, ptr, idx, val, **opts):
+        self.fmt, self.m, self.n = fmt, m, n
+        self.handle = None
+        self.handle = spw_create(fmt, m, n, ptr, idx, val, create_opts(**opts) if opts else None)
+
+    def info(self) -> dict:
+        return spw_info(self.handle)
+
+    def mv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.m, dtype=x.dtype, device=x.device)
+        spw_mv(self.handle, x, y, stream)
+        return y
+
+    def vtm(self, v: torch.Tensor, u: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if u is None:
+            u = torch.empty(self.n, dtype=v.dtype, device=v.device)
+        spw_vtm(self.handle, v, u, stream)
+        return u
+
+    def mv_batch(self, X: torch.Tensor, Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if Y is None:
+            Y = torch.empty((self.m, X.shape[1]), dtype=X.dtype, device=X.device)
+        spw_mv_batch(self.handle, X, Y, stream)
+        return Y
+
+    def vtm_batch(self, V: torch.Tensor, U: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if U is None:
+            U = torch.empty((self.n, V.shape[1]), dtype=V.dtype, device=V.device)
+        spw_vtm_batch(self.handle, V, U, stream)
+        return U
+
+    def close(self):
+        if self.handle:
+            spw_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,147 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every declared symbol, argument and matrix validation reports errors before
+touching a device, and the host chunk/zone plan matches the oracle's zones."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spw.h")
+
+
+@pytest.fixture(scope="module")
+def spw():
+    from paper_1812_00904_amd import spw as mod
+    mod.load()
+    return mod
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(spw):
+    lib = ctypes.CDLL(spw.LIB_PATH)
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding knows the signature of each one
+    assert set(names) <= set(spw.SIGNATURES), set(names) - set(spw.SIGNATURES)
+
+
+def test_status_strings(spw):
+    lib = spw.load()
+    for i, name in enumerate(spw.STATUS_NAMES):
+        assert lib.spw_status_string(i).decode() == name
+    assert lib.spw_status_string(99).decode() == "SPW_UNKNOWN_STATUS"
+
+
+def _expect(spw, status_name, fn, *args):
+    with pytest.raises(spw.SpwError) as ei:
+        fn(*args)
+    assert ei.value.status_name == status_name, str(ei.value)
+    return str(ei.value)
+
+
+def test_create_rejects_bad_matrices_before_device_use(spw):
+    ptr = np.array([0, 2, 3], dtype=np.int64)
+    idx = np.array([0, 1, 1], dtype=np.int32)
+    val = np.ones(3)
+    # ptr must start at 0
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 2, np.array([1, 2, 3]), idx, val)
+    # decreasing pointer
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 3,
+            np.array([0, 2, 1, 3]), idx, val)
+    # index out of range, named by position
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 2, ptr,
+                  np.array([0, 1, 2], dtype=np.int32), val)
+    assert "position 2" in msg
+    # not strictly increasing inside a column (duplicate)
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 2, ptr,
+                  np.array([1, 1, 0], dtype=np.int32), val)
+    assert "position 1" in msg
+    # CSR: ptr over rows, indices are columns
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSR, 2, 1, ptr, idx, val)
+
+
+def test_create_rejects_bad_arguments(spw):
+    lib = spw.load()
+    h = ctypes.c_void_p()
+    ptr = np.zeros(3, dtype=np.int64)
+    assert lib.spw_create(None, 0, 2, 2, 0, ptr.ctypes.data, None, None, None) == 1
+    assert lib.spw_create(ctypes.byref(h), 7, 2, 2, 0, ptr.ctypes.data, None, None, None) == 1
+    assert lib.spw_create(ctypes.byref(h), 0, -1, 2, 0, ptr.ctypes.data, None, None, None) == 1
+    assert lib.spw_create(ctypes.byref(h), 0, 2, 2, 0, None, None, None, None) == 1
+    assert lib.spw_create(ctypes.byref(h), 0, 2, 2, 3, ptr.ctypes.data, None, None, None) == 1
+    bad = spw.create_opts()
+    bad.struct_size = 3
+    assert lib.spw_create(ctypes.byref(h), 0, 2, 2, 0, ptr.ctypes.data, None, None, ctypes.byref(bad)) == 1
+    assert "struct_size" in lib.spw_last_error().decode()
+    assert lib.spw_mv(None, 0, None, None, None) == 1
+    assert lib.spw_destroy(None) == 0
+
+
+def _check_plan_against_oracle(spw, A, C):
+    owned, zc, zf, zl = spw.spw_plan_zones(A.n, A.ptr, C)
+    off = oracle.offsets_fixed(A.nnz, C)
+    ozc, osf, osl = oracle.zones(A.n, A.ptr, off)
+    assert np.array_equal(zc, ozc)
+    assert np.array_equal(zf, osf)
+    assert np.array_equal(zl, osl)
+    # owned: first column whose start lies at or after the chunk start; last = n
+    G = off.size - 1
+    assert owned.size == G + 1 and owned[G] == A.n
+    for c in range(G):
+        first_at_or_after = int(np.searchsorted(A.ptr, off[c], side="left"))
+        assert owned[c] == first_at_or_after
+    # the zone chunk sets agree with the paper's setup scans over the same split
+    if G >= 1 and A.nnz:
+        jf, jl = oracle.cover(A.n, A.ptr, off)
+        sv = oracle.setup_vars(jf, jl)
+        assert zc.size == int(sv["leftGroupEnd"].sum())
+        for g in range(G):
+            if sv["needRight"][g]:
+                k = int(sv["rightGroup"][g])
+                assert zf[k] <= g and zl[k] == g + sv["procsOnRight"][g]
+            if sv["needLeft"][g]:
+                k = int(sv["leftGroup"][g])
+                assert zf[k] == g - sv["procsOnLeft"][g]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("C", [1, 3, 16, 512])
+def test_plan_zones_match_oracle(spw, seed, C):
+    A = synth.random_csc(50, 700, 4.0, seed, empty_frac=0.3)
+    A = synth.from_lengths(50, np.r_[np.diff(A.ptr)[:300], [50, 0, 0, 50, 1], np.diff(A.ptr)[300:]], seed)
+    _check_plan_against_oracle(spw, A, C)
+
+
+def test_plan_zones_worked_example(spw):
+    import json
+    ex = json.load(open(os.path.join(ROOT, "tests", "golden", "worked_example.json")))
+    lengths = [len(c) for c in ex["fig1_rows_per_column"]]
+    ptr = np.r_[0, np.cumsum(lengths)].astype(np.int64)
+    owned, zc, zf, zl = spw.spw_plan_zones(8, ptr, ex["group_size"])
+    assert [int(c) + 1 for c in zc] == [z["column"] for z in ex["table1_zones"]]
+    assert [list(range(a, b + 1)) for a, b in zip(zf, zl)] == [z["S"] for z in ex["table1_zones"]]
+
+
+def test_plan_zones_edge_cases(spw):
+    # empty matrix: no chunks, no zones
+    owned, zc, _, _ = spw.spw_plan_zones(5, np.zeros(6, dtype=np.int64), 4)
+    assert owned.tolist() == [5] and zc.size == 0
+    # one long column across many chunks: one zone spanning all of them
+    owned, zc, zf, zl = spw.spw_plan_zones(1, np.array([0, 100], dtype=np.int64), 7)
+    assert zc.tolist() == [0] and zf.tolist() == [0] and zl.tolist() == [14]
+    # boundaries that fall exactly on column starts cut nothing
+    owned, zc, _, _ = spw.spw_plan_zones(4, np.array([0, 4, 8, 12, 16], dtype=np.int64), 4)
+    assert zc.size == 0 and owned.tolist() == [0, 1, 2, 3, 4]

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bar (binary64): per component |gpu - oracle| <= 1e-13 * sum|a||x| (the
+oracle's denominator); where that sum is 0 the result must be exactly 0.
+Integer-valued inputs must match bit for bit.  Repeated calls must be
+bit-identical, and every output component must be written.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-13
+
+
+@pytest.fixture(scope="module")
+def spw():
+    from paper_1812_00904_amd import spw as mod
+    mod.load()
+    assert torch.cuda.is_available()
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def check(got, ref, d, what, tol=TOL64):
+    got = np.asarray(got)
+    assert got.shape == ref.shape, what
+    assert not np.isnan(got).any(), "%s: unwritten (NaN) components at %s" % (what, np.nonzero(np.isnan(got))[0][:5])
+    err = np.abs(got - ref)
+    bad = err > tol * d
+    if bad.any():
+        i = int(np.nonzero(bad)[0][0])
+        raise AssertionError("%s: %d components off; first %d: got %r want %r (d=%r)"
+                             % (what, int(bad.sum()), i, got[i], ref[i], d[i]))
+
+
+def run_both(spw, A, fmt, x, v, opts=None, reps=1):
+    """Create the matrix in format `fmt` from the CSC arrays of A (CSR = transpose) and
+    return (y, u) device results, NaN-prefilled so unwritten entries show."""
+    if fmt == spw.SPW_CSC:
+        m, n = A.m, A.n
+    else:
+        m, n = A.n, A.m
+    M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, **(opts or {}))
+    xd, vd = dev(x), dev(v)
+    ys, us = [], []
+    for _ in range(reps):
+        y = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+        u = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        M.mv(xd, y)
+        M.vtm(vd, u)
+        torch.cuda.synchronize()
+        ys.append(y.cpu().numpy())
+        us.append(u.cpu().numpy())
+    info = M.info()
+    M.close()
+    return ys, us, info
+
+
+def oracle_pair(A, fmt, x, v):
+    if fmt == 0:
+        y, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x, with_d=True)
+        u, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v, with_d=True)
+    else:
+        y, dy = oracle.mv_csr(A.n, A.m, A.ptr, A.idx, A.val, x, with_d=True)
+        u, du = oracle.vtm_csr(A.n, A.m, A.ptr, A.idx, A.val, v, with_d=True)
+    return y, dy, u, du
+
+
+def vectors_for(A, fmt, seed, kind="uniform"):
+    # CSC: x has n entries, v has m; CSR (the transpose, n x m): x has m, v has n
+    a, b = (A.n, A.m) if fmt == 0 else (A.m, A.n)
+    return synth.vector(a, seed, 1, kind), synth.vector(b, seed, 2, kind)
+
+
+def parity(spw, A, fmt, seed=0, opts=None, reps=1, kind="uniform", name=""):
+    x, v = vectors_for(A, fmt, seed, kind)
+    print("parity case %s fmt=%d m=%d n=%d nnz=%d opts=%s" % (name, fmt, A.m, A.n, A.nnz, opts), flush=True)
+    ys, us, info = run_both(spw, A, fmt, x, v, opts, reps)
+    y, dy, u, du = oracle_pair(A, fmt, x, v)
+    check(ys[0], y, dy, "%s mv fmt=%d" % (name, fmt))
+    check(us[0], u, du, "%s vtm fmt=%d" % (name, fmt))
+    for r in range(1, reps):
+        assert np.array_equal(ys[r], ys[0]), "mv not bit-identical on repeat %d" % r
+        assert np.array_equal(us[r], us[0]), "vtm not bit-identical on repeat %d" % r
+    return ys[0], us[0], y, u, info
+
+
+FMTS = [0, 1]
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_small_config_full(spw, fmt):
+    A = synth.config_matrix("c0")
+    parity(spw, A, fmt, seed=1, reps=3, name="c0")
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "single_col", "one_row"])
+def test_structures(spw, fmt, case):
+    if case == "ragged":
+        A = synth.random_csc(37, 5000, 5.0, 3, values="lognormal")
+    elif case == "many_empty":
+        A = synth.random_csc(300, 40000, 3.0, 4, empty_frac=0.8)
+    elif case == "dense_cols":
+        L = np.r_[np.full(300, 2), [6000] * 3, np.full(500, 1), [6000], np.full(77, 3)]
+        A = synth.from_lengths(6000, L, 5, row_alpha=0.8, values="lognormal")
+    elif case == "tiny":
+        A = synth.random_csc(3, 4, 2.0, 6)
+    elif case == "single_col":
+        A = synth.from_lengths(20000, np.array([20000]), 7)
+    else:
+        A = synth.from_lengths(1, np.r_[np.ones(9000, dtype=np.int64), np.zeros(100, dtype=np.int64)], 8)
+    parity(spw, A, fmt, seed=2, reps=2, name=case)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_integer_data_bit_exact(spw, fmt):
+    A = synth.random_csc(500, 30000, 6.0, 9, values="int", empty_frac=0.2)
+    A = synth.from_lengths(500, np.r_[np.diff(A.ptr), [500] * 4], 9, values="int")
+    x, v = vectors_for(A, fmt, 9, kind="int")
+    ys, us, _ = run_both(spw, A, fmt, x, v)
+    y, _, u, _ = oracle_pair(A, fmt, x, v)
+    assert np.array_equal(ys[0], y)
+    assert np.array_equal(us[0], u)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_empty_matrix(spw, fmt):
+    A = synth.from_lengths(10, np.zeros(50, dtype=np.int64), 1)
+    _, u_gpu, y_ref, u_ref, _ = parity(spw, A, fmt, name="empty")
+    assert np.all(u_gpu == 0)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("opts", [dict(panel_rows=97), dict(relabel=0), dict(relabel=1), dict(validate=0)])
+def test_plan_options(spw, fmt, opts):
+    A = synth.config_matrix("c0", scale=0.3)
+    _, _, _, _, info = parity(spw, A, fmt, seed=4, opts=opts, name="opts")
+    if "panel_rows" in opts:
+        assert info["n_panels"] == -(-info["inner_rows"] // 97)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_wide_index_path_and_panels(spw, fmt):
+    # more than 65,536 short-side rows: 4-byte row indices and several panels
+    A = synth.random_csc(70000, 20000, 12.0, 10, values="lognormal", row_alpha=0.8)
+    _, _, _, _, info = parity(spw, A, fmt, seed=5, name="wide_index")
+    assert info["index_bytes"] == 4 and info["n_panels"] > 1
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_large_config_scaled(spw, fmt):
+    A = synth.config_matrix("c1", scale=0.02)
+    _, _, _, _, info = parity(spw, A, fmt, seed=6, reps=2, name="c1x0.02")
+    assert info["n_panels"] >= 3 and info["relabeled"] == 1
+
+
+def test_large_config_full_size(spw):
+    """The 2e8-nonzero wide matrix at full size, in the benchmark's launch setup."""
+    A = synth.config_matrix("c1")
+    x, v = synth.config_vectors("c1", A.m, A.n)
+    print("full-size case m=%d n=%d nnz=%d" % (A.m, A.n, A.nnz), flush=True)
+    ys, us, info = run_both(spw, A, 0, x, v, reps=2)
+    y, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x, with_d=True)
+    check(ys[0], y, dy, "c1 mv")
+    del y, dy
+    u, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v, with_d=True)
+    check(us[0], u, du, "c1 vtm")
+    assert np.array_equal(ys[1], ys[0]) and np.array_equal(us[1], us[0])
+
+
+def test_streams_and_determinism(spw):
+    A = synth.config_matrix("c0", scale=0.5)
+    M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val)
+    x, v = synth.config_vectors("c0", A.m, A.n)
+    xd, vd = dev(x), dev(v)
+    ref_y = M.mv(xd).cpu().numpy()
+    ref_u = M.vtm(vd).cpu().numpy()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(10):
+            y = M.mv(xd, stream=s)
+            u = M.vtm(vd, stream=s)
+    s.synchronize()
+    assert np.array_equal(y.cpu().numpy(), ref_y)
+    assert np.array_equal(u.cpu().numpy(), ref_u)
+    M.close()
