@@ -1,0 +1,304 @@
+#!/usr/bin/env python3
+"""Benchmark of the wide/tall sparse product path on one MI355X.
+
+A step is one pass of the hot path over the 2e8-nonzero wide matrix
+(m = 50,000, n = 2e7, FP64): y = A x followed by u^T = v^T A, the
+multiply pair the paper's driver repeats.  `value` is the effective HBM
+bandwidth of that pair under the algorithmic byte model
+
+    bytes(A x)   = nnz*(8 + 4) + 4*(n+1) + 8*n (read x) + 8*m (write y)
+    bytes(v^T A) = nnz*(8 + 4) + 4*(n+1) + 8*m (read v) + 8*n (write u)
+
+(8-byte values, 4-byte indices and pointers), divided by the measured time.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  Also reports, outside the timed steps: the tall mirror
+(the same arrays read as a 2e7 x 50,000 CSR matrix), per-kernel roofline
+figures, plain-call latency percentiles, and the CPU oracle timed on the host.
+
+`--pmc-summary DIR` turns rocprofv3 counter output (FETCH_SIZE / WRITE_SIZE
+runs of `--profile-run`) into the traffic summary under profiles/.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
+
+
+def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, si: int = 4, sp: int = 4) -> int:
+    """Algorithmic bytes of one product (either direction; they move the same amount)."""
+    return nnz * (sv + si) + sp * (n + 1) + k * sx * n + k * sx * m
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """Per-kernel HBM bytes per launch from the committed counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if "=" in line and not line.startswith("#"):
+            a, b = line.split("=", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    return kv
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    i = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[i]
+
+
+def cpu_baseline(A, x, v, budget_s: float = 20.0):
+    """The oracle, untuned, single-threaded, on this host: as many full mv+vtm
+    pairs over the same matrix as fit about `budget_s` seconds (at least one)."""
+    import oracle
+    t_pairs = []
+    t0 = time.perf_counter()
+    while True:
+        t = time.perf_counter()
+        oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x)
+        oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v)
+        t_pairs.append(time.perf_counter() - t)
+        if time.perf_counter() - t0 + t_pairs[-1] > budget_s or len(t_pairs) >= 20:
+            break
+    t_med = sorted(t_pairs)[len(t_pairs) // 2]
+    pair_bytes = 2 * model_bytes(A.m, A.n, A.nnz)
+    return {"value": round(pair_bytes / t_med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full y=Ax + u^T=v^T A pairs over the same %d-nonzero matrix, single thread, "
+                      "median pair %.3f s" % (len(t_pairs), A.nnz, t_med)}
+
+
+def time_pairs(M, xd, vd, yd, ud, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        M.mv(xd, yd)
+        M.vtm(vd, ud)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(steps):
+        a, b, c = ev[i]
+        a.record()
+        M.mv(xd, yd)
+        b.record()
+        M.vtm(vd, ud)
+        c.record()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+    mv_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    vtm_ms = [b.elapsed_time(c) for _, b, c in ev]
+    return total_ms, wall, mv_ms, vtm_ms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tall", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
+    ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
+                    help="FETCH_SIZE and WRITE_SIZE rocprofv3 output directories -> traffic summary")
+    args = ap.parse_args()
+
+    if args.pmc_summary:
+        return summarize_pmc(*args.pmc_summary)
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (the multi-GPU "
+              "sharding is described in DESIGN.md but not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1812_00904_amd import SPW_CSC, SPW_CSR, SpwMatrix, spw_profile_enable, spw_profile_read, \
+        spw_profile_reset
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    A = synth.config_matrix("c1", scale=args.scale)
+    x, v = synth.config_vectors("c1", A.m, A.n)
+    gen_s = time.perf_counter() - t
+    print("[bench] generated m=%d n=%d nnz=%d in %.1fs" % (A.m, A.n, A.nnz, gen_s), file=sys.stderr, flush=True)
+
+    t = time.perf_counter()
+    M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    create_s = time.perf_counter() - t
+    info = M.info()
+    xd = torch.from_numpy(x).to(dev)
+    vd = torch.from_numpy(v).to(dev)
+    yd = torch.empty(A.m, dtype=torch.float64, device=dev)
+    ud = torch.empty(A.n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    print("[bench] created in %.1fs: %s" % (create_s, info), file=sys.stderr, flush=True)
+
+    if args.profile_run:
+        for _ in range(3):
+            M.mv(xd, yd)
+            M.vtm(vd, ud)
+        # calibration: a plain copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] profile run done", file=sys.stderr, flush=True)
+        return
+
+    spw_profile_reset()
+    spw_profile_enable(True)
+    total_ms, wall, mv_ms, vtm_ms = time_pairs(M, xd, vd, yd, ud, args.steps, args.warmup)
+    spw_profile_enable(False)
+    prof = spw_profile_read()
+    spw_profile_reset()
+    ms_per_step = total_ms / args.steps
+    pair_bytes = 2 * model_bytes(A.m, A.n, A.nnz)
+    value = pair_bytes / (ms_per_step * 1e-3) / 1e9
+    print("[bench] %d pairs in %.3f ms (%.3f ms/pair, wall %.3f s): %.1f GB/s"
+          % (args.steps, total_ms, ms_per_step, wall, value), file=sys.stderr, flush=True)
+
+    # per-kernel figures (average launch duration from events on the launch stream)
+    kernels = {}
+    for name, (launches, tot) in prof.items():
+        avg = tot / max(launches, 1)
+        kernels[name] = {"launches": launches, "avg_us": round(avg * 1e3, 2)}
+    one_op = model_bytes(A.m, A.n, A.nnz)
+    for name, op in (("mv_bucket_f64", "mv"), ("vtm_wave_f64", "vtm")):
+        if name in kernels:
+            gbs = one_op / (kernels[name]["avg_us"] * 1e-6) / 1e9
+            kernels[name]["achieved_GBps"] = round(gbs, 1)
+            kernels[name]["op"] = op
+    dom = max(("mv_bucket_f64", "vtm_wave_f64"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
+    traffic = read_traffic()
+    tr_val = None
+    if traffic and ("%s_bytes_per_launch" % dom) in traffic:
+        tr_val = float(traffic["%s_bytes_per_launch" % dom])
+    achieved = kernels[dom]["achieved_GBps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr_val,
+                "algorithmic_bytes_per_launch": one_op}
+
+    extra = {"kernels": kernels,
+             "latency_ms": {"mv_p50": round(percentile(mv_ms, 50), 4), "mv_p99": round(percentile(mv_ms, 99), 4),
+                            "vtm_p50": round(percentile(vtm_ms, 50), 4),
+                            "vtm_p99": round(percentile(vtm_ms, 99), 4)},
+             "mv_GBps": round(one_op / (percentile(mv_ms, 50) * 1e-3) / 1e9, 1),
+             "vtm_GBps": round(one_op / (percentile(vtm_ms, 50) * 1e-3) / 1e9, 1),
+             "plan": {k: info[k] for k in ("n_chunks", "n_zones", "n_panels", "panel_rows", "mv_workgroups",
+                                          "index_bytes", "relabeled", "device_bytes")},
+             "generate_s": round(gen_s, 2), "create_s": round(create_s, 2)}
+    if traffic:
+        extra["traffic_summary"] = os.path.relpath(TRAFFIC_FILE, ROOT)
+
+    if not args.no_tall:
+        # the tall mirror: the same arrays as CSR of the n x m transpose
+        T = SpwMatrix(SPW_CSR, A.n, A.m, A.ptr, A.idx, A.val)
+        xt = vd          # tall x has m_tall' = 50,000 ... entries: the short side
+        yt = torch.empty(A.n, dtype=torch.float64, device=dev)
+        vt = xd
+        ut = torch.empty(A.m, dtype=torch.float64, device=dev)
+        tot, _, tmv, tvtm = time_pairs(T, xt, vt, yt, ut, max(args.steps // 2, 5), 2)
+        extra["tall"] = {"workload": "CSR m=%d n=%d (same arrays)" % (A.n, A.m),
+                         "pair_GBps": round(pair_bytes / (tot / max(args.steps // 2, 5) * 1e-3) / 1e9, 1),
+                         "mv_GBps": round(one_op / (percentile(tmv, 50) * 1e-3) / 1e9, 1),
+                         "vtm_GBps": round(one_op / (percentile(tvtm, 50) * 1e-3) / 1e9, 1)}
+        T.close()
+        del yt, ut
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(A, x, v)
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "wide CSC m=%d n=%d nnz=%d (Zipf(1.1) column lengths + 100 half-dense "
+                                  "columns, Zipf(0.8) rows, lognormal values); step = y=Ax then u^T=v^T A"
+                                  % (A.m, A.n, A.nnz),
+                      "m": A.m, "n": A.n, "nnz": A.nnz, "pair_model_bytes": pair_bytes,
+                      "peak_GBps": HBM_PEAK_GBS, "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2)},
+           "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
+    print(json.dumps(out), flush=True)
+    M.close()
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str):
+    """Fold rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of a --profile-run
+    into per-launch HBM bytes for the product kernels, calibrated by the 1 GiB copy."""
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") == counter:
+                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return rows
+
+    out = ["# HBM traffic per launch, from rocprofv3 --pmc runs of `bench.py --profile-run`",
+           "# FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
+           "# the same counter on a 1 GiB device copy (copy_ kernel) to exactly 1 GiB.",
+           "kernel_source_sha256_16=%s" % kernel_hash()]
+    per = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = load(d, counter)
+        copy = [v for k, v in rows if "copy" in k.lower() or "elementwise" in k.lower()]
+        cal = None
+        if copy:
+            cal = (1 << 20) / (sorted(copy)[len(copy) // 2])   # KiB expected / KiB read
+        out.append("%s_copy_calibration=%s" % (counter, "%.4f" % cal if cal else "none"))
+        for name in ("mv_bucket_f64", "vtm_wave_f64", "mv_reduce_f64", "zone_fixup_f64", "gather_f64", "zero_cols_f64"):
+            vals = [v for k, v in rows if name in k]
+            if vals:
+                med = sorted(vals)[len(vals) // 2] * 1024.0 * (cal or 1.0)
+                per.setdefault(name, {})[counter] = med
+                out.append("%s_%s_bytes=%.0f" % (name, counter, med))
+    for name, d in per.items():
+        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
+            out.append("%s_bytes_per_launch=%.0f" % (name, d["FETCH_SIZE"] + d["WRITE_SIZE"]))
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -149,12 +149,16 @@ struct DeviceGuard {
     }
 };
 
-// Row panels and workgroups of the scatter product (see spw_internal.h).
+// Row panels, wave row sets and blocks of the scatter product (see
+// spw_internal.h and the scatter kernel).  idx_int holds the internal
+// (renumbered) rows.
 spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx_int, const double *val,
                             int64_t panel_rows_opt)
 {
     const int64_t rows = A.rows, cols = A.cols, nnz = A.nnz;
-    const int64_t TILE = mv_tile_nnz();
+    const int64_t BLK = mv_block_nnz();
+    const int64_t NB = mv_waves();
+    const int64_t SPAN = 65536;                 // columns a block may span (16-bit offsets)
     const int64_t limit = mv_lds_rows_limit(SPW_F64, 1);
     int64_t R = rows;
     if (panel_rows_opt > 0) R = std::min<int64_t>(panel_rows_opt, limit);
@@ -166,137 +170,169 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx
     const int64_t P = (rows + R - 1) / R;
     A.panel_rows = R;
     A.n_panels = P;
-    A.tile = TILE;
-
-    // Per-panel column pointers (absolute positions) and panel bases.
-    std::vector<int64_t> base((size_t)P + 1, 0);
-    std::vector<int32_t> pptr;
     const bool u16 = A.idx_kind == IdxKind::U16;
     auto row_of = [&](int64_t p) -> int64_t {
         return u16 ? (int64_t)((const uint16_t *)idx_int)[p] : (int64_t)((const int32_t *)idx_int)[p];
     };
+
+    // 1. Column-major order inside each panel: (panel, column) counts, then a
+    //    stable scatter of the source positions.
+    std::vector<int64_t> pptr((size_t)(P * (cols + 1)), 0);
+    std::vector<int64_t> order;
     if (P == 1) {
-        A.panels_alias = true;
-        A.d_pptr = A.d_ptr;
-        A.d_pidx = A.d_idx;
-        A.d_pval = A.d_val;
-        base[1] = nnz;
-        pptr.resize((size_t)cols + 1);
-        for (int64_t j = 0; j <= cols; ++j) pptr[(size_t)j] = (int32_t)ptr[j];
+        for (int64_t j = 0; j <= cols; ++j) pptr[(size_t)j] = ptr[j];
     } else {
-        A.panels_alias = false;
-        // count nonzeros per (panel, column)
         std::vector<int32_t> cnt((size_t)(P * cols), 0);
         parallel_for(cols, [&](int64_t a, int64_t b) {
             for (int64_t j = a; j < b; ++j)
                 for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) cnt[(size_t)(row_of(p) / R * cols + j)]++;
         });
-        std::vector<int64_t> pnnz((size_t)P, 0);
+        int64_t run = 0;
         for (int64_t q = 0; q < P; ++q) {
-            int64_t s = 0;
-            for (int64_t j = 0; j < cols; ++j) s += cnt[(size_t)(q * cols + j)];
-            pnnz[(size_t)q] = s;
-        }
-        for (int64_t q = 0; q < P; ++q) base[(size_t)q + 1] = round_up(base[(size_t)q] + pnnz[(size_t)q], TILE);
-        if (base[(size_t)P] >= ((int64_t)1 << 31) - TILE)
-            return fail(SPW_ERR_UNSUPPORTED, "panelled storage exceeds 2^31 positions");
-        pptr.resize((size_t)(P * (cols + 1)));
-        for (int64_t q = 0; q < P; ++q) {
-            int64_t run = base[(size_t)q];
-            int32_t *pp = pptr.data() + q * (cols + 1);
+            int64_t *pp = pptr.data() + q * (cols + 1);
             for (int64_t j = 0; j < cols; ++j) {
-                pp[j] = (int32_t)run;
+                pp[j] = run;
                 run += cnt[(size_t)(q * cols + j)];
             }
-            pp[cols] = (int32_t)run;
+            pp[cols] = run;
         }
         cnt.clear();
         cnt.shrink_to_fit();
-        const int64_t total = base[(size_t)P];
-        std::vector<double> pval((size_t)total, 0.0);
-        std::vector<uint16_t> pidx16;
-        std::vector<int32_t> pidx32;
-        if (u16) pidx16.assign((size_t)total, 0);
-        else pidx32.assign((size_t)total, 0);
+        order.resize((size_t)nnz);
         parallel_for(cols, [&](int64_t a, int64_t b) {
-            std::vector<int32_t> cur((size_t)P);
+            std::vector<int64_t> cur((size_t)P);
             for (int64_t j = a; j < b; ++j) {
                 for (int64_t q = 0; q < P; ++q) cur[(size_t)q] = pptr[(size_t)(q * (cols + 1) + j)];
-                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
-                    const int64_t r = row_of(p), q = r / R;
-                    const int64_t dst = cur[(size_t)q]++;
-                    pval[(size_t)dst] = val[p];
-                    if (u16) pidx16[(size_t)dst] = (uint16_t)(r - q * R);
-                    else pidx32[(size_t)dst] = (int32_t)(r - q * R);
-                }
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) order[(size_t)cur[(size_t)(row_of(p) / R)]++] = p;
             }
         });
-        int32_t *dp = nullptr;
-        double *dv = nullptr;
-        spw_status st = dev_alloc(A, &dp, P * (cols + 1), "panel column starts");
-        if (st) return st;
-        if ((st = h2d(dp, pptr.data(), pptr.size() * 4, "panel column starts"))) return st;
-        if ((st = dev_alloc(A, &dv, total, "panel values"))) return st;
-        if ((st = h2d(dv, pval.data(), (size_t)total * 8, "panel values"))) return st;
-        A.d_pptr = dp;
-        A.d_pval = dv;
-        if (u16) {
-            uint16_t *di = nullptr;
-            if ((st = dev_alloc(A, &di, total, "panel rows"))) return st;
-            if ((st = h2d(di, pidx16.data(), (size_t)total * 2, "panel rows"))) return st;
-            A.d_pidx = di;
-        } else {
-            int32_t *di = nullptr;
-            if ((st = dev_alloc(A, &di, total, "panel rows"))) return st;
-            if ((st = h2d(di, pidx32.data(), (size_t)total * 4, "panel rows"))) return st;
-            A.d_pidx = di;
+    }
+    auto src_of = [&](int64_t pos) -> int64_t { return P == 1 ? pos : order[(size_t)pos]; };
+
+    // 2. Deal each panel's rows to the NB waves, heaviest first onto the lightest wave.
+    std::vector<uint8_t> wave_of((size_t)rows, 0);
+    {
+        std::vector<int64_t> rc((size_t)rows, 0);
+        for (int64_t p = 0; p < nnz; ++p) rc[(size_t)row_of(p)]++;
+        for (int64_t q = 0; q < P; ++q) {
+            const int64_t r0 = q * R, r1 = std::min(rows, r0 + R);
+            std::vector<int32_t> rs((size_t)(r1 - r0));
+            std::iota(rs.begin(), rs.end(), (int32_t)r0);
+            std::stable_sort(rs.begin(), rs.end(), [&](int32_t a, int32_t b) { return rc[(size_t)a] > rc[(size_t)b]; });
+            std::vector<int64_t> load((size_t)NB, 0);
+            for (int32_t r : rs) {
+                const int64_t wv = std::min_element(load.begin(), load.end()) - load.begin();
+                wave_of[(size_t)r] = (uint8_t)wv;
+                load[(size_t)wv] += rc[(size_t)r];
+            }
         }
     }
 
-    // Tiles of each panel and their column ranges.
-    A.tiles.clear();
-    std::vector<int64_t> tile0((size_t)P + 1, 0);
-    for (int64_t q = 0; q < P; ++q) {
-        tile0[(size_t)q] = (int64_t)A.tiles.size();
-        const int32_t *pp = pptr.data() + (A.panels_alias ? 0 : q * (cols + 1));
-        const int64_t b0 = pp[0], b1 = pp[cols];
-        for (int64_t st = b0; st < b1; st += TILE) {
-            const int64_t en = std::min(b1, st + TILE);
-            // column holding st: last j with pp[j] <= st; column holding en-1 likewise
-            const int64_t jlo = std::upper_bound(pp, pp + cols + 1, (int32_t)st) - pp - 1;
-            const int64_t jhi = std::upper_bound(pp, pp + cols + 1, (int32_t)(en - 1)) - pp - 1;
-            A.tiles.push_back(Tile{(int32_t)st, (int32_t)en, (int32_t)jlo, (int32_t)jhi});
-        }
-    }
-    tile0[(size_t)P] = (int64_t)A.tiles.size();
-
-    // Workgroups: as many as fit the chip in one wave of launches, each with a
-    // contiguous run of one panel's tiles.
+    // 3. Workgroups: contiguous runs of one panel's column-ordered nonzeros, as
+    //    many in total as the chip runs at once.
     const int cus = device_cu_count(A.device);
-    const int64_t lds = R * 8 + 4160 * 4;
-    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, (160 * 1024) / std::max<int64_t>(lds, 1)));
+    const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024) / std::max<int64_t>(R * 8 + 256, 1)));
     const int64_t target = (int64_t)cus * per_cu;
-    const int64_t ntiles = (int64_t)A.tiles.size();
-    const int64_t tiles_per_wg = std::max<int64_t>(1, (ntiles + target - 1) / std::max<int64_t>(target, 1));
-    A.wgs.clear();
+    struct WgRange {
+        int32_t panel;
+        int64_t a, b;      // panel-ordered positions
+    };
+    std::vector<WgRange> wr;
     A.panels.clear();
     for (int64_t q = 0; q < P; ++q) {
+        const int64_t qa = pptr[(size_t)(q * (cols + 1))], qb = pptr[(size_t)(q * (cols + 1) + cols)];
         PanelDesc pd;
         pd.row0 = (int32_t)(q * R);
         pd.rows = (int32_t)std::min(R, rows - q * R);
-        pd.wg0 = (int32_t)A.wgs.size();
-        for (int64_t t = tile0[(size_t)q]; t < tile0[(size_t)q + 1]; t += tiles_per_wg)
-            A.wgs.push_back(WgDesc{(int32_t)q, (int32_t)t,
-                                   (int32_t)std::min(tile0[(size_t)q + 1], t + tiles_per_wg), 0});
-        pd.nwg = (int32_t)(A.wgs.size() - (size_t)pd.wg0);
+        pd.wg0 = (int32_t)wr.size();
+        if (qb > qa) {
+            const int64_t nw = std::max<int64_t>(1, (int64_t)((double)target * (double)(qb - qa) / (double)nnz + 0.5));
+            for (int64_t w = 0; w < nw; ++w) {
+                const int64_t a = qa + (qb - qa) * w / nw, b = qa + (qb - qa) * (w + 1) / nw;
+                if (b > a) wr.push_back(WgRange{(int32_t)q, a, b});
+            }
+        }
+        pd.nwg = (int32_t)(wr.size() - (size_t)pd.wg0);
         A.panels.push_back(pd);
     }
-    A.mv_wgs = (int64_t)A.wgs.size();
+    const int64_t W = (int64_t)wr.size();
+
+    // 4. Blocks per (workgroup, wave): nonzeros of that wave's rows in column
+    //    order, at most BLK per block and spanning fewer than SPAN columns.
+    struct Blk {
+        int32_t col_base, count;
+        uint32_t packed[512];
+        double val[512];
+    };
+    std::vector<std::vector<std::vector<Blk>>> wblocks((size_t)W);
+    parallel_for(W, [&](int64_t wa, int64_t wb) {
+        for (int64_t w = wa; w < wb; ++w) {
+            const WgRange &g = wr[(size_t)w];
+            const int64_t *pp = pptr.data() + (int64_t)g.panel * (cols + 1);
+            std::vector<std::vector<Blk>> &bl = wblocks[(size_t)w];
+            bl.assign((size_t)NB, {});
+            int64_t j = std::upper_bound(pp, pp + cols + 1, g.a) - pp - 1;
+            for (int64_t pos = g.a; pos < g.b; ++pos) {
+                while (pp[j + 1] <= pos) ++j;
+                const int64_t sp = src_of(pos);
+                const int64_t r = row_of(sp);
+                std::vector<Blk> &v = bl[wave_of[(size_t)r]];
+                if (v.empty() || v.back().count == BLK || j - v.back().col_base >= SPAN) {
+                    v.emplace_back();
+                    Blk &nb = v.back();
+                    nb.col_base = (int32_t)j;
+                    nb.count = 0;
+                    std::memset(nb.packed, 0, sizeof(nb.packed));
+                    std::memset(nb.val, 0, sizeof(nb.val));
+                }
+                Blk &cb = v.back();
+                const int32_t l = cb.count++;
+                const int32_t slot = (l % 64) * 8 + l / 64;     // logical l = (l/64)*64 + l%64
+                cb.packed[slot] = ((uint32_t)(r - (int64_t)g.panel * R) << 16) | (uint32_t)(j - cb.col_base);
+                cb.val[slot] = val[sp];
+            }
+        }
+    });
+    order.clear();
+    order.shrink_to_fit();
+    std::vector<int32_t> wg_blk((size_t)(W * (NB + 1)), 0);
+    int64_t nblk = 0;
+    for (int64_t w = 0; w < W; ++w)
+        for (int64_t b = 0; b < NB; ++b) {
+            wg_blk[(size_t)(w * (NB + 1) + b)] = (int32_t)nblk;
+            nblk += (int64_t)wblocks[(size_t)w][(size_t)b].size();
+            wg_blk[(size_t)(w * (NB + 1) + b + 1)] = (int32_t)nblk;
+        }
+    if (nblk * BLK >= ((int64_t)1 << 31)) return fail(SPW_ERR_UNSUPPORTED, "scatter-product storage exceeds 2^31 slots");
+    const int64_t nslots = std::max<int64_t>(nblk, 1) * BLK;
+    std::vector<uint32_t> packed((size_t)nslots, 0u);
+    std::vector<double> mval((size_t)nslots, 0.0);
+    std::vector<int32_t> bdesc((size_t)(2 * std::max<int64_t>(nblk, 1)), 0);
+    parallel_for(W, [&](int64_t wa, int64_t wb) {
+        for (int64_t w = wa; w < wb; ++w)
+            for (int64_t b = 0; b < NB; ++b) {
+                int64_t id = wg_blk[(size_t)(w * (NB + 1) + b)];
+                for (const Blk &bk : wblocks[(size_t)w][(size_t)b]) {
+                    bdesc[(size_t)(2 * id)] = bk.col_base;
+                    bdesc[(size_t)(2 * id + 1)] = bk.count;
+                    std::memcpy(&packed[(size_t)(id * BLK)], bk.packed, sizeof(bk.packed));
+                    std::memcpy(&mval[(size_t)(id * BLK)], bk.val, sizeof(bk.val));
+                    ++id;
+                }
+            }
+    });
+    wblocks.clear();
+    A.n_mblocks = nblk;
+    A.mv_wgs = W;
     spw_status st;
-    if ((st = dev_alloc(A, &A.d_tiles, std::max<int64_t>(ntiles, 1), "tiles"))) return st;
-    if ((st = h2d(A.d_tiles, A.tiles.data(), A.tiles.size() * sizeof(Tile), "tiles"))) return st;
-    if ((st = dev_alloc(A, &A.d_wgs, std::max<int64_t>(A.mv_wgs, 1), "workgroups"))) return st;
-    if ((st = h2d(A.d_wgs, A.wgs.data(), A.wgs.size() * sizeof(WgDesc), "workgroups"))) return st;
+    if ((st = dev_alloc(A, &A.d_mpacked, nslots, "block words"))) return st;
+    if ((st = h2d(A.d_mpacked, packed.data(), (size_t)nslots * 4, "block words"))) return st;
+    if ((st = dev_alloc(A, &A.d_mval, nslots, "block values"))) return st;
+    if ((st = h2d(A.d_mval, mval.data(), (size_t)nslots * 8, "block values"))) return st;
+    if ((st = dev_alloc(A, &A.d_mblocks, (int64_t)bdesc.size(), "block table"))) return st;
+    if ((st = h2d(A.d_mblocks, bdesc.data(), bdesc.size() * 4, "block table"))) return st;
+    if ((st = dev_alloc(A, &A.d_wg_blk, std::max<int64_t>((int64_t)wg_blk.size(), 1), "workgroup table"))) return st;
+    if ((st = h2d(A.d_wg_blk, wg_blk.data(), wg_blk.size() * 4, "workgroup table"))) return st;
     if ((st = dev_alloc(A, &A.d_panels, P, "panels"))) return st;
     if ((st = h2d(A.d_panels, A.panels.data(), A.panels.size() * sizeof(PanelDesc), "panels"))) return st;
     return SPW_OK;
@@ -495,8 +531,18 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     // Zone plan of the column dots.
     build_zone_plan(cols, ptr, chunk, A->zp);
     A->n_zones = (int64_t)A->zp.zone_col.size();
-    if ((st = dev_alloc(*A, &A->d_owned, A->zp.n_chunks + 1, "chunk table"))) return st;
-    if ((st = h2d(A->d_owned, A->zp.owned.data(), A->zp.owned.size() * 4, "chunk table"))) return st;
+    if ((st = dev_alloc(*A, &A->d_cjlo, std::max<int64_t>(A->zp.n_chunks, 1), "chunk table"))) return st;
+    if ((st = h2d(A->d_cjlo, A->zp.jlo.data(), A->zp.jlo.size() * 4, "chunk table"))) return st;
+    if ((st = dev_alloc(*A, &A->d_cjhi, std::max<int64_t>(A->zp.n_chunks, 1), "chunk table"))) return st;
+    if ((st = h2d(A->d_cjhi, A->zp.jhi.data(), A->zp.jhi.size() * 4, "chunk table"))) return st;
+    {
+        std::vector<int32_t> empty;
+        for (int64_t j = 0; j < cols; ++j)
+            if (ptr[j + 1] == ptr[j]) empty.push_back((int32_t)j);
+        A->n_empty = (int64_t)empty.size();
+        if ((st = dev_alloc(*A, &A->d_empty, std::max<int64_t>(A->n_empty, 1), "empty columns"))) return st;
+        if ((st = h2d(A->d_empty, empty.data(), empty.size() * 4, "empty columns"))) return st;
+    }
     if ((st = dev_alloc(*A, &A->d_zone_col, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
     if ((st = dev_alloc(*A, &A->d_zone_first, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
     if ((st = dev_alloc(*A, &A->d_zone_last, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;

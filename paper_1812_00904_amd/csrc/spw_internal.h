@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/spw.h"
+#include "spw.h"
 
 namespace spw {
 
@@ -29,6 +29,7 @@ struct ZonePlan {
     int64_t chunk = 0;
     int64_t n_chunks = 0;
     std::vector<int32_t> owned;       // n_chunks + 1
+    std::vector<int32_t> jlo, jhi;    // per chunk: columns holding its first / last position
     std::vector<int32_t> zone_col;    // per zone
     std::vector<int32_t> zone_first;  // first chunk (holds the column start)
     std::vector<int32_t> zone_last;   // last chunk touching the column
@@ -37,15 +38,6 @@ struct ZonePlan {
 // Builds the zone plan; ptr has cols+1 entries.  Pure host code.
 void build_zone_plan(int64_t cols, const int64_t *ptr, int64_t chunk, ZonePlan &out);
 
-// Tile of the scatter product: positions [start, end) of one panel, whose
-// columns lie in [jlo, jhi].
-struct Tile {
-    int32_t start, end, jlo, jhi;
-};
-// Workgroup of the scatter product: panel, tile range [t0, t1).
-struct WgDesc {
-    int32_t panel, t0, t1, pad;
-};
 // Panel of the scatter product: internal rows [row0, row0+rows), workgroups
 // [wg0, wg0+nwg) hold its partial vectors.
 struct PanelDesc {
@@ -82,23 +74,22 @@ struct spw_matrix_s {
     int32_t *d_inv = nullptr;           // rows: internal row -> caller row
 
     spw::ZonePlan zp;
-    int32_t *d_owned = nullptr;         // n_chunks + 1
+    int32_t *d_cjlo = nullptr;          // per chunk: column holding its first position
+    int32_t *d_cjhi = nullptr;          // per chunk: column holding its last position
+    int32_t *d_empty = nullptr;         // columns without nonzeros
+    int64_t n_empty = 0;
     int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
     int64_t n_zones = 0;
 
-    // scatter-product storage (row panels; aliases the column-dot arrays when
-    // there is a single panel)
+    // scatter-product storage: row panels; inside a panel, per workgroup column
+    // range and per wave (a set of the panel's rows), blocks of 512 nonzeros
     int64_t panel_rows = 0, n_panels = 0;
-    int64_t tile = 0;                   // nonzeros per scatter tile
-    int32_t *d_pptr = nullptr;          // n_panels * (cols + 1), absolute positions
-    void *d_pidx = nullptr;             // panel-local row indices
-    void *d_pval = nullptr;
-    bool panels_alias = true;
-    std::vector<spw::Tile> tiles;
-    std::vector<spw::WgDesc> wgs;
+    uint32_t *d_mpacked = nullptr;      // (panel-local row << 16) | (column - block column base)
+    double *d_mval = nullptr;
+    int32_t *d_mblocks = nullptr;       // per block: column base, count
+    int32_t *d_wg_blk = nullptr;        // per workgroup: waves+1 offsets into the blocks
+    int64_t n_mblocks = 0;
     std::vector<spw::PanelDesc> panels;
-    spw::Tile *d_tiles = nullptr;
-    spw::WgDesc *d_wgs = nullptr;
     spw::PanelDesc *d_panels = nullptr;
     int64_t mv_wgs = 0;
 
@@ -118,8 +109,10 @@ int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, in
               void *y, int64_t ldy, void *stream);
 // Device-side limits the host plan must respect.
 int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
-int64_t mv_tile_nnz();
+int64_t mv_block_nnz();
+int64_t mv_waves();
 int64_t vtm_chunk_default();
+int64_t vtm_hot_rows_limit();
 int device_cu_count(int device);
 
 // Profiling hooks (spw_profile.cpp).

@@ -1,24 +1,33 @@
 // HIP kernels for gfx950 (CDNA4, wave64) and their launch glue.
 //
 // Both products are bound by HBM bandwidth (about 0.17 flop per byte for
-// binary64 values with 2-byte row indices), so the kernels are written for
-// streaming: coalesced 16-byte loads of the index and value arrays, the short
-// vector read through L1/L2 (or held in LDS), no MFMA.
+// binary64 values with 2-byte row indices): no MFMA.  What decides their speed
+// on this chip is (a) keeping enough bytes in flight per CU and (b) keeping
+// the gathers of the dense vectors off the texture path when their addresses
+// diverge across a wave (each distinct cache line costs the L1 a cycle).  So
+// both kernels run persistent workgroups whose waves work independently (no
+// workgroup barrier inside the main loops), and the gathers go to LDS or are
+// arranged so that the lanes of one instruction touch few cache lines.
 //
 // Column dots (u_j = sum_i v_i b_ij over a CSC matrix B; the paper's v^T A,
-// Section IV-A): one workgroup per equal-nonzero chunk.  The chunk's products
-// are staged in LDS, each column that starts in the chunk is summed by one
-// lane (or one wave when long), and the partial sums of columns cut by a chunk
-// boundary ("overlap zones") go to a carry array; a second kernel adds the
-// carries of each zone in ascending chunk order (the zone reduction).
+// Section IV-A): each wave takes equal-nonzero chunks of 64*ITEMS positions
+// (the paper's nonzero split, Section II, with a wave as the processor).  The
+// most used entries of v (rows renumbered by count) are staged in LDS.  A lane
+// walks ITEMS consecutive positions, closing a run at every column end; runs
+// inside a lane are final, the first/last run of each lane are joined across
+// the wave by a segmented scan, and a column cut by a chunk boundary leaves a
+// carry that the zone kernel adds in ascending chunk order.
 //
 // Scatter product (y = B x; the paper's A x, Section III): a row panel of y
-// lives in LDS per workgroup; each workgroup streams a contiguous run of the
-// panel's nonzeros and adds a_ij x_j into LDS.  The waves of a workgroup take
-// turns (one wave at a time between barriers), so every LDS sum is formed in a
-// fixed order; the per-workgroup partial vectors are then added in ascending
-// workgroup order (the paper's y = sum_i y_(i)).  No floating-point atomics
-// touch global memory, so results are bit-identical from run to run.
+// lives in LDS per workgroup.  The panel's rows are dealt to the 16 waves of
+// the workgroup (balanced by count), and each wave streams, in column order,
+// only the nonzeros of its own rows, adding them into LDS.  No two waves touch
+// the same LDS entry, and a wave adds in program order, so every sum is formed
+// in a fixed order; the per-workgroup partial vectors are then added in
+// ascending workgroup order (the paper's y = sum_i y_(i)).  Consecutive lanes
+// hold consecutive nonzeros of one column range, so an x gather instruction
+// touches only a few cache lines.  No floating-point atomics touch global
+// memory: results are bit-identical from run to run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,138 +40,209 @@ namespace {
 
 constexpr int WAVE = 64;
 
-__device__ __forceinline__ double wave_sum(double v)
+// All lanes of the wave see each other's LDS writes after this point.
+__device__ __forceinline__ void wave_sync()
 {
-    // Butterfly over the 64 lanes; the pattern is fixed, so the result is too.
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Fixed-order sum over a workgroup; every lane receives the result.
-template <int BLOCK>
-__device__ __forceinline__ double block_sum(double v, double *red)
-{
-    constexpr int NW = BLOCK / WAVE;
-    v = wave_sum(v);
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) s += red[w];
-    return s;
-}
-
-template <typename IdxT> struct IdxPair;
-template <> struct IdxPair<uint16_t> {
-    __device__ __forceinline__ static void load(const uint16_t *p, int &a, int &b)
+template <typename IdxT, int N> struct IdxLoad;
+template <int N> struct IdxLoad<uint16_t, N> {   // N 2-byte indices, N multiple of 8
+    __device__ __forceinline__ static void load(const uint16_t *p, int *r)
     {
-        uint32_t w = *reinterpret_cast<const uint32_t *>(p);
-        a = (int)(w & 0xFFFFu);
-        b = (int)(w >> 16);
+#pragma unroll
+        for (int i = 0; i < N; i += 8) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(p + i);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                r[i + 2 * t] = (int)(w[t] & 0xFFFFu);
+                r[i + 2 * t + 1] = (int)(w[t] >> 16);
+            }
+        }
     }
 };
-template <> struct IdxPair<int32_t> {
-    __device__ __forceinline__ static void load(const int32_t *p, int &a, int &b)
+template <int N> struct IdxLoad<int32_t, N> {    // N 4-byte indices, N multiple of 4
+    __device__ __forceinline__ static void load(const int32_t *p, int *r)
     {
-        int2 w = *reinterpret_cast<const int2 *>(p);
-        a = w.x;
-        b = w.y;
+#pragma unroll
+        for (int i = 0; i < N; i += 4) {
+            const int4 q = *reinterpret_cast<const int4 *>(p + i);
+            r[i] = q.x;
+            r[i + 1] = q.y;
+            r[i + 2] = q.z;
+            r[i + 3] = q.w;
+        }
     }
 };
 
 // ------------------------------------------------------------------------
-// Column dots over one chunk.
-//   ptr    : cols+1 column starts (absolute positions)
-//   idx    : row of every position (renumbered rows when relabeled)
-//   val    : value of every position
-//   owned  : first column starting in each chunk (n_chunks+1 entries)
-//   v      : short input vector (already renumbered)
-//   u      : long output; columns wholly inside one chunk are final here
-//   carry  : [2c] = part of the column that entered chunk c from the left,
-//            [2c+1] = part of the last owned column when it leaves chunk c
+// Segmented sums across a wave.
+//
+// The pair operator is the paper's segmented addition (Section IV-B):
+//     (s, k) o (t, l) = (s + t, l) if k == l, else (t, l)
+// It is associative, so an inclusive scan of (partial sum, key) pairs over the
+// lanes leaves in each lane the running sum of its key's segment.  The scan
+// tree is fixed, so the rounding of every sum is reproducible.
 // ------------------------------------------------------------------------
-template <int BLOCK, int CHUNK, typename IdxT>
-__global__ __launch_bounds__(BLOCK) void vtm_chunk_f64(
+struct SegPair {
+    double s;
+    int k;
+};
+
+__device__ __forceinline__ SegPair seg_op(SegPair a, SegPair b)
+{
+    return (a.k == b.k) ? SegPair{a.s + b.s, b.k} : b;
+}
+
+__device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const double ps = __shfl_up(x.s, off, WAVE);
+        const int pk = __shfl_up(x.k, off, WAVE);
+        if (lane >= off) x = seg_op(SegPair{ps, pk}, x);
+    }
+    return x;
+}
+
+// ------------------------------------------------------------------------
+// Column dots, one wave per chunk of 64*ITEMS positions.
+//   ptr      : cols+1 column starts (absolute positions)
+//   idx, val : row (renumbered when relabeled) and value of every position
+//   cjlo/cjhi: column holding the chunk's first / last position
+//   v        : short input vector (renumbered); rows < vhot are read from LDS
+//   u        : long output; a column wholly inside the chunk is final here
+//   carry    : [2c] = part of the column entering chunk c from the left,
+//              [2c+1] = part of the column leaving chunk c to the right
+//              (a column crossing the whole chunk leaves its part in [2c])
+// Dynamic LDS: vhot doubles, then SLICE_W column starts per wave.  Columns
+// without nonzeros are written by zero_cols, not here.
+// ------------------------------------------------------------------------
+template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT>
+__global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
     const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const double *__restrict__ val,
-    const int32_t *__restrict__ owned, int64_t nnz, const double *__restrict__ v,
-    double *__restrict__ u, double *__restrict__ carry)
+    const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks,
+    const double *__restrict__ v, int vhot, double *__restrict__ u, double *__restrict__ carry)
 {
-    constexpr int LONG_SEG = 96;                 // segments longer than this use a whole wave
     constexpr int NW = BLOCK / WAVE;
-    __shared__ double prod[CHUNK];
-    __shared__ int long_cols[CHUNK / LONG_SEG + 2];
-    __shared__ int n_long;
-    __shared__ double red[NW];
+    constexpr int WCH = WAVE * ITEMS;
+    extern __shared__ double lds[];
+    double *vh = lds;
+    int32_t *slice = reinterpret_cast<int32_t *>(lds + vhot) + (threadIdx.x / WAVE) * SLICE_W;
+    const int lane = threadIdx.x & (WAVE - 1);
 
-    const int tid = threadIdx.x;
-    const int64_t c = blockIdx.x;
-    const int64_t s = c * (int64_t)CHUNK;
-    const int len = (int)min((int64_t)CHUNK, nnz - s);
+    for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
+    __syncthreads();
 
-    // Phase 1: products of the chunk into LDS (coalesced 16-byte value loads).
-    if (len == CHUNK) {
+    const int64_t stride = (int64_t)gridDim.x * NW;
+    for (int64_t c = (int64_t)blockIdx.x * NW + threadIdx.x / WAVE; c < nchunks; c += stride) {
+        const int s = (int)(c * WCH);
+        const int e = (int)min((int64_t)s + WCH, nnz);
+        const int jlo = cjlo[c], jhi = cjhi[c];
+        const int ncol = jhi - jlo + 2;           // starts of columns jlo .. jhi+1
+        const bool in_lds = ncol <= SLICE_W;
+        const int p0 = s + lane * ITEMS;
+        const int my_n = max(0, min(ITEMS, e - p0));
+
+        double a[ITEMS];
+        int r[ITEMS];
+        if (my_n == ITEMS) {
 #pragma unroll
-        for (int r = 0; r < CHUNK / (2 * BLOCK); ++r) {
-            const int e = 2 * (tid + r * BLOCK);
-            const double2 a = *reinterpret_cast<const double2 *>(val + s + e);
-            int i0, i1;
-            IdxPair<IdxT>::load(idx + s + e, i0, i1);
-            double2 pr;
-            pr.x = a.x * v[i0];
-            pr.y = a.y * v[i1];
-            *reinterpret_cast<double2 *>(prod + e) = pr;
+            for (int i = 0; i < ITEMS; i += 2) {
+                const double2 w = *reinterpret_cast<const double2 *>(val + p0 + i);
+                a[i] = w.x;
+                a[i + 1] = w.y;
+            }
+            IdxLoad<IdxT, ITEMS>::load(idx + p0, r);
+        } else {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                a[i] = (i < my_n) ? val[p0 + i] : 0.0;
+                r[i] = (i < my_n) ? (int)idx[p0 + i] : 0;
+            }
         }
-    } else {
-        for (int e = tid; e < len; e += BLOCK) prod[e] = val[s + e] * v[(int)idx[s + e]];
-    }
-    if (tid == 0) n_long = 0;
-    __syncthreads();
-
-    const int o0 = owned[c], o1 = owned[c + 1];
-    const int64_t e_abs = s + len;
-
-    // Phase 2a: the column entering from the left (a zone member), if any.
-    const int lend = (int)min((int64_t)ptr[o0] - s, (int64_t)len);
-    if (lend > 0) {
-        double part = 0.0;
-        for (int e = tid; e < lend; e += BLOCK) part += prod[e];
-        part = block_sum<BLOCK>(part, red);
-        if (tid == 0) carry[2 * c] = part;
-    }
-
-    // Phase 2b: columns starting in this chunk, one lane each.
-    for (int j = o0 + tid; j < o1; j += BLOCK) {
-        const int64_t a = ptr[j], b = ptr[j + 1];
-        const int aa = (int)(a - s), bb = (int)(min(b, e_abs) - s);
-        if (bb - aa > LONG_SEG) {
-            long_cols[atomicAdd(&n_long, 1)] = j;
-            continue;
+        if (in_lds)
+            for (int i = lane; i < ncol; i += WAVE) slice[i] = ptr[jlo + i];
+        double prod[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const int ri = r[i];
+            prod[i] = a[i] * (ri < vhot ? vh[ri] : v[ri]);
         }
-        double sum = 0.0;
-        for (int e = aa; e < bb; ++e) sum += prod[e];
-        if (b <= e_abs) u[j] = sum;
-        else carry[2 * c + 1] = sum;
-    }
-    __syncthreads();
+        wave_sync();
+        const int32_t *cs = in_lds ? slice : ptr + jlo;
 
-    // Phase 2c: long columns, one wave each (lane-strided, then a fixed butterfly).
-    const int wave = tid / WAVE, lane = tid % WAVE;
-    const int nl = n_long;
-    for (int q = wave; q < nl; q += NW) {
-        const int j = long_cols[q];
-        const int64_t a = ptr[j], b = ptr[j + 1];
-        const int aa = (int)(a - s), bb = (int)(min(b, e_abs) - s);
-        double part = 0.0;
-        for (int e = aa + lane; e < bb; e += WAVE) part += prod[e];
-        part = wave_sum(part);
-        if (lane == 0) {
-            if (b <= e_abs) u[j] = part;
-            else carry[2 * c + 1] = part;
+        double head_sum = 0.0, run = 0.0;
+        int hk, k;
+        bool multi = false;
+        if (my_n > 0) {
+            int lo = 0, hi = ncol - 2;            // largest k with cs[k] <= p0
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cs[mid] <= p0) lo = mid;
+                else hi = mid - 1;
+            }
+            k = lo;
+            int nxt = cs[k + 1];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                if (i < my_n) {
+                    const int p = p0 + i;
+                    if (p >= nxt) {
+                        if (!multi) {
+                            head_sum = run;
+                            hk = k;
+                            multi = true;
+                        } else {
+                            u[jlo + k] = run;    // column wholly inside this lane
+                        }
+                        do {
+                            ++k;
+                            nxt = cs[k + 1];
+                        } while (nxt <= p);
+                        run = 0.0;
+                    }
+                    run += prod[i];
+                }
+            }
+            if (!multi) hk = k;
+        } else {
+            k = -2 - lane;                        // inactive lane: a key no one shares
+            hk = -2 - lane;
         }
+
+        const SegPair o = wave_seg_scan(SegPair{run, k});
+        const double prev_s = __shfl_up(o.s, 1, WAVE);
+        const int prev_k = __shfl_up(o.k, 1, WAVE);
+        const int next_hk = __shfl_down(hk, 1, WAVE);
+        if (my_n > 0) {
+            auto emit = [&](int kk, double value) {
+                const bool before = cs[kk] < s, after = cs[kk + 1] > e;
+                if (before) carry[2 * c] = value;
+                else if (after) carry[2 * c + 1] = value;
+                else u[jlo + kk] = value;
+            };
+            if (multi) {
+                // the lane's first column ends inside it: add what earlier lanes hold
+                double tot = head_sum;
+                if (lane > 0 && prev_k == hk) tot = prev_s + head_sum;
+                emit(hk, tot);
+            }
+            if (lane == WAVE - 1 || next_hk != k) emit(k, o.s);
+        }
+        wave_sync();                              // slice reads done before the next chunk
     }
+}
+
+// Columns without nonzeros: u_j = 0.
+__global__ void zero_cols_f64(const int32_t *__restrict__ cols, int64_t count, double *__restrict__ u)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < count) u[cols[i]] = 0.0;
 }
 
 // Zone reduction: u[j_k] = right carry of the first chunk + left carries of the
@@ -187,104 +267,61 @@ __global__ void gather_f64(const int32_t *__restrict__ inv, int64_t len, const d
     if (r < len) out[r] = in[inv[r]];
 }
 
-__global__ void fill_f64(double *__restrict__ out, int64_t len, double value)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < len) out[i] = value;
-}
-
 // ------------------------------------------------------------------------
-// Scatter product over one panel.
-//   pptr    : n_panels blocks of cols+1 column starts (absolute positions)
-//   idx/val : panel-local rows and values, panels padded to whole tiles
-//   tiles   : [start, end) positions and column range [jlo, jhi] of each tile
-//   wgs     : panel and tile range of each workgroup
-//   partial : per-workgroup partial sums, panel_rows entries each
-// Dynamic LDS: panel_rows doubles (the y panel) + SLICE ints (column starts).
+// Scatter product over one row panel.
+// Storage: blocks of 512 nonzeros.  A block holds nonzeros of one wave's rows,
+// in column order, from one workgroup's column range; logical nonzero
+// j*64 + lane sits at slot lane*8 + j, so each lane loads its 8 slots as
+// 16-byte vectors while each add instruction covers 64 consecutive nonzeros.
+// A slot holds (panel-local row << 16 | column - block column base) and the value.
+//   blocks : (column base, count) per block
+//   wg_blk : per workgroup, NW+1 offsets into blocks: wave w owns [wg_blk[w], wg_blk[w+1])
+//   partial: per-workgroup partial sums, panel_rows entries each
+// Dynamic LDS: panel_rows doubles.
 // ------------------------------------------------------------------------
-template <int BLOCK, int ITEMS, int SLICE, typename IdxT>
-__global__ __launch_bounds__(BLOCK) void mv_panel_f64(
-    const int32_t *__restrict__ pptr, int64_t ptr_len, const IdxT *__restrict__ idx,
-    const double *__restrict__ val, const Tile *__restrict__ tiles, const WgDesc *__restrict__ wgs,
-    const double *__restrict__ x, double *__restrict__ partial, int panel_rows)
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
+    const uint32_t *__restrict__ packed, const double *__restrict__ val, const int2 *__restrict__ blocks,
+    const int32_t *__restrict__ wg_blk, const double *__restrict__ x, double *__restrict__ partial,
+    int panel_rows)
 {
-    extern __shared__ double smem[];
-    double *ypan = smem;
-    int32_t *slice = reinterpret_cast<int32_t *>(smem + panel_rows);
     constexpr int NW = BLOCK / WAVE;
-    const int tid = threadIdx.x, wave = tid / WAVE;
-
-    const WgDesc wd = wgs[blockIdx.x];
-    const int32_t *ptr = pptr + (int64_t)wd.panel * ptr_len;
+    extern __shared__ double ypan[];
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
     for (int i = tid; i < panel_rows; i += BLOCK) ypan[i] = 0.0;
+    __syncthreads();
 
-    for (int t = wd.t0; t < wd.t1; ++t) {
-        const Tile td = tiles[t];
-        const int ncol = td.jhi - td.jlo + 2;        // column starts jlo .. jhi+1
-        const bool in_lds = ncol <= SLICE;
-        __syncthreads();                             // previous tile is done with `slice`
-        if (in_lds)
-            for (int i = tid; i < ncol; i += BLOCK) slice[i] = ptr[td.jlo + i];
-        __syncthreads();
-        const int32_t *cs = in_lds ? slice : ptr + td.jlo;   // cs[k] = start of column jlo+k
-
-        double prod[ITEMS];
-        int row[ITEMS];
-        const int p0 = td.start + tid * ITEMS;
-        if (p0 < td.end) {
-            // largest k with cs[k] <= p0 (the column holding p0)
-            int lo = 0, hi = ncol - 2;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (cs[mid] <= p0) lo = mid;
-                else hi = mid - 1;
-            }
-            int k = lo;
-            int nxt = cs[k + 1];
-            if (p0 + ITEMS <= td.end) {
-                double vv[ITEMS];
-                int rr[ITEMS];
+    const int32_t *wb = wg_blk + (int64_t)blockIdx.x * (NW + 1);
+    const int b0 = wb[wave], b1 = wb[wave + 1];
+    uint32_t w[8];
+    double a[8];
+    int2 bd;
+    auto load = [&](int b) {
+        bd = blocks[b];
+        const int64_t base = (int64_t)b * 512 + lane * 8;
+        const uint4 q0 = *reinterpret_cast<const uint4 *>(packed + base);
+        const uint4 q1 = *reinterpret_cast<const uint4 *>(packed + base + 4);
+        w[0] = q0.x; w[1] = q0.y; w[2] = q0.z; w[3] = q0.w;
+        w[4] = q1.x; w[5] = q1.y; w[6] = q1.z; w[7] = q1.w;
 #pragma unroll
-                for (int i = 0; i < ITEMS; i += 2) {
-                    const double2 a = *reinterpret_cast<const double2 *>(val + p0 + i);
-                    vv[i] = a.x;
-                    vv[i + 1] = a.y;
-                    IdxPair<IdxT>::load(idx + p0 + i, rr[i], rr[i + 1]);
-                }
-#pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    while (nxt <= p0 + i) { ++k; nxt = cs[k + 1]; }
-                    prod[i] = vv[i] * x[td.jlo + k];
-                    row[i] = rr[i];
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const int p = p0 + i;
-                    if (p < td.end) {
-                        while (nxt <= p) { ++k; nxt = cs[k + 1]; }
-                        prod[i] = val[p] * x[td.jlo + k];
-                        row[i] = (int)idx[p];
-                    } else {
-                        prod[i] = 0.0;
-                        row[i] = -1;
-                    }
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) { prod[i] = 0.0; row[i] = -1; }
+        for (int j = 0; j < 8; j += 2) {
+            const double2 d = *reinterpret_cast<const double2 *>(val + base + j);
+            a[j] = d.x;
+            a[j + 1] = d.y;
         }
-        // Waves add into the LDS panel one at a time: a fixed order per entry.
-        for (int w = 0; w < NW; ++w) {
-            if (wave == w) {
+    };
+    if (b0 < b1) load(b0);
+    for (int b = b0; b < b1; ++b) {
+        const uint32_t cw[8] = {w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]};
+        const double ca[8] = {a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]};
+        const int2 cb = bd;
+        if (b + 1 < b1) load(b + 1);              // next block in flight while this one is added
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i)
-                    if (row[i] >= 0)
-                        __hip_atomic_fetch_add(&ypan[row[i]], prod[i], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        for (int j = 0; j < 8; ++j) {
+            if (j * WAVE + lane < cb.y) {
+                const double p = ca[j] * x[cb.x + (int)(cw[j] & 0xFFFFu)];
+                __hip_atomic_fetch_add(&ypan[cw[j] >> 16], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            __syncthreads();
         }
     }
     __syncthreads();
@@ -308,11 +345,11 @@ __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows
     y[inv ? inv[r] : r] = s;
 }
 
-constexpr int VTM_BLOCK = 256;
-constexpr int VTM_CHUNK = 4096;
-constexpr int MV_BLOCK = 512;
-constexpr int MV_ITEMS = 8;
-constexpr int MV_SLICE = 4160;
+constexpr int VTM_BLOCK = 1024;
+constexpr int VTM_ITEMS = 16;
+constexpr int VTM_SLICE_W = 256;
+constexpr int MV_BLOCK = 1024;
+constexpr int LDS_BYTES = 160 * 1024;
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
@@ -329,16 +366,23 @@ struct ProfScope {
     }
 };
 
+template <typename K>
+void allow_full_lds(K kernel)
+{
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+}
+
 }  // namespace
 
 int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k)
 {
     (void)vdt;
-    const int64_t lds = 160 * 1024 - MV_SLICE * 4 - 256;
-    return lds / (8 * std::max<int32_t>(k, 1));
+    return std::min<int64_t>((LDS_BYTES - 256) / (8 * std::max<int32_t>(k, 1)), 65536);
 }
-int64_t mv_tile_nnz() { return (int64_t)MV_BLOCK * MV_ITEMS; }
-int64_t vtm_chunk_default() { return VTM_CHUNK; }
+int64_t mv_block_nnz() { return 512; }
+int64_t mv_waves() { return MV_BLOCK / WAVE; }
+int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
+int64_t vtm_hot_rows_limit() { return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / 8; }
 
 int device_cu_count(int device)
 {
@@ -355,11 +399,14 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
         return (int)hipErrorNotSupported;
     double *uo = (double *)u;
     if (A.cols == 0) return 0;
-    if (A.nnz == 0) {
-        ProfScope ps(stream, "fill_f64");
-        hipLaunchKernelGGL(fill_f64, dim3(blocks_for(A.cols, 256)), dim3(256), 0, stream, uo, A.cols, 0.0);
-        return (int)hipGetLastError();
+    if (A.n_empty > 0) {
+        ProfScope ps(stream, "zero_cols_f64");
+        hipLaunchKernelGGL(zero_cols_f64, dim3(blocks_for(A.n_empty, 256)), dim3(256), 0, stream, A.d_empty,
+                           A.n_empty, uo);
+        int e = (int)hipGetLastError();
+        if (e) return e;
     }
+    if (A.nnz == 0) return 0;
     const double *vin = (const double *)v;
     if (A.relabeled) {
         ProfScope ps(stream, "gather_f64");
@@ -368,16 +415,29 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
         vin = (const double *)A.scratch.vperm;
     }
     {
-        ProfScope ps(stream, "vtm_chunk_f64");
-        if (A.zp.chunk != VTM_CHUNK) return (int)hipErrorNotSupported;
+        ProfScope ps(stream, "vtm_wave_f64");
+        if (A.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
+        const int vhot = (int)std::min<int64_t>(A.rows, vtm_hot_rows_limit());
+        const size_t lds = (size_t)vhot * 8 + (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
+        const int cus = device_cu_count(A.device);
+        const int64_t wgs_needed = (A.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
+        static bool attr = false;
+        if (!attr) {
+            allow_full_lds(vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t>);
+            allow_full_lds(vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>);
+            attr = true;
+        }
         if (A.idx_kind == IdxKind::U16)
-            hipLaunchKernelGGL((vtm_chunk_f64<VTM_BLOCK, VTM_CHUNK, uint16_t>), dim3((unsigned)A.zp.n_chunks),
-                               dim3(VTM_BLOCK), 0, stream, A.d_ptr, (const uint16_t *)A.d_idx,
-                               (const double *)A.d_val, A.d_owned, A.nnz, vin, uo, A.scratch.carry);
+            hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t>), dim3(grid),
+                               dim3(VTM_BLOCK), lds, stream, A.d_ptr, (const uint16_t *)A.d_idx,
+                               (const double *)A.d_val, A.d_cjlo, A.d_cjhi, A.nnz, A.zp.n_chunks, vin, vhot, uo,
+                               A.scratch.carry);
         else
-            hipLaunchKernelGGL((vtm_chunk_f64<VTM_BLOCK, VTM_CHUNK, int32_t>), dim3((unsigned)A.zp.n_chunks),
-                               dim3(VTM_BLOCK), 0, stream, A.d_ptr, (const int32_t *)A.d_idx,
-                               (const double *)A.d_val, A.d_owned, A.nnz, vin, uo, A.scratch.carry);
+            hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>), dim3(grid),
+                               dim3(VTM_BLOCK), lds, stream, A.d_ptr, (const int32_t *)A.d_idx,
+                               (const double *)A.d_val, A.d_cjlo, A.d_cjhi, A.nnz, A.zp.n_chunks, vin, vhot, uo,
+                               A.scratch.carry);
         int e = (int)hipGetLastError();
         if (e) return e;
     }
@@ -400,27 +460,16 @@ int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, in
     double *yo = (double *)y;
     if (A.rows == 0) return 0;
     if (A.mv_wgs > 0) {
-        ProfScope ps(stream, "mv_panel_f64");
-        const size_t lds = (size_t)A.panel_rows * 8 + (size_t)MV_SLICE * 4;
-        static bool attr_set = false;
-        if (!attr_set) {
-            const int cap = 160 * 1024;
-            (void)hipFuncSetAttribute((const void *)mv_panel_f64<MV_BLOCK, MV_ITEMS, MV_SLICE, uint16_t>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-            (void)hipFuncSetAttribute((const void *)mv_panel_f64<MV_BLOCK, MV_ITEMS, MV_SLICE, int32_t>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-            attr_set = true;
+        ProfScope ps(stream, "mv_bucket_f64");
+        const size_t lds = (size_t)A.panel_rows * 8;
+        static bool attr = false;
+        if (!attr) {
+            allow_full_lds(mv_bucket_f64<MV_BLOCK>);
+            attr = true;
         }
-        if (A.idx_kind == IdxKind::U16)
-            hipLaunchKernelGGL((mv_panel_f64<MV_BLOCK, MV_ITEMS, MV_SLICE, uint16_t>), dim3((unsigned)A.mv_wgs),
-                               dim3(MV_BLOCK), lds, stream, A.d_pptr, A.cols + 1, (const uint16_t *)A.d_pidx,
-                               (const double *)A.d_pval, A.d_tiles, A.d_wgs, (const double *)x,
-                               A.scratch.partial, (int)A.panel_rows);
-        else
-            hipLaunchKernelGGL((mv_panel_f64<MV_BLOCK, MV_ITEMS, MV_SLICE, int32_t>), dim3((unsigned)A.mv_wgs),
-                               dim3(MV_BLOCK), lds, stream, A.d_pptr, A.cols + 1, (const int32_t *)A.d_pidx,
-                               (const double *)A.d_pval, A.d_tiles, A.d_wgs, (const double *)x,
-                               A.scratch.partial, (int)A.panel_rows);
+        hipLaunchKernelGGL((mv_bucket_f64<MV_BLOCK>), dim3((unsigned)A.mv_wgs), dim3(MV_BLOCK), lds, stream,
+                           (const uint32_t *)A.d_mpacked, (const double *)A.d_mval, (const int2 *)A.d_mblocks,
+                           A.d_wg_blk, (const double *)x, A.scratch.partial, (int)A.panel_rows);
         int e = (int)hipGetLastError();
         if (e) return e;
     }

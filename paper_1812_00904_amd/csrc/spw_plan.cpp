@@ -22,6 +22,8 @@ void build_zone_plan(int64_t cols, const int64_t *ptr, int64_t chunk, ZonePlan &
     zp.chunk = chunk;
     zp.n_chunks = nnz > 0 ? (nnz + chunk - 1) / chunk : 0;
     zp.owned.assign((size_t)zp.n_chunks + 1, 0);
+    zp.jlo.assign((size_t)zp.n_chunks, 0);
+    zp.jhi.assign((size_t)zp.n_chunks, 0);
     zp.zone_col.clear();
     zp.zone_first.clear();
     zp.zone_last.clear();
@@ -31,6 +33,10 @@ void build_zone_plan(int64_t cols, const int64_t *ptr, int64_t chunk, ZonePlan &
         // first column whose start is at or after s
         const int64_t o = std::lower_bound(ptr, end, s) - ptr;
         zp.owned[(size_t)c] = (int32_t)o;
+        // columns holding the first and the last position of the chunk
+        const int64_t e = std::min(nnz, s + chunk);
+        zp.jlo[(size_t)c] = (int32_t)(std::upper_bound(ptr, end, s) - ptr - 1);
+        zp.jhi[(size_t)c] = (int32_t)(std::upper_bound(ptr, end, e - 1) - ptr - 1);
         if (c > 0 && ptr[o] > s) {
             // column o-1 starts before s and reaches into chunk c: a zone member
             const int32_t j = (int32_t)(o - 1);
