@@ -261,9 +261,10 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx
     //    order, at most BLK per block and spanning fewer than SPAN columns.
     struct Blk {
         int32_t col_base, count;
-        uint32_t packed[512];
-        double val[512];
+        uint32_t packed[1024];
+        double val[1024];
     };
+    if (BLK > 1024 || BLK % 256) return fail(SPW_ERR_UNSUPPORTED, "scatter block size mismatch");
     std::vector<std::vector<std::vector<Blk>>> wblocks((size_t)W);
     parallel_for(W, [&](int64_t wa, int64_t wb) {
         for (int64_t w = wa; w < wb; ++w) {
@@ -282,14 +283,16 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx
                     Blk &nb = v.back();
                     nb.col_base = (int32_t)j;
                     nb.count = 0;
-                    std::memset(nb.packed, 0, sizeof(nb.packed));
-                    std::memset(nb.val, 0, sizeof(nb.val));
+                    std::memset(nb.packed, 0, (size_t)BLK * sizeof(uint32_t));
+                    std::memset(nb.val, 0, (size_t)BLK * sizeof(double));
                 }
                 Blk &cb = v.back();
+                // logical nonzero l = jj*64 + ln goes to the interleaved slots the kernel reads
                 const int32_t l = cb.count++;
-                const int32_t slot = (l % 64) * 8 + l / 64;     // logical l = (l/64)*64 + l%64
-                cb.packed[slot] = ((uint32_t)(r - (int64_t)g.panel * R) << 16) | (uint32_t)(j - cb.col_base);
-                cb.val[slot] = val[sp];
+                const int32_t jj = l / 64, ln = l % 64;
+                cb.packed[((jj / 4) * 64 + ln) * 4 + jj % 4] =
+                    ((uint32_t)(r - (int64_t)g.panel * R) << 16) | (uint32_t)(j - cb.col_base);
+                cb.val[((jj / 2) * 64 + ln) * 2 + jj % 2] = val[sp];
             }
         }
     });
@@ -315,8 +318,8 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx
                 for (const Blk &bk : wblocks[(size_t)w][(size_t)b]) {
                     bdesc[(size_t)(2 * id)] = bk.col_base;
                     bdesc[(size_t)(2 * id + 1)] = bk.count;
-                    std::memcpy(&packed[(size_t)(id * BLK)], bk.packed, sizeof(bk.packed));
-                    std::memcpy(&mval[(size_t)(id * BLK)], bk.val, sizeof(bk.val));
+                    std::memcpy(&packed[(size_t)(id * BLK)], bk.packed, (size_t)BLK * sizeof(uint32_t));
+                    std::memcpy(&mval[(size_t)(id * BLK)], bk.val, (size_t)BLK * sizeof(double));
                     ++id;
                 }
             }
@@ -494,37 +497,56 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
         if ((st = dev_alloc(*A, &A->d_ptr, cols + 1, "column starts"))) return st;
         if ((st = h2d(A->d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
     }
+    // Logical-order internal rows (used to build the scatter storage), and the
+    // chunk-interleaved copies the column-dot kernel reads: inside each chunk of
+    // W = 64*I positions, item i of lane l (position l*I + i) is stored at
+    // ((i/G)*64 + l)*G + i%G, G being the number of elements in 16 bytes.
+    const int64_t WCH = vtm_chunk_default(), ITEMS = WCH / 64;
+    auto ilv = [&](int64_t p, int64_t G) -> int64_t {
+        const int64_t o = p % WCH, cb = p - o, ln = o / ITEMS, i = o % ITEMS;
+        return cb + ((i / G) * 64 + ln) * G + i % G;
+    };
     std::vector<uint16_t> i16;
     std::vector<int32_t> i32;
     const void *idx_int = nullptr;
+    const bool rl = A->relabeled != 0;
     if (A->idx_kind == IdxKind::U16) {
-        i16.assign((size_t)zpad, 0);
-        const bool rl = A->relabeled != 0;
+        i16.assign((size_t)std::max<int64_t>(nnz, 1), 0);
         parallel_for(nnz, [&](int64_t a, int64_t b) {
             for (int64_t p = a; p < b; ++p) i16[(size_t)p] = (uint16_t)(rl ? rank[(size_t)idx[p]] : idx[p]);
         });
+        std::vector<uint16_t> ii((size_t)zpad, 0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 8)] = i16[(size_t)p];
+        });
         uint16_t *d = nullptr;
         if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
-        if ((st = h2d(d, i16.data(), (size_t)zpad * 2, "row indices"))) return st;
+        if ((st = h2d(d, ii.data(), (size_t)zpad * 2, "row indices"))) return st;
         A->d_idx = d;
         idx_int = i16.data();
     } else {
-        i32.assign((size_t)zpad, 0);
-        const bool rl = A->relabeled != 0;
+        i32.assign((size_t)std::max<int64_t>(nnz, 1), 0);
         parallel_for(nnz, [&](int64_t a, int64_t b) {
             for (int64_t p = a; p < b; ++p) i32[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
         });
+        std::vector<int32_t> ii((size_t)zpad, 0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 4)] = i32[(size_t)p];
+        });
         int32_t *d = nullptr;
         if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
-        if ((st = h2d(d, i32.data(), (size_t)zpad * 4, "row indices"))) return st;
+        if ((st = h2d(d, ii.data(), (size_t)zpad * 4, "row indices"))) return st;
         A->d_idx = d;
         idx_int = i32.data();
     }
     {
+        std::vector<double> vi((size_t)zpad, 0.0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) vi[(size_t)ilv(p, 2)] = val[p];
+        });
         double *d = nullptr;
         if ((st = dev_alloc(*A, &d, zpad, "values"))) return st;
-        if (hipMemset(d, 0, (size_t)zpad * 8) != hipSuccess) return fail(SPW_ERR_DEVICE, "hipMemset failed");
-        if ((st = h2d(d, val, (size_t)nnz * 8, "values"))) return st;
+        if ((st = h2d(d, vi.data(), (size_t)zpad * 8, "values"))) return st;
         A->d_val = d;
     }
 

@@ -40,6 +40,10 @@ namespace {
 
 constexpr int WAVE = 64;
 
+// Native vector types: non-temporal loads need them.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
 // All lanes of the wave see each other's LDS writes after this point.
 __device__ __forceinline__ void wave_sync()
 {
@@ -48,32 +52,36 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Loads the N indices of one lane from an interleaved chunk (see the column-dot
+// kernel): group g of 16 bytes of lane l sits at (g*64 + l)*16 bytes.
 template <typename IdxT, int N> struct IdxLoad;
-template <int N> struct IdxLoad<uint16_t, N> {   // N 2-byte indices, N multiple of 8
-    __device__ __forceinline__ static void load(const uint16_t *p, int *r)
+template <int N> struct IdxLoad<uint16_t, N> {
+    __device__ __forceinline__ static void load(const uint16_t *base, int lane, int *r)
     {
 #pragma unroll
-        for (int i = 0; i < N; i += 8) {
-            const uint4 q = *reinterpret_cast<const uint4 *>(p + i);
+        for (int g = 0; g < N / 8; ++g) {
+            const u32x4_t q =
+                __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base + (int64_t)(g * 64 + lane) * 8));
             const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                r[i + 2 * t] = (int)(w[t] & 0xFFFFu);
-                r[i + 2 * t + 1] = (int)(w[t] >> 16);
+                r[8 * g + 2 * t] = (int)(w[t] & 0xFFFFu);
+                r[8 * g + 2 * t + 1] = (int)(w[t] >> 16);
             }
         }
     }
 };
-template <int N> struct IdxLoad<int32_t, N> {    // N 4-byte indices, N multiple of 4
-    __device__ __forceinline__ static void load(const int32_t *p, int *r)
+template <int N> struct IdxLoad<int32_t, N> {
+    __device__ __forceinline__ static void load(const int32_t *base, int lane, int *r)
     {
 #pragma unroll
-        for (int i = 0; i < N; i += 4) {
-            const int4 q = *reinterpret_cast<const int4 *>(p + i);
-            r[i] = q.x;
-            r[i + 1] = q.y;
-            r[i + 2] = q.z;
-            r[i + 3] = q.w;
+        for (int g = 0; g < N / 4; ++g) {
+            const u32x4_t q =
+                __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base + (int64_t)(g * 64 + lane) * 4));
+            r[4 * g] = (int)q.x;
+            r[4 * g + 1] = (int)q.y;
+            r[4 * g + 2] = (int)q.z;
+            r[4 * g + 3] = (int)q.w;
         }
     }
 };
@@ -148,22 +156,22 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
         const int p0 = s + lane * ITEMS;
         const int my_n = max(0, min(ITEMS, e - p0));
 
+        // Storage inside a chunk is interleaved so that each load instruction
+        // reads one contiguous span: item i of lane l sits at value slot
+        // ((i/2)*64 + l)*2 + i%2 and at index slot ((i/G)*64 + l)*G + i%G,
+        // with G = 16 / sizeof(index).  Tails are zero-padded.
         double a[ITEMS];
         int r[ITEMS];
-        if (my_n == ITEMS) {
+        {
+            const int64_t cb = c * WCH;
 #pragma unroll
-            for (int i = 0; i < ITEMS; i += 2) {
-                const double2 w = *reinterpret_cast<const double2 *>(val + p0 + i);
-                a[i] = w.x;
-                a[i + 1] = w.y;
+            for (int q = 0; q < ITEMS / 2; ++q) {
+                const f64x2_t w = __builtin_nontemporal_load(
+                    reinterpret_cast<const f64x2_t *>(val + cb + (int64_t)(q * WAVE + lane) * 2));
+                a[2 * q] = w.x;
+                a[2 * q + 1] = w.y;
             }
-            IdxLoad<IdxT, ITEMS>::load(idx + p0, r);
-        } else {
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                a[i] = (i < my_n) ? val[p0 + i] : 0.0;
-                r[i] = (i < my_n) ? (int)idx[p0 + i] : 0;
-            }
+            IdxLoad<IdxT, ITEMS>::load(idx + cb, lane, r);
         }
         if (in_lds)
             for (int i = lane; i < ncol; i += WAVE) slice[i] = ptr[jlo + i];
@@ -269,16 +277,52 @@ __global__ void gather_f64(const int32_t *__restrict__ inv, int64_t len, const d
 
 // ------------------------------------------------------------------------
 // Scatter product over one row panel.
-// Storage: blocks of 512 nonzeros.  A block holds nonzeros of one wave's rows,
-// in column order, from one workgroup's column range; logical nonzero
-// j*64 + lane sits at slot lane*8 + j, so each lane loads its 8 slots as
-// 16-byte vectors while each add instruction covers 64 consecutive nonzeros.
-// A slot holds (panel-local row << 16 | column - block column base) and the value.
+// Storage: blocks of 64*MV_ITEMS nonzeros.  A block holds nonzeros of one
+// wave's rows, in column order, from one workgroup's column range.  Logical
+// nonzero j*64 + lane sits at word slot ((j/4)*64 + lane)*4 + j%4 and at value
+// slot ((j/2)*64 + lane)*2 + j%2, so every load instruction reads one
+// contiguous span while each add instruction covers 64 consecutive nonzeros
+// (whose x entries share a few cache lines).  A word is
+// (panel-local row << 16 | column - block column base).  The streams are read
+// with non-temporal loads so they do not push x out of the caches.
 //   blocks : (column base, count) per block
 //   wg_blk : per workgroup, NW+1 offsets into blocks: wave w owns [wg_blk[w], wg_blk[w+1])
 //   partial: per-workgroup partial sums, panel_rows entries each
-// Dynamic LDS: panel_rows doubles.
+// The loop keeps two blocks of words/values and one block of x gathers in
+// flight.  Dynamic LDS: panel_rows doubles.
 // ------------------------------------------------------------------------
+constexpr int MV_ITEMS = 16;
+constexpr int MV_BLK = WAVE * MV_ITEMS;
+
+struct MvBlk {
+    uint32_t w[MV_ITEMS];
+    double a[MV_ITEMS];
+    int2 bd;
+};
+
+__device__ __forceinline__ void mv_load(MvBlk &B, const uint32_t *__restrict__ packed, const double *__restrict__ val,
+                                        const int2 *__restrict__ blocks, int b, int lane)
+{
+    B.bd = blocks[b];
+    const int64_t base = (int64_t)b * MV_BLK;
+#pragma unroll
+    for (int g = 0; g < MV_ITEMS / 4; ++g) {
+        const u32x4_t q =
+            __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(packed + base + (int64_t)(g * 64 + lane) * 4));
+        B.w[4 * g] = q.x;
+        B.w[4 * g + 1] = q.y;
+        B.w[4 * g + 2] = q.z;
+        B.w[4 * g + 3] = q.w;
+    }
+#pragma unroll
+    for (int g = 0; g < MV_ITEMS / 2; ++g) {
+        const f64x2_t d =
+            __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(val + base + (int64_t)(g * 64 + lane) * 2));
+        B.a[2 * g] = d.x;
+        B.a[2 * g + 1] = d.y;
+    }
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
     const uint32_t *__restrict__ packed, const double *__restrict__ val, const int2 *__restrict__ blocks,
@@ -293,62 +337,71 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
 
     const int32_t *wb = wg_blk + (int64_t)blockIdx.x * (NW + 1);
     const int b0 = wb[wave], b1 = wb[wave + 1];
-    uint32_t w[8];
-    double a[8];
-    int2 bd;
-    auto load = [&](int b) {
-        bd = blocks[b];
-        const int64_t base = (int64_t)b * 512 + lane * 8;
-        const uint4 q0 = *reinterpret_cast<const uint4 *>(packed + base);
-        const uint4 q1 = *reinterpret_cast<const uint4 *>(packed + base + 4);
-        w[0] = q0.x; w[1] = q0.y; w[2] = q0.z; w[3] = q0.w;
-        w[4] = q1.x; w[5] = q1.y; w[6] = q1.z; w[7] = q1.w;
+    MvBlk cur, nxt;
+    double xc[MV_ITEMS];
+    auto gather = [&](const MvBlk &B, double *xv) {
 #pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-            const double2 d = *reinterpret_cast<const double2 *>(val + base + j);
-            a[j] = d.x;
-            a[j + 1] = d.y;
-        }
+        for (int j = 0; j < MV_ITEMS; ++j)
+            xv[j] = (j * WAVE + lane < B.bd.y) ? x[B.bd.x + (int)(B.w[j] & 0xFFFFu)] : 0.0;
     };
-    if (b0 < b1) load(b0);
+    if (b0 < b1) {
+        mv_load(cur, packed, val, blocks, b0, lane);
+        if (b0 + 1 < b1) mv_load(nxt, packed, val, blocks, b0 + 1, lane);
+        gather(cur, xc);
+    }
     for (int b = b0; b < b1; ++b) {
-        const uint32_t cw[8] = {w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]};
-        const double ca[8] = {a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]};
-        const int2 cb = bd;
-        if (b + 1 < b1) load(b + 1);              // next block in flight while this one is added
+        double p[MV_ITEMS];
+        uint32_t row[MV_ITEMS];
+        const int lim = cur.bd.y - lane;          // item j is a nonzero when j*64 < lim
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (j * WAVE + lane < cb.y) {
-                const double p = ca[j] * x[cb.x + (int)(cw[j] & 0xFFFFu)];
-                __hip_atomic_fetch_add(&ypan[cw[j] >> 16], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+        for (int j = 0; j < MV_ITEMS; ++j) {
+            p[j] = cur.a[j] * xc[j];
+            row[j] = cur.w[j] >> 16;
         }
+        if (b + 1 < b1) {
+            cur = nxt;
+            if (b + 2 < b1) mv_load(nxt, packed, val, blocks, b + 2, lane);
+            gather(cur, xc);                      // x of the next block in flight
+        }
+#pragma unroll
+        for (int j = 0; j < MV_ITEMS; ++j)
+            if (j * WAVE < lim) __hip_atomic_fetch_add(&ypan[row[j]], p[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     double *out = partial + (int64_t)blockIdx.x * panel_rows;
     for (int i = tid; i < panel_rows; i += BLOCK) out[i] = ypan[i];
 }
 
-// y[caller row] = sum over the panel's workgroups of their partials, ascending.
+// y[caller row] = sum over the panel's workgroups of their partials.  Eight
+// lanes share a row: lane t adds workgroups t, t+8, t+16, ... in ascending
+// order, then the eight sums are combined by a fixed butterfly, so the order
+// of every addition is fixed.
 __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows,
                               const PanelDesc *__restrict__ panels, int64_t rows,
                               const int32_t *__restrict__ inv, double *__restrict__ y)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    const int p = (int)(r / panel_rows);
-    const int local = (int)(r - (int64_t)p * panel_rows);
-    const PanelDesc pd = panels[p];
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t r = g >> 3;
+    const int t = (int)(g & 7);
+    const bool live = r < rows;
     double s = 0.0;
-    const double *src = partial + (int64_t)pd.wg0 * panel_rows + local;
-    for (int w = 0; w < pd.nwg; ++w) s += src[(int64_t)w * panel_rows];
-    y[inv ? inv[r] : r] = s;
+    if (live) {
+        const int p = (int)(r / panel_rows);
+        const int local = (int)(r - (int64_t)p * panel_rows);
+        const PanelDesc pd = panels[p];
+        const double *src = partial + (int64_t)pd.wg0 * panel_rows + local;
+        for (int w = t; w < pd.nwg; w += 8) s += src[(int64_t)w * panel_rows];
+    }
+    s += __shfl_xor(s, 1, 8);
+    s += __shfl_xor(s, 2, 8);
+    s += __shfl_xor(s, 4, 8);
+    if (live && t == 0) y[inv ? inv[r] : r] = s;
 }
 
 constexpr int VTM_BLOCK = 1024;
 constexpr int VTM_ITEMS = 16;
 constexpr int VTM_SLICE_W = 256;
-constexpr int MV_BLOCK = 1024;
+constexpr int MV_BLOCK = 256;
 constexpr int LDS_BYTES = 160 * 1024;
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -379,7 +432,7 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k)
     (void)vdt;
     return std::min<int64_t>((LDS_BYTES - 256) / (8 * std::max<int32_t>(k, 1)), 65536);
 }
-int64_t mv_block_nnz() { return 512; }
+int64_t mv_block_nnz() { return MV_BLK; }
 int64_t mv_waves() { return MV_BLOCK / WAVE; }
 int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
 int64_t vtm_hot_rows_limit() { return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / 8; }
@@ -475,7 +528,7 @@ int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, in
     }
     {
         ProfScope ps(stream, "mv_reduce_f64");
-        hipLaunchKernelGGL(mv_reduce_f64, dim3(blocks_for(A.rows, 256)), dim3(256), 0, stream, A.scratch.partial,
+        hipLaunchKernelGGL(mv_reduce_f64, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream, A.scratch.partial,
                            (int)A.panel_rows, A.d_panels, A.rows, A.relabeled ? A.d_inv : nullptr, yo);
         int e = (int)hipGetLastError();
         if (e) return e;
