@@ -492,9 +492,12 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     // index and value arrays are padded with zeros to a whole number of chunks.
     const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), pad);
     {
-        std::vector<int32_t> p32((size_t)cols + 1);
+        // column starts, then a padding window so that the column-dot kernel
+        // can always read a fixed number of entries after any column
+        const int64_t win = vtm_slice_window();
+        std::vector<int32_t> p32((size_t)(cols + 1 + win), (int32_t)nnz);
         for (int64_t j = 0; j <= cols; ++j) p32[(size_t)j] = (int32_t)ptr[j];
-        if ((st = dev_alloc(*A, &A->d_ptr, cols + 1, "column starts"))) return st;
+        if ((st = dev_alloc(*A, &A->d_ptr, cols + 1 + win, "column starts"))) return st;
         if ((st = h2d(A->d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
     }
     // Logical-order internal rows (used to build the scatter storage), and the

@@ -113,6 +113,7 @@ int64_t mv_block_nnz();
 int64_t mv_waves();
 int64_t vtm_chunk_default();
 int64_t vtm_hot_rows_limit();
+int64_t vtm_slice_window();
 int device_cu_count(int device);
 
 // Profiling hooks (spw_profile.cpp).

@@ -44,46 +44,52 @@ constexpr int WAVE = 64;
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 
-// All lanes of the wave see each other's LDS writes after this point.
+// All lanes of the wave see each other's LDS writes after this point.  Only
+// the LDS counter is waited on, so loads of later data stay in flight (a wave's
+// LDS operations complete in issue order; the empty asm statements keep the
+// compiler from moving memory accesses across this point).
 __device__ __forceinline__ void wave_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);          // lgkmcnt(0); vmcnt and expcnt left open
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    asm volatile("" ::: "memory");
 }
 
-// Loads the N indices of one lane from an interleaved chunk (see the column-dot
-// kernel): group g of 16 bytes of lane l sits at (g*64 + l)*16 bytes.
-template <typename IdxT, int N> struct IdxLoad;
-template <int N> struct IdxLoad<uint16_t, N> {
-    __device__ __forceinline__ static void load(const uint16_t *base, int lane, int *r)
+// Raw index words of one lane, loaded from an interleaved chunk (see the
+// column-dot kernel): 16-byte group g of lane l sits at byte (g*64 + l)*16.
+template <typename IdxT, int N> struct IdxRaw;
+template <int N> struct IdxRaw<uint16_t, N> {    // N 2-byte indices in N/2 words
+    uint32_t w[N / 2];
+    __device__ __forceinline__ void load(const uint16_t *base, int lane)
     {
 #pragma unroll
         for (int g = 0; g < N / 8; ++g) {
             const u32x4_t q =
                 __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base + (int64_t)(g * 64 + lane) * 8));
-            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                r[8 * g + 2 * t] = (int)(w[t] & 0xFFFFu);
-                r[8 * g + 2 * t + 1] = (int)(w[t] >> 16);
-            }
+            w[4 * g] = q.x;
+            w[4 * g + 1] = q.y;
+            w[4 * g + 2] = q.z;
+            w[4 * g + 3] = q.w;
         }
     }
+    __device__ __forceinline__ int get(int i) const { return (int)((w[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu); }
 };
-template <int N> struct IdxLoad<int32_t, N> {
-    __device__ __forceinline__ static void load(const int32_t *base, int lane, int *r)
+template <int N> struct IdxRaw<int32_t, N> {     // N 4-byte indices
+    uint32_t w[N];
+    __device__ __forceinline__ void load(const int32_t *base, int lane)
     {
 #pragma unroll
         for (int g = 0; g < N / 4; ++g) {
             const u32x4_t q =
                 __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(base + (int64_t)(g * 64 + lane) * 4));
-            r[4 * g] = (int)q.x;
-            r[4 * g + 1] = (int)q.y;
-            r[4 * g + 2] = (int)q.z;
-            r[4 * g + 3] = (int)q.w;
+            w[4 * g] = q.x;
+            w[4 * g + 1] = q.y;
+            w[4 * g + 2] = q.z;
+            w[4 * g + 3] = q.w;
         }
     }
+    __device__ __forceinline__ int get(int i) const { return (int)w[i]; }
 };
 
 // ------------------------------------------------------------------------
@@ -119,17 +125,100 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 
 // ------------------------------------------------------------------------
 // Column dots, one wave per chunk of 64*ITEMS positions.
-//   ptr      : cols+1 column starts (absolute positions)
-//   idx, val : row (renumbered when relabeled) and value of every position
+//   ptr      : cols+1 column starts (absolute positions), followed by SLICE_W
+//              padding entries so a fixed-size window can always be read
+//   idx, val : row (renumbered when relabeled) and value of every position,
+//              interleaved inside each chunk: item i of lane l sits at value
+//              slot ((i/2)*64 + l)*2 + i%2 and at index slot ((i/G)*64 + l)*G
+//              + i%G (G indices per 16 bytes); tails are zero-padded
 //   cjlo/cjhi: column holding the chunk's first / last position
 //   v        : short input vector (renumbered); rows < vhot are read from LDS
 //   u        : long output; a column wholly inside the chunk is final here
 //   carry    : [2c] = part of the column entering chunk c from the left,
 //              [2c+1] = part of the column leaving chunk c to the right
 //              (a column crossing the whole chunk leaves its part in [2c])
+// Each wave handles the chunks c, c + stride, ...; the values, indices and
+// column-start window of the next chunk, and the column range of the one
+// after, are loaded while the current chunk is reduced.
 // Dynamic LDS: vhot doubles, then SLICE_W column starts per wave.  Columns
 // without nonzeros are written by zero_cols, not here.
 // ------------------------------------------------------------------------
+// Reduces one chunk whose products are in `prod` (lane-owned positions
+// p0 .. p0+ITEMS-1): cs[k] is the start of column jlo+k.  Inlined twice, with
+// cs in LDS or in global memory, so that each copy uses the matching loads.
+template <int ITEMS>
+__device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double *prod, int s, int e, int jlo,
+                                                 int ncol, int64_t c, int lane, double *__restrict__ u,
+                                                 double *__restrict__ carry)
+{
+    const int p0 = s + lane * ITEMS;
+    const int my_n = max(0, min(ITEMS, e - p0));
+    double head_sum = 0.0, run = 0.0;
+    int hk, k;
+    bool multi = false;
+    if (my_n > 0) {
+        int lo = 0, hi = ncol - 2;                // largest k with cs[k] <= p0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cs[mid] <= p0) lo = mid;
+            else hi = mid - 1;
+        }
+        k = lo;
+        int nxtc = cs[k + 1];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i < my_n) {
+                const int p = p0 + i;
+                if (p >= nxtc) {
+                    if (!multi) {
+                        head_sum = run;
+                        hk = k;
+                        multi = true;
+                    } else {
+                        u[jlo + k] = run;        // column wholly inside this lane
+                    }
+                    do {
+                        ++k;
+                        nxtc = cs[k + 1];
+                    } while (nxtc <= p);
+                    run = 0.0;
+                }
+                run += prod[i];
+            }
+        }
+        if (!multi) hk = k;
+    } else {
+        k = -2 - lane;                            // inactive lane: a key no one shares
+        hk = -2 - lane;
+    }
+
+    const SegPair o = wave_seg_scan(SegPair{run, k});
+    const double prev_s = __shfl_up(o.s, 1, WAVE);
+    const int prev_k = __shfl_up(o.k, 1, WAVE);
+    const int next_hk = __shfl_down(hk, 1, WAVE);
+    if (my_n > 0) {
+        auto emit = [&](int kk, double value) {
+            const bool before = cs[kk] < s, after = cs[kk + 1] > e;
+            if (before) carry[2 * c] = value;
+            else if (after) carry[2 * c + 1] = value;
+            else u[jlo + kk] = value;
+        };
+        if (multi) {
+            // the lane's first column ends inside it: add what earlier lanes hold
+            double tot = head_sum;
+            if (lane > 0 && prev_k == hk) tot = prev_s + head_sum;
+            emit(hk, tot);
+        }
+        if (lane == WAVE - 1 || next_hk != k) emit(k, o.s);
+    }
+}
+
+template <typename IdxT, int ITEMS, int SLW> struct VtmChunk {
+    double a[ITEMS];
+    IdxRaw<IdxT, ITEMS> r;
+    int32_t sl[SLW];
+};
+
 template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT>
 __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
     const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const double *__restrict__ val,
@@ -138,111 +227,90 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
 {
     constexpr int NW = BLOCK / WAVE;
     constexpr int WCH = WAVE * ITEMS;
+    constexpr int SLW = SLICE_W / WAVE;
     extern __shared__ double lds[];
     double *vh = lds;
-    int32_t *slice = reinterpret_cast<int32_t *>(lds + vhot) + (threadIdx.x / WAVE) * SLICE_W;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    int32_t *slice = reinterpret_cast<int32_t *>(lds + vhot) + wave * SLICE_W;
     const int lane = threadIdx.x & (WAVE - 1);
 
     for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
     __syncthreads();
 
     const int64_t stride = (int64_t)gridDim.x * NW;
-    for (int64_t c = (int64_t)blockIdx.x * NW + threadIdx.x / WAVE; c < nchunks; c += stride) {
-        const int s = (int)(c * WCH);
+    int64_t c = (int64_t)blockIdx.x * NW + wave;
+    if (c >= nchunks) return;
+
+    // Two chunk buffers used alternately (no register copies, so no wait for
+    // data still in flight): while one chunk is reduced, the next one's
+    // values, indices and column-start window are being fetched.
+    VtmChunk<IdxT, ITEMS, SLW> A, B;
+    auto load_chunk = [&](VtmChunk<IdxT, ITEMS, SLW> &C, int64_t cc, int jl) {
+        const int64_t cb = cc * WCH;
+#pragma unroll
+        for (int q = 0; q < ITEMS / 2; ++q) {
+            const f64x2_t w = __builtin_nontemporal_load(
+                reinterpret_cast<const f64x2_t *>(val + cb + (int64_t)(q * WAVE + lane) * 2));
+            C.a[2 * q] = w.x;
+            C.a[2 * q + 1] = w.y;
+        }
+        C.r.load(idx + cb, lane);
+#pragma unroll
+        for (int t = 0; t < SLW; ++t) C.sl[t] = ptr[jl + lane + t * WAVE];
+    };
+    // Reduces chunk cc held in C, after issuing the loads of chunk cn into N
+    // (when cn < nchunks).  jlo/jhi describe cc, jln describes cn.
+    auto step = [&](VtmChunk<IdxT, ITEMS, SLW> &C, VtmChunk<IdxT, ITEMS, SLW> &N, int64_t cc, int jlo, int jhi,
+                    int64_t cn, int jln) {
+        const int s = (int)(cc * WCH);
         const int e = (int)min((int64_t)s + WCH, nnz);
-        const int jlo = cjlo[c], jhi = cjhi[c];
         const int ncol = jhi - jlo + 2;           // starts of columns jlo .. jhi+1
         const bool in_lds = ncol <= SLICE_W;
-        const int p0 = s + lane * ITEMS;
-        const int my_n = max(0, min(ITEMS, e - p0));
-
-        // Storage inside a chunk is interleaved so that each load instruction
-        // reads one contiguous span: item i of lane l sits at value slot
-        // ((i/2)*64 + l)*2 + i%2 and at index slot ((i/G)*64 + l)*G + i%G,
-        // with G = 16 / sizeof(index).  Tails are zero-padded.
-        double a[ITEMS];
-        int r[ITEMS];
-        {
-            const int64_t cb = c * WCH;
 #pragma unroll
-            for (int q = 0; q < ITEMS / 2; ++q) {
-                const f64x2_t w = __builtin_nontemporal_load(
-                    reinterpret_cast<const f64x2_t *>(val + cb + (int64_t)(q * WAVE + lane) * 2));
-                a[2 * q] = w.x;
-                a[2 * q + 1] = w.y;
-            }
-            IdxLoad<IdxT, ITEMS>::load(idx + cb, lane, r);
-        }
-        if (in_lds)
-            for (int i = lane; i < ncol; i += WAVE) slice[i] = ptr[jlo + i];
+        for (int t = 0; t < SLW; ++t) slice[lane + t * WAVE] = C.sl[t];
         double prod[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            const int ri = r[i];
-            prod[i] = a[i] * (ri < vhot ? vh[ri] : v[ri]);
+            // the LDS read and the global read stay separate instructions (a
+            // selected pointer would become a flat load, which waits for every
+            // outstanding load)
+            const int ri = C.r.get(i);
+            const double lv = vh[min(ri, vhot - 1)];
+            double gv = 0.0;
+            if (ri >= vhot) gv = v[ri];
+            prod[i] = C.a[i] * (ri < vhot ? lv : gv);
         }
+        // The gathers must land before the next chunk's loads are issued: the
+        // load counter is in order, so waiting for them later would also wait
+        // for the prefetch.
+        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
+        if (cn < nchunks) load_chunk(N, cn, jln);
         wave_sync();
-        const int32_t *cs = in_lds ? slice : ptr + jlo;
+        if (in_lds) vtm_reduce_chunk<ITEMS>(slice, prod, s, e, jlo, ncol, cc, lane, u, carry);
+        else vtm_reduce_chunk<ITEMS>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, u, carry);
+        wave_sync();                              // slice reads done before it is rewritten
+    };
 
-        double head_sum = 0.0, run = 0.0;
-        int hk, k;
-        bool multi = false;
-        if (my_n > 0) {
-            int lo = 0, hi = ncol - 2;            // largest k with cs[k] <= p0
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (cs[mid] <= p0) lo = mid;
-                else hi = mid - 1;
-            }
-            k = lo;
-            int nxt = cs[k + 1];
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                if (i < my_n) {
-                    const int p = p0 + i;
-                    if (p >= nxt) {
-                        if (!multi) {
-                            head_sum = run;
-                            hk = k;
-                            multi = true;
-                        } else {
-                            u[jlo + k] = run;    // column wholly inside this lane
-                        }
-                        do {
-                            ++k;
-                            nxt = cs[k + 1];
-                        } while (nxt <= p);
-                        run = 0.0;
-                    }
-                    run += prod[i];
-                }
-            }
-            if (!multi) hk = k;
-        } else {
-            k = -2 - lane;                        // inactive lane: a key no one shares
-            hk = -2 - lane;
+    // chunk sequence c, c + stride, ...; column ranges are loaded one step ahead
+    int jlo0 = cjlo[c], jhi0 = cjhi[c];
+    load_chunk(A, c, jlo0);
+    for (;;) {
+        const int64_t c1 = c + stride;
+        int jlo1 = 0, jhi1 = 0;
+        if (c1 < nchunks) {
+            jlo1 = cjlo[c1];
+            jhi1 = cjhi[c1];
         }
-
-        const SegPair o = wave_seg_scan(SegPair{run, k});
-        const double prev_s = __shfl_up(o.s, 1, WAVE);
-        const int prev_k = __shfl_up(o.k, 1, WAVE);
-        const int next_hk = __shfl_down(hk, 1, WAVE);
-        if (my_n > 0) {
-            auto emit = [&](int kk, double value) {
-                const bool before = cs[kk] < s, after = cs[kk + 1] > e;
-                if (before) carry[2 * c] = value;
-                else if (after) carry[2 * c + 1] = value;
-                else u[jlo + kk] = value;
-            };
-            if (multi) {
-                // the lane's first column ends inside it: add what earlier lanes hold
-                double tot = head_sum;
-                if (lane > 0 && prev_k == hk) tot = prev_s + head_sum;
-                emit(hk, tot);
-            }
-            if (lane == WAVE - 1 || next_hk != k) emit(k, o.s);
+        step(A, B, c, jlo0, jhi0, c1, jlo1);
+        if (c1 >= nchunks) break;
+        const int64_t c2 = c1 + stride;
+        if (c2 < nchunks) {
+            jlo0 = cjlo[c2];
+            jhi0 = cjhi[c2];
         }
-        wave_sync();                              // slice reads done before the next chunk
+        step(B, A, c1, jlo1, jhi1, c2, jlo0);
+        if (c2 >= nchunks) break;
+        c = c2;
     }
 }
 
@@ -337,35 +405,52 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
 
     const int32_t *wb = wg_blk + (int64_t)blockIdx.x * (NW + 1);
     const int b0 = wb[wave], b1 = wb[wave + 1];
-    MvBlk cur, nxt;
-    double xc[MV_ITEMS];
+    // Two block buffers used alternately (no register copies, so no wait for
+    // data still in flight): while block b is added, the x entries of block
+    // b+1 and the words/values of block b+2 are being fetched.
+    MvBlk B0, B1;
+    double x0[MV_ITEMS], x1[MV_ITEMS];
+    // padding slots hold word 0, so their gather reads x[column base]: no branch
     auto gather = [&](const MvBlk &B, double *xv) {
 #pragma unroll
-        for (int j = 0; j < MV_ITEMS; ++j)
-            xv[j] = (j * WAVE + lane < B.bd.y) ? x[B.bd.x + (int)(B.w[j] & 0xFFFFu)] : 0.0;
+        for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[B.bd.x + (int)(B.w[j] & 0xFFFFu)];
     };
-    if (b0 < b1) {
-        mv_load(cur, packed, val, blocks, b0, lane);
-        if (b0 + 1 < b1) mv_load(nxt, packed, val, blocks, b0 + 1, lane);
-        gather(cur, xc);
-    }
-    for (int b = b0; b < b1; ++b) {
-        double p[MV_ITEMS];
-        uint32_t row[MV_ITEMS];
-        const int lim = cur.bd.y - lane;          // item j is a nonzero when j*64 < lim
+    auto add_block = [&](const MvBlk &B, const double *xv, double *p, uint32_t *row) {
 #pragma unroll
         for (int j = 0; j < MV_ITEMS; ++j) {
-            p[j] = cur.a[j] * xc[j];
-            row[j] = cur.w[j] >> 16;
+            p[j] = B.a[j] * xv[j];
+            row[j] = B.w[j] >> 16;
         }
-        if (b + 1 < b1) {
-            cur = nxt;
-            if (b + 2 < b1) mv_load(nxt, packed, val, blocks, b + 2, lane);
-            gather(cur, xc);                      // x of the next block in flight
-        }
+    };
+    auto commit = [&](int count, const double *p, const uint32_t *row) {
+        const int lim = count - lane;             // item j is a nonzero when j*64 < lim
 #pragma unroll
         for (int j = 0; j < MV_ITEMS; ++j)
             if (j * WAVE < lim) __hip_atomic_fetch_add(&ypan[row[j]], p[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    if (b0 < b1) {
+        mv_load(B0, packed, val, blocks, b0, lane);
+        gather(B0, x0);
+        if (b0 + 1 < b1) mv_load(B1, packed, val, blocks, b0 + 1, lane);
+    }
+    for (int b = b0; b < b1; b += 2) {
+        double p[MV_ITEMS];
+        uint32_t row[MV_ITEMS];
+        add_block(B0, x0, p, row);
+        int cnt = B0.bd.y;
+        if (b + 1 < b1) {
+            gather(B1, x1);
+            if (b + 2 < b1) mv_load(B0, packed, val, blocks, b + 2, lane);
+        }
+        commit(cnt, p, row);
+        if (b + 1 >= b1) break;
+        add_block(B1, x1, p, row);
+        cnt = B1.bd.y;
+        if (b + 2 < b1) {
+            gather(B0, x0);
+            if (b + 3 < b1) mv_load(B1, packed, val, blocks, b + 3, lane);
+        }
+        commit(cnt, p, row);
     }
     __syncthreads();
     double *out = partial + (int64_t)blockIdx.x * panel_rows;
@@ -398,7 +483,7 @@ __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows
     if (live && t == 0) y[inv ? inv[r] : r] = s;
 }
 
-constexpr int VTM_BLOCK = 1024;
+constexpr int VTM_BLOCK = 512;
 constexpr int VTM_ITEMS = 16;
 constexpr int VTM_SLICE_W = 256;
 constexpr int MV_BLOCK = 256;
@@ -435,6 +520,7 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k)
 int64_t mv_block_nnz() { return MV_BLK; }
 int64_t mv_waves() { return MV_BLOCK / WAVE; }
 int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
+int64_t vtm_slice_window() { return VTM_SLICE_W; }
 int64_t vtm_hot_rows_limit() { return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / 8; }
 
 int device_cu_count(int device)
