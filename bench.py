@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS section")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
     ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
@@ -243,6 +244,12 @@ def main():
         T.close()
         del yt, ut
 
+    if not args.no_batch:
+        M.close()
+        del xd, vd, yd, ud
+        torch.cuda.empty_cache()
+        extra["batched"] = bench_batched(args)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
@@ -258,7 +265,74 @@ def main():
                       "peak_GBps": HBM_PEAK_GBS, "pct_of_peak": round(100 * value / HBM_PEAK_GBS, 2)},
            "roofline": roofline, "cpu_baseline": cpu, "extra": extra}
     print(json.dumps(out), flush=True)
+    if args.no_batch:
+        M.close()
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batched(args):
+    """Multi-RHS blocks on the batching matrix (m=20,000, n=5e6, ~5e7 nonzeros):
+    one fused pass for k right-hand sides against k plain single-vector calls,
+    binary64 and binary32 vectors, both directions."""
+    import torch
+    import synth
+    from paper_1812_00904_amd import SPW_CSC, SpwMatrix
+    A = synth.config_matrix("c2", scale=args.scale)
+    M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    res = {"workload": "wide CSC m=%d n=%d nnz=%d (Zipf(1.1) lengths + 100 half-dense columns, Zipf(0.8) rows)"
+                       % (A.m, A.n, A.nnz), "rows": []}
+    for dtype, sx in ((torch.float64, 8), (torch.float32, 4)):
+        for k in (1, 4, 16, 64):
+            X = torch.rand((A.n, k), dtype=dtype, device="cuda") * 2 - 1
+            V = torch.rand((A.m, k), dtype=dtype, device="cuda") * 2 - 1
+            Y = torch.empty((A.m, k), dtype=dtype, device="cuda")
+            U = torch.empty((A.n, k), dtype=dtype, device="cuda")
+            xs = [X[:, c].contiguous() for c in range(k)]
+            vs = [V[:, c].contiguous() for c in range(k)]
+            ys = [torch.empty(A.m, dtype=dtype, device="cuda") for _ in range(k)]
+            us = [torch.empty(A.n, dtype=dtype, device="cuda") for _ in range(k)]
+            reps = 3
+            t_mv = _time(lambda: M.mv_batch(X, Y), reps)
+            t_vtm = _time(lambda: M.vtm_batch(V, U), reps)
+
+            def plain_mv():
+                for c in range(k):
+                    M.mv(xs[c], ys[c])
+
+            def plain_vtm():
+                for c in range(k):
+                    M.vtm(vs[c], us[c])
+            t_pmv = _time(plain_mv, reps)
+            t_pvtm = _time(plain_vtm, reps)
+            by = model_bytes(A.m, A.n, A.nnz, k=k, sx=sx)
+            by1 = model_bytes(A.m, A.n, A.nnz, k=1, sx=sx)
+            row = {"dtype": "f64" if sx == 8 else "f32", "k": k,
+                   "mv_batch_ms": round(t_mv, 4), "vtm_batch_ms": round(t_vtm, 4),
+                   "mv_plain_k_calls_ms": round(t_pmv, 4), "vtm_plain_k_calls_ms": round(t_pvtm, 4),
+                   "mv_batch_GBps": round(by / (t_mv * 1e-3) / 1e9, 1),
+                   "vtm_batch_GBps": round(by / (t_vtm * 1e-3) / 1e9, 1),
+                   "mv_plain_GBps": round(k * by1 / (t_pmv * 1e-3) / 1e9, 1),
+                   "vtm_plain_GBps": round(k * by1 / (t_pvtm * 1e-3) / 1e9, 1),
+                   "mv_speedup": round(t_pmv / t_mv, 2), "vtm_speedup": round(t_pvtm / t_vtm, 2)}
+            res["rows"].append(row)
+            print("[bench] batched %s" % row, file=sys.stderr, flush=True)
+            del X, V, Y, U, xs, vs, ys, us
+            torch.cuda.empty_cache()
     M.close()
+    return res
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str):

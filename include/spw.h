@@ -64,15 +64,21 @@ typedef struct spw_matrix_s *spw_matrix;
  * or call spw_create_opts_default.  NULL opts means defaults.
  *   value_storage : F64 (default), F32 or BF16 -- the stored nonzero values are
  *                   rounded once from the given binary64 values, to nearest even.
- *   chunk_nnz     : nonzeros per transpose-product chunk (0 = automatic; must be
- *                   a multiple of 512 when given).
+ *   chunk_nnz     : nonzeros per column-dot chunk (0 = automatic; this build
+ *                   supports only its default, 1024).
  *   relabel       : -1 automatic, 0 off, 1 on.  On: rows are renumbered inside
  *                   the library by descending nonzero count, so the most used
  *                   entries of the short vector share cache lines; results are
  *                   returned in the caller's numbering.
  *   validate      : 1 (default) checks the arrays in O(nnz); 0 trusts them.
  *   panel_rows    : rows per on-chip accumulation panel for A x (0 = automatic).
- *   device        : HIP device ordinal, -1 = the current device. */
+ *   device        : HIP device ordinal, -1 = the current device.
+ *   transpose     : -1 (default) or 1 also keeps the transpose, which the
+ *                   multi-RHS products of the long-to-short direction (CSC A x,
+ *                   CSR v^T A) use for k > 4 and the binary32-vector forms of
+ *                   that direction need; 0 saves that memory: binary64 blocks
+ *                   then run one scatter pass per column and binary32 ones
+ *                   return SPW_ERR_UNSUPPORTED. */
 typedef struct {
     uint32_t struct_size;
     spw_dtype value_storage;
@@ -81,7 +87,8 @@ typedef struct {
     int32_t validate;
     int32_t panel_rows;
     int32_t device;
-    int32_t reserved[8];
+    int32_t transpose;
+    int32_t reserved[7];
 } spw_create_opts;
 
 /* Read-only description of a created matrix. */
@@ -102,6 +109,8 @@ typedef struct {
     int32_t relabeled;            /* rows renumbered by frequency */
     int32_t device;
     int64_t device_bytes;         /* device memory held by the handle */
+    int32_t has_transpose;        /* the transpose is kept (see spw_create_opts.transpose) */
+    int32_t reserved;
 } spw_matrix_info;
 
 /* ---------------------------------------------------------------- matrices */

@@ -149,10 +149,92 @@ struct DeviceGuard {
     }
 };
 
+// Column-dot storage of a rows x cols CSC matrix (ptr over columns, rows[]
+// already in the numbering the kernel will use).
+spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, const int64_t *ptr,
+                        const int32_t *rowi, const double *val)
+{
+    const int64_t nnz = ptr[cols];
+    C.rows = rows;
+    C.cols = cols;
+    C.nnz = nnz;
+    C.idx_kind = rows <= 65536 ? IdxKind::U16 : IdxKind::I32;
+    spw_status st;
+    const int64_t WCH = vtm_chunk_default(), ITEMS = WCH / 64;
+    const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), 4096);
+    {
+        // column starts, then a padding window so that the column-dot kernel
+        // can always read a fixed number of entries after any column
+        const int64_t win = vtm_slice_window();
+        std::vector<int32_t> p32((size_t)(cols + 1 + win), (int32_t)nnz);
+        for (int64_t j = 0; j <= cols; ++j) p32[(size_t)j] = (int32_t)ptr[j];
+        if ((st = dev_alloc(A, &C.d_ptr, cols + 1 + win, "column starts"))) return st;
+        if ((st = h2d(C.d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
+    }
+    // Chunk-interleaved copies: inside each chunk of W = 64*I positions, item i
+    // of lane l (position l*I + i) is stored at ((i/G)*64 + l)*G + i%G, G being
+    // the number of elements in 16 bytes.
+    auto ilv = [&](int64_t p, int64_t G) -> int64_t {
+        const int64_t o = p % WCH, cb = p - o, ln = o / ITEMS, i = o % ITEMS;
+        return cb + ((i / G) * 64 + ln) * G + i % G;
+    };
+    if (C.idx_kind == IdxKind::U16) {
+        std::vector<uint16_t> ii((size_t)zpad, 0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 8)] = (uint16_t)rowi[p];
+        });
+        uint16_t *d = nullptr;
+        if ((st = dev_alloc(A, &d, zpad, "row indices"))) return st;
+        if ((st = h2d(d, ii.data(), (size_t)zpad * 2, "row indices"))) return st;
+        C.d_idx = d;
+    } else {
+        std::vector<int32_t> ii((size_t)zpad, 0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 4)] = rowi[p];
+        });
+        int32_t *d = nullptr;
+        if ((st = dev_alloc(A, &d, zpad, "row indices"))) return st;
+        if ((st = h2d(d, ii.data(), (size_t)zpad * 4, "row indices"))) return st;
+        C.d_idx = d;
+    }
+    {
+        std::vector<double> vi((size_t)zpad, 0.0);
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) vi[(size_t)ilv(p, 2)] = val[p];
+        });
+        double *d = nullptr;
+        if ((st = dev_alloc(A, &d, zpad, "values"))) return st;
+        if ((st = h2d(d, vi.data(), (size_t)zpad * 8, "values"))) return st;
+        C.d_val = d;
+    }
+    build_zone_plan(cols, ptr, WCH, C.zp);
+    C.n_zones = (int64_t)C.zp.zone_col.size();
+    if ((st = dev_alloc(A, &C.d_cjlo, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;
+    if ((st = h2d(C.d_cjlo, C.zp.jlo.data(), C.zp.jlo.size() * 4, "chunk table"))) return st;
+    if ((st = dev_alloc(A, &C.d_cjhi, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;
+    if ((st = h2d(C.d_cjhi, C.zp.jhi.data(), C.zp.jhi.size() * 4, "chunk table"))) return st;
+    {
+        std::vector<int32_t> empty;
+        for (int64_t j = 0; j < cols; ++j)
+            if (ptr[j + 1] == ptr[j]) empty.push_back((int32_t)j);
+        C.n_empty = (int64_t)empty.size();
+        if ((st = dev_alloc(A, &C.d_empty, std::max<int64_t>(C.n_empty, 1), "empty columns"))) return st;
+        if ((st = h2d(C.d_empty, empty.data(), empty.size() * 4, "empty columns"))) return st;
+    }
+    if ((st = dev_alloc(A, &C.d_zone_col, std::max<int64_t>(C.n_zones, 1), "zone table"))) return st;
+    if ((st = dev_alloc(A, &C.d_zone_first, std::max<int64_t>(C.n_zones, 1), "zone table"))) return st;
+    if ((st = dev_alloc(A, &C.d_zone_last, std::max<int64_t>(C.n_zones, 1), "zone table"))) return st;
+    if ((st = h2d(C.d_zone_col, C.zp.zone_col.data(), (size_t)C.n_zones * 4, "zone table"))) return st;
+    if ((st = h2d(C.d_zone_first, C.zp.zone_first.data(), (size_t)C.n_zones * 4, "zone table"))) return st;
+    if ((st = h2d(C.d_zone_last, C.zp.zone_last.data(), (size_t)C.n_zones * 4, "zone table"))) return st;
+    C.built = true;
+    return SPW_OK;
+}
+
 // Row panels, wave row sets and blocks of the scatter product (see
-// spw_internal.h and the scatter kernel).  idx_int holds the internal
+// spw_internal.h and the scatter kernel).  rowi holds the internal
 // (renumbered) rows.
-spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx_int, const double *val,
+spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *rowi, const double *val,
                             int64_t panel_rows_opt)
 {
     const int64_t rows = A.rows, cols = A.cols, nnz = A.nnz;
@@ -170,10 +252,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const void *idx
     const int64_t P = (rows + R - 1) / R;
     A.panel_rows = R;
     A.n_panels = P;
-    const bool u16 = A.idx_kind == IdxKind::U16;
-    auto row_of = [&](int64_t p) -> int64_t {
-        return u16 ? (int64_t)((const uint16_t *)idx_int)[p] : (int64_t)((const int32_t *)idx_int)[p];
-    };
+    auto row_of = [&](int64_t p) -> int64_t { return (int64_t)rowi[p]; };
 
     // 1. Column-major order inside each panel: (panel, column) counts, then a
     //    stable scatter of the source positions.
@@ -364,10 +443,9 @@ spw_status alloc_scratch(spw_matrix_s &A, int32_t k)
     spw_status st;
     if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows * k, "partial sums")))
         return st;
-    if ((st = dev_alloc(A, &A.scratch.carry, std::max<int64_t>(2 * A.zp.n_chunks, 1) * k, "carries"))) return st;
-    double *vp = nullptr;
-    if ((st = dev_alloc(A, &vp, std::max<int64_t>(A.rows, 1) * k, "renumbered vector"))) return st;
-    A.scratch.vperm = vp;
+    const int64_t nch = std::max<int64_t>(A.cd.zp.n_chunks, A.cdt.zp.n_chunks);
+    if ((st = dev_alloc(A, &A.scratch.carry, std::max<int64_t>(2 * nch, 1) * k, "carries"))) return st;
+    if ((st = dev_alloc(A, &A.scratch.vperm, std::max<int64_t>(A.rows, 1) * k, "renumbered vector"))) return st;
     A.scratch.kcap = k;
     return SPW_OK;
 }
@@ -409,6 +487,7 @@ spw_status spw_create_opts_default(spw_create_opts *o)
     o->validate = 1;
     o->panel_rows = 0;
     o->device = -1;
+    o->transpose = -1;
     return SPW_OK;
 }
 
@@ -457,7 +536,6 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     A->rows = rows;
     A->cols = cols;
     (void)hipGetDevice(&A->device);
-    A->idx_kind = rows <= 65536 ? IdxKind::U16 : IdxKind::I32;
     A->relabeled = opts.relabel < 0 ? (rows > 4096 ? 1 : 0) : (opts.relabel ? 1 : 0);
     if (rows == 0) A->relabeled = 0;
 
@@ -487,97 +565,38 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
         if ((st = dev_alloc(*A, &A->d_inv, rows, "row renumbering"))) return st;
         if ((st = h2d(A->d_inv, inv.data(), (size_t)rows * 4, "row renumbering"))) return st;
     }
+    std::vector<int32_t> rowi((size_t)std::max<int64_t>(nnz, 1), 0);
+    {
+        const bool rl = A->relabeled != 0;
+        parallel_for(nnz, [&](int64_t a, int64_t b) {
+            for (int64_t p = a; p < b; ++p) rowi[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
+        });
+    }
+    if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val))) return st;
 
-    // Column-dot storage: int32 column starts, 2- or 4-byte rows, values; the
-    // index and value arrays are padded with zeros to a whole number of chunks.
-    const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), pad);
-    {
-        // column starts, then a padding window so that the column-dot kernel
-        // can always read a fixed number of entries after any column
-        const int64_t win = vtm_slice_window();
-        std::vector<int32_t> p32((size_t)(cols + 1 + win), (int32_t)nnz);
-        for (int64_t j = 0; j <= cols; ++j) p32[(size_t)j] = (int32_t)ptr[j];
-        if ((st = dev_alloc(*A, &A->d_ptr, cols + 1 + win, "column starts"))) return st;
-        if ((st = h2d(A->d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
+    // The transpose (caller's numbering), used by the multi-RHS scatter
+    // products: its column dots are the rows of B.
+    if (opts.transpose != 0 && nnz > 0) {
+        std::vector<int64_t> tptr((size_t)rows + 1, 0);
+        for (int64_t p = 0; p < nnz; ++p) tptr[(size_t)idx[p] + 1]++;
+        for (int64_t r = 0; r < rows; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
+        std::vector<int32_t> tidx((size_t)nnz);
+        std::vector<double> tval((size_t)nnz);
+        {
+            std::vector<int64_t> cur(tptr.begin(), tptr.end() - 1);
+            for (int64_t j = 0; j < cols; ++j)
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
+                    const int64_t dst = cur[(size_t)idx[p]]++;
+                    tidx[(size_t)dst] = (int32_t)j;
+                    tval[(size_t)dst] = val[p];
+                }
+        }
+        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data()))) return st;
     }
-    // Logical-order internal rows (used to build the scatter storage), and the
-    // chunk-interleaved copies the column-dot kernel reads: inside each chunk of
-    // W = 64*I positions, item i of lane l (position l*I + i) is stored at
-    // ((i/G)*64 + l)*G + i%G, G being the number of elements in 16 bytes.
-    const int64_t WCH = vtm_chunk_default(), ITEMS = WCH / 64;
-    auto ilv = [&](int64_t p, int64_t G) -> int64_t {
-        const int64_t o = p % WCH, cb = p - o, ln = o / ITEMS, i = o % ITEMS;
-        return cb + ((i / G) * 64 + ln) * G + i % G;
-    };
-    std::vector<uint16_t> i16;
-    std::vector<int32_t> i32;
-    const void *idx_int = nullptr;
-    const bool rl = A->relabeled != 0;
-    if (A->idx_kind == IdxKind::U16) {
-        i16.assign((size_t)std::max<int64_t>(nnz, 1), 0);
-        parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) i16[(size_t)p] = (uint16_t)(rl ? rank[(size_t)idx[p]] : idx[p]);
-        });
-        std::vector<uint16_t> ii((size_t)zpad, 0);
-        parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 8)] = i16[(size_t)p];
-        });
-        uint16_t *d = nullptr;
-        if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
-        if ((st = h2d(d, ii.data(), (size_t)zpad * 2, "row indices"))) return st;
-        A->d_idx = d;
-        idx_int = i16.data();
-    } else {
-        i32.assign((size_t)std::max<int64_t>(nnz, 1), 0);
-        parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) i32[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
-        });
-        std::vector<int32_t> ii((size_t)zpad, 0);
-        parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) ii[(size_t)ilv(p, 4)] = i32[(size_t)p];
-        });
-        int32_t *d = nullptr;
-        if ((st = dev_alloc(*A, &d, zpad, "row indices"))) return st;
-        if ((st = h2d(d, ii.data(), (size_t)zpad * 4, "row indices"))) return st;
-        A->d_idx = d;
-        idx_int = i32.data();
-    }
-    {
-        std::vector<double> vi((size_t)zpad, 0.0);
-        parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) vi[(size_t)ilv(p, 2)] = val[p];
-        });
-        double *d = nullptr;
-        if ((st = dev_alloc(*A, &d, zpad, "values"))) return st;
-        if ((st = h2d(d, vi.data(), (size_t)zpad * 8, "values"))) return st;
-        A->d_val = d;
-    }
-
-    // Zone plan of the column dots.
-    build_zone_plan(cols, ptr, chunk, A->zp);
-    A->n_zones = (int64_t)A->zp.zone_col.size();
-    if ((st = dev_alloc(*A, &A->d_cjlo, std::max<int64_t>(A->zp.n_chunks, 1), "chunk table"))) return st;
-    if ((st = h2d(A->d_cjlo, A->zp.jlo.data(), A->zp.jlo.size() * 4, "chunk table"))) return st;
-    if ((st = dev_alloc(*A, &A->d_cjhi, std::max<int64_t>(A->zp.n_chunks, 1), "chunk table"))) return st;
-    if ((st = h2d(A->d_cjhi, A->zp.jhi.data(), A->zp.jhi.size() * 4, "chunk table"))) return st;
-    {
-        std::vector<int32_t> empty;
-        for (int64_t j = 0; j < cols; ++j)
-            if (ptr[j + 1] == ptr[j]) empty.push_back((int32_t)j);
-        A->n_empty = (int64_t)empty.size();
-        if ((st = dev_alloc(*A, &A->d_empty, std::max<int64_t>(A->n_empty, 1), "empty columns"))) return st;
-        if ((st = h2d(A->d_empty, empty.data(), empty.size() * 4, "empty columns"))) return st;
-    }
-    if ((st = dev_alloc(*A, &A->d_zone_col, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
-    if ((st = dev_alloc(*A, &A->d_zone_first, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
-    if ((st = dev_alloc(*A, &A->d_zone_last, std::max<int64_t>(A->n_zones, 1), "zone table"))) return st;
-    if ((st = h2d(A->d_zone_col, A->zp.zone_col.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
-    if ((st = h2d(A->d_zone_first, A->zp.zone_first.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
-    if ((st = h2d(A->d_zone_last, A->zp.zone_last.data(), (size_t)A->n_zones * 4, "zone table"))) return st;
 
     // Scatter-product storage.
     if (rows > 0) {
-        if ((st = build_mv_storage(*A, ptr, idx_int, val, opts.panel_rows))) return st;
+        if ((st = build_mv_storage(*A, ptr, rowi.data(), val, opts.panel_rows))) return st;
     }
     if ((st = alloc_scratch(*A, 1))) return st;
     if (hipDeviceSynchronize() != hipSuccess) {
@@ -613,13 +632,14 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *o)
     o->nnz = A->nnz;
     o->inner_rows = A->rows;
     o->inner_cols = A->cols;
-    o->chunk_nnz = A->zp.chunk;
-    o->n_chunks = A->zp.n_chunks;
-    o->n_zones = A->n_zones;
+    o->chunk_nnz = A->cd.zp.chunk;
+    o->n_chunks = A->cd.zp.n_chunks;
+    o->n_zones = A->cd.n_zones;
     o->n_panels = A->n_panels;
     o->panel_rows = A->panel_rows;
     o->mv_workgroups = A->mv_wgs;
-    o->index_bytes = A->idx_kind == IdxKind::U16 ? 2 : 4;
+    o->index_bytes = A->cd.idx_kind == IdxKind::U16 ? 2 : 4;
+    o->has_transpose = A->cdt.built ? 1 : 0;
     o->relabeled = A->relabeled;
     o->device = A->device;
     o->device_bytes = A->device_bytes;
@@ -643,8 +663,26 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     if (dg.st) return dg.st;
     spw_status st = alloc_scratch(*A, k);
     if (st) return st;
-    const int e = scatter ? launch_mv(*A, vdt, k, in, ldi, out, ldo, stream)
-                          : launch_vtm(*A, vdt, k, in, ldi, out, ldo, stream);
+    int e;
+    if (k == 1 && ldi == 1 && ldo == 1 && vdt == SPW_F64) {
+        e = scatter ? launch_mv(*A, vdt, k, in, ldi, out, ldo, stream) : launch_vtm(*A, vdt, k, in, ldi, out, ldo, stream);
+    } else if (scatter && vdt == SPW_F64 && (k <= 4 || !A->cdt.built)) {
+        // few binary64 right-hand sides: one scatter pass per column (reads A
+        // k times, x once per column) beats gathering rows of X per nonzero
+        e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
+    } else if (scatter) {
+        // k right-hand sides in one pass: column dots over the kept transpose
+        if (!A->cdt.built && A->nnz > 0)
+            return fail(SPW_ERR_UNSUPPORTED, std::string(fname) +
+                                                 ": this form needs the transpose (spw_create_opts.transpose = 0 dropped it)");
+        if (A->nnz == 0) {
+            e = launch_zero_fill(vdt, k, out, ldo, A->rows, stream);   // no nonzeros: all outputs are zero
+        } else {
+            e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
+        }
+    } else {
+        e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
+    }
     if (e == (int)hipErrorNotSupported)
         return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");
     if (e) return fail(SPW_ERR_DEVICE, std::string(fname) + ": kernel launch failed: " + hipGetErrorString((hipError_t)e));

@@ -48,10 +48,29 @@ struct PanelDesc {
 
 enum class IdxKind : int32_t { U16 = 0, I32 = 1 };
 
+// Column-dot storage of a short-by-long CSC matrix: int32 column starts (plus
+// a padding window), 2- or 4-byte rows and binary64 values, both interleaved
+// inside each chunk (see the column-dot kernel), the chunk/zone plan and the
+// columns without nonzeros.
+struct ColDot {
+    int64_t rows = 0, cols = 0, nnz = 0;
+    IdxKind idx_kind = IdxKind::U16;
+    int32_t *d_ptr = nullptr;
+    void *d_idx = nullptr;
+    void *d_val = nullptr;
+    ZonePlan zp;
+    int32_t *d_cjlo = nullptr, *d_cjhi = nullptr;
+    int32_t *d_empty = nullptr;
+    int64_t n_empty = 0;
+    int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
+    int64_t n_zones = 0;
+    bool built = false;
+};
+
 struct Scratch {
     double *partial = nullptr;    // mv_wgs * panel_rows * kcap  (binary64 partial sums)
-    double *carry = nullptr;      // 2 * n_chunks * kcap
-    void *vperm = nullptr;        // rows * kcap * 8  (renumbered input of the column dots)
+    double *carry = nullptr;      // 2 * max chunks * kcap
+    double *vperm = nullptr;      // rows * kcap  (renumbered input of the column dots)
     int32_t kcap = 0;
 };
 
@@ -63,23 +82,12 @@ struct spw_matrix_s {
     int64_t m = 0, n = 0, nnz = 0;      // caller's shape
     int64_t rows = 0, cols = 0;         // B = short x long
     int device = 0;
-    spw::IdxKind idx_kind = spw::IdxKind::U16;
     int32_t relabeled = 0;
-
-    // column-dot storage (original column order, renumbered rows)
-    int32_t *d_ptr = nullptr;           // cols + 1
-    void *d_idx = nullptr;              // nnz (+ padding), uint16 or int32
-    void *d_val = nullptr;              // nnz (+ padding), value_storage type
     int32_t *d_rank = nullptr;          // rows: caller row -> internal row
     int32_t *d_inv = nullptr;           // rows: internal row -> caller row
 
-    spw::ZonePlan zp;
-    int32_t *d_cjlo = nullptr;          // per chunk: column holding its first position
-    int32_t *d_cjhi = nullptr;          // per chunk: column holding its last position
-    int32_t *d_empty = nullptr;         // columns without nonzeros
-    int64_t n_empty = 0;
-    int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
-    int64_t n_zones = 0;
+    spw::ColDot cd;                     // B itself (renumbered rows)
+    spw::ColDot cdt;                    // B^T (caller's numbering), for multi-RHS scatter products
 
     // scatter-product storage: row panels; inside a panel, per workgroup column
     // range and per wave (a set of the panel's rows), blocks of 512 nonzeros
@@ -107,6 +115,12 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
                void *u, int64_t ldu, void *stream);
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
               void *y, int64_t ldy, void *stream);
+// Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
+// inv renumbers the rows of V (NULL when C uses the caller's numbering).
+int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream);
+// Fills rows x k of a row-major block (leading dimension ld) with zeros.
+int launch_zero_fill(spw_dtype vdt, int32_t k, void *out, int64_t ld, int64_t rows, void *stream);
 // Device-side limits the host plan must respect.
 int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
 int64_t mv_block_nnz();

@@ -355,6 +355,7 @@ __global__ void gather_f64(const int32_t *__restrict__ inv, int64_t len, const d
 // with non-temporal loads so they do not push x out of the caches.
 //   blocks : (column base, count) per block
 //   wg_blk : per workgroup, NW+1 offsets into blocks: wave w owns [wg_blk[w], wg_blk[w+1])
+//   x      : input, entry j at x[j*ldx]
 //   partial: per-workgroup partial sums, panel_rows entries each
 // The loop keeps two blocks of words/values and one block of x gathers in
 // flight.  Dynamic LDS: panel_rows doubles.
@@ -394,7 +395,7 @@ __device__ __forceinline__ void mv_load(MvBlk &B, const uint32_t *__restrict__ p
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
     const uint32_t *__restrict__ packed, const double *__restrict__ val, const int2 *__restrict__ blocks,
-    const int32_t *__restrict__ wg_blk, const double *__restrict__ x, double *__restrict__ partial,
+    const int32_t *__restrict__ wg_blk, const double *__restrict__ x, int64_t ldx, double *__restrict__ partial,
     int panel_rows)
 {
     constexpr int NW = BLOCK / WAVE;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
     // padding slots hold word 0, so their gather reads x[column base]: no branch
     auto gather = [&](const MvBlk &B, double *xv) {
 #pragma unroll
-        for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[B.bd.x + (int)(B.w[j] & 0xFFFFu)];
+        for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[(int64_t)(B.bd.x + (int)(B.w[j] & 0xFFFFu)) * ldx];
     };
     auto add_block = [&](const MvBlk &B, const double *xv, double *p, uint32_t *row) {
 #pragma unroll
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
 // of every addition is fixed.
 __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows,
                               const PanelDesc *__restrict__ panels, int64_t rows,
-                              const int32_t *__restrict__ inv, double *__restrict__ y)
+                              const int32_t *__restrict__ inv, double *__restrict__ y, int64_t ldy)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t r = g >> 3;
@@ -480,7 +481,153 @@ __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
-    if (live && t == 0) y[inv ? inv[r] : r] = s;
+    if (live && t == 0) y[(int64_t)(inv ? inv[r] : r) * ldy] = s;
+}
+
+// ------------------------------------------------------------------------
+// Multi-RHS column dots: U = C^T V for k right-hand sides (V is rows x k and U
+// is cols x k, both row-major with leading dimensions ldv, ldu).  A group of
+// L lanes (L = k rounded up to a power of two) walks one 1024-nonzero chunk in
+// storage order, lane c carrying the running dot of the current column with
+// column c of V; the 64/L groups of a wave take different chunks.  Columns are
+// cut at chunk boundaries exactly as in the single-vector kernel, with k-wide
+// carries: carry[(2*chunk + side)*k + c].  The chunk storage is the same
+// interleaved layout, so positions are mapped to their slots here.  Columns
+// without nonzeros are written by zero_cols_batch.
+// ------------------------------------------------------------------------
+template <typename IdxT> struct IdxSlot;
+template <> struct IdxSlot<uint16_t> {
+    static constexpr int G = 8;
+};
+template <> struct IdxSlot<int32_t> {
+    static constexpr int G = 4;
+};
+
+template <typename IdxT, int L, typename VinT, typename VoutT>
+__global__ __launch_bounds__(L * (L <= 8 ? 64 : 512 / L)) void coldot_batch(
+    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const double *__restrict__ val,
+    const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks, int k,
+    const VinT *__restrict__ V, int64_t ldv, VoutT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
+{
+    constexpr int WCH = 1024, ITEMS = 16, GI = IdxSlot<IdxT>::G;
+    constexpr int GPB = L <= 8 ? 64 : 512 / L;    // groups per workgroup
+    constexpr int SL = 128;                       // column starts kept in LDS per group
+    constexpr int T = L >= 8 ? L : 8;             // positions a group fetches per step
+    constexpr int Q = T / L;                      // positions per lane per step
+    __shared__ int32_t slices[GPB * SL];
+    const int gl = threadIdx.x % L;
+    const int gid = threadIdx.x / L;
+    int32_t *slice = slices + gid * SL;
+    const bool colok = gl < k;
+    const int cl = min(gl, k - 1);                 // idle lanes read a valid column
+    const int64_t ngroups = (int64_t)gridDim.x * GPB;
+    for (int64_t c = (int64_t)blockIdx.x * GPB + gid; c < nchunks; c += ngroups) {
+        const int s = (int)(c * WCH);
+        const int e = (int)min((int64_t)s + WCH, nnz);
+        const int jlo = cjlo[c];
+        const int ncol = cjhi[c] - jlo + 2;
+        const bool in_lds = ncol <= SL;
+        if (in_lds)
+            for (int i = gl; i < ncol; i += L) slice[i] = ptr[jlo + i];
+        // the group's lanes belong to one wave, so a wave-level sync suffices
+        wave_sync();
+        int j = jlo;
+        int cend = in_lds ? slice[1] : ptr[jlo + 1];
+        bool before = (in_lds ? slice[0] : ptr[jlo]) < s;
+        double acc = 0.0;
+        auto emit = [&](int jj, double v, bool bef, bool aft) {
+            if (!colok) return;
+            if (bef) carry[(2 * c) * k + gl] = v;
+            else if (aft) carry[(2 * c + 1) * k + gl] = v;
+            else U[(int64_t)jj * ldu + gl] = (VoutT)v;
+        };
+        for (int p0 = s; p0 < e; p0 += T) {
+            // lane gl fetches positions p0 + gl + q*L
+            double a[Q];
+            int r[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const int pp = p0 + gl + q * L;
+                a[q] = 0.0;
+                r[q] = 0;
+                if (pp < e) {
+                    const int o = pp - s, ln = o / ITEMS, i = o % ITEMS;
+                    a[q] = val[s + ((i >> 1) * 64 + ln) * 2 + (i & 1)];
+                    r[q] = (int)idx[s + ((i / GI) * 64 + ln) * GI + i % GI];
+                }
+            }
+            const int steps = min(T, e - p0);
+#pragma unroll
+            for (int t0 = 0; t0 < T; t0 += 8) {
+                // eight gathers in flight before they are used
+                double at[8], vv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = t0 + u;
+                    at[u] = __shfl(a[t / L], t % L, L);
+                    const int rt = __shfl(r[t / L], t % L, L);
+                    vv[u] = (double)V[(int64_t)rt * ldv + cl];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = t0 + u;
+                    if (t < steps) {
+                        const int p = p0 + t;
+                        while (p >= cend) {            // the current column ends before p
+                            emit(j, acc, before, false);
+                            acc = 0.0;
+                            before = false;
+                            do {
+                                ++j;
+                                cend = in_lds ? slice[j + 1 - jlo] : ptr[j + 1];
+                            } while (cend <= p);       // skip columns without nonzeros
+                        }
+                        acc += at[u] * vv[u];
+                    }
+                }
+            }
+        }
+        emit(j, acc, before, cend > e);
+        wave_sync();                                   // slice reads done before it is rewritten
+    }
+}
+
+// Multi-RHS zone reduction: one lane per (zone, right-hand side).
+template <typename VoutT>
+__global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
+                                 const int32_t *__restrict__ zlast, int64_t nz, int k,
+                                 const double *__restrict__ carry, VoutT *__restrict__ U, int64_t ldu)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nz * k) return;
+    const int64_t z = g / k;
+    const int cc = (int)(g - z * k);
+    const int a = zfirst[z], b = zlast[z];
+    double s = carry[(2 * (int64_t)a + 1) * k + cc];
+    for (int c = a + 1; c <= b; ++c) s += carry[(2 * (int64_t)c) * k + cc];
+    U[(int64_t)zcol[z] * ldu + cc] = (VoutT)s;
+}
+
+template <typename VoutT>
+__global__ void zero_cols_batch(const int32_t *__restrict__ cols, int64_t count, int k, VoutT *__restrict__ U,
+                                int64_t ldu)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= count * k) return;
+    const int64_t i = g / k;
+    U[(int64_t)cols[i] * ldu + (g - i * k)] = (VoutT)0;
+}
+
+// Renumber the rows of a k-wide block: out[r*k + c] = in[inv[r]*ldv + c].
+template <typename VinT>
+__global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k, const VinT *__restrict__ in,
+                            int64_t ldv, double *__restrict__ out)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    const int cc = (int)(g - r * k);
+    out[g] = (double)in[(int64_t)inv[r] * ldv + cc];
 }
 
 constexpr int VTM_BLOCK = 512;
@@ -537,29 +684,29 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
     if (vdt != SPW_F64 || k != 1 || ldv != 1 || ldu != 1 || A.value_storage != SPW_F64)
         return (int)hipErrorNotSupported;
     double *uo = (double *)u;
-    if (A.cols == 0) return 0;
-    if (A.n_empty > 0) {
+    if (A.cd.cols == 0) return 0;
+    if (A.cd.n_empty > 0) {
         ProfScope ps(stream, "zero_cols_f64");
-        hipLaunchKernelGGL(zero_cols_f64, dim3(blocks_for(A.n_empty, 256)), dim3(256), 0, stream, A.d_empty,
-                           A.n_empty, uo);
+        hipLaunchKernelGGL(zero_cols_f64, dim3(blocks_for(A.cd.n_empty, 256)), dim3(256), 0, stream, A.cd.d_empty,
+                           A.cd.n_empty, uo);
         int e = (int)hipGetLastError();
         if (e) return e;
     }
-    if (A.nnz == 0) return 0;
+    if (A.cd.nnz == 0) return 0;
     const double *vin = (const double *)v;
     if (A.relabeled) {
         ProfScope ps(stream, "gather_f64");
         hipLaunchKernelGGL(gather_f64, dim3(blocks_for(A.rows, 256)), dim3(256), 0, stream, A.d_inv, A.rows,
-                           vin, (double *)A.scratch.vperm);
-        vin = (const double *)A.scratch.vperm;
+                           vin, A.scratch.vperm);
+        vin = A.scratch.vperm;
     }
     {
         ProfScope ps(stream, "vtm_wave_f64");
-        if (A.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
+        if (A.cd.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
         const int vhot = (int)std::min<int64_t>(A.rows, vtm_hot_rows_limit());
         const size_t lds = (size_t)vhot * 8 + (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
         const int cus = device_cu_count(A.device);
-        const int64_t wgs_needed = (A.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
+        const int64_t wgs_needed = (A.cd.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
         static bool attr = false;
         if (!attr) {
@@ -567,23 +714,23 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
             allow_full_lds(vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>);
             attr = true;
         }
-        if (A.idx_kind == IdxKind::U16)
+        if (A.cd.idx_kind == IdxKind::U16)
             hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, A.d_ptr, (const uint16_t *)A.d_idx,
-                               (const double *)A.d_val, A.d_cjlo, A.d_cjhi, A.nnz, A.zp.n_chunks, vin, vhot, uo,
+                               dim3(VTM_BLOCK), lds, stream, A.cd.d_ptr, (const uint16_t *)A.cd.d_idx,
+                               (const double *)A.cd.d_val, A.cd.d_cjlo, A.cd.d_cjhi, A.cd.nnz, A.cd.zp.n_chunks, vin, vhot, uo,
                                A.scratch.carry);
         else
             hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, A.d_ptr, (const int32_t *)A.d_idx,
-                               (const double *)A.d_val, A.d_cjlo, A.d_cjhi, A.nnz, A.zp.n_chunks, vin, vhot, uo,
+                               dim3(VTM_BLOCK), lds, stream, A.cd.d_ptr, (const int32_t *)A.cd.d_idx,
+                               (const double *)A.cd.d_val, A.cd.d_cjlo, A.cd.d_cjhi, A.cd.nnz, A.cd.zp.n_chunks, vin, vhot, uo,
                                A.scratch.carry);
         int e = (int)hipGetLastError();
         if (e) return e;
     }
-    if (A.n_zones > 0) {
+    if (A.cd.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup_f64");
-        hipLaunchKernelGGL(zone_fixup_f64, dim3(blocks_for(A.n_zones, 256)), dim3(256), 0, stream, A.d_zone_col,
-                           A.d_zone_first, A.d_zone_last, A.n_zones, A.scratch.carry, uo);
+        hipLaunchKernelGGL(zone_fixup_f64, dim3(blocks_for(A.cd.n_zones, 256)), dim3(256), 0, stream, A.cd.d_zone_col,
+                           A.cd.d_zone_first, A.cd.d_zone_last, A.cd.n_zones, A.scratch.carry, uo);
         int e = (int)hipGetLastError();
         if (e) return e;
     }
@@ -593,33 +740,143 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, i
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx, void *y,
               int64_t ldy, void *stream_)
 {
+    // k right-hand sides run as k passes of the scatter kernel over strided
+    // columns of X and Y (the multi-RHS path uses this for small k)
     hipStream_t stream = (hipStream_t)stream_;
-    if (vdt != SPW_F64 || k != 1 || ldx != 1 || ldy != 1 || A.value_storage != SPW_F64)
-        return (int)hipErrorNotSupported;
-    double *yo = (double *)y;
+    if (vdt != SPW_F64 || A.value_storage != SPW_F64) return (int)hipErrorNotSupported;
     if (A.rows == 0) return 0;
-    if (A.mv_wgs > 0) {
-        ProfScope ps(stream, "mv_bucket_f64");
-        const size_t lds = (size_t)A.panel_rows * 8;
-        static bool attr = false;
-        if (!attr) {
-            allow_full_lds(mv_bucket_f64<MV_BLOCK>);
-            attr = true;
-        }
-        hipLaunchKernelGGL((mv_bucket_f64<MV_BLOCK>), dim3((unsigned)A.mv_wgs), dim3(MV_BLOCK), lds, stream,
-                           (const uint32_t *)A.d_mpacked, (const double *)A.d_mval, (const int2 *)A.d_mblocks,
-                           A.d_wg_blk, (const double *)x, A.scratch.partial, (int)A.panel_rows);
-        int e = (int)hipGetLastError();
-        if (e) return e;
+    static bool attr = false;
+    if (!attr) {
+        allow_full_lds(mv_bucket_f64<MV_BLOCK>);
+        attr = true;
     }
-    {
-        ProfScope ps(stream, "mv_reduce_f64");
-        hipLaunchKernelGGL(mv_reduce_f64, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream, A.scratch.partial,
-                           (int)A.panel_rows, A.d_panels, A.rows, A.relabeled ? A.d_inv : nullptr, yo);
-        int e = (int)hipGetLastError();
-        if (e) return e;
+    for (int32_t c = 0; c < k; ++c) {
+        const double *xc = (const double *)x + c;
+        double *yc = (double *)y + c;
+        if (A.mv_wgs > 0) {
+            ProfScope ps(stream, "mv_bucket_f64");
+            const size_t lds = (size_t)A.panel_rows * 8;
+            hipLaunchKernelGGL((mv_bucket_f64<MV_BLOCK>), dim3((unsigned)A.mv_wgs), dim3(MV_BLOCK), lds, stream,
+                               (const uint32_t *)A.d_mpacked, (const double *)A.d_mval, (const int2 *)A.d_mblocks,
+                               A.d_wg_blk, xc, ldx, A.scratch.partial, (int)A.panel_rows);
+            int e = (int)hipGetLastError();
+            if (e) return e;
+        }
+        {
+            ProfScope ps(stream, "mv_reduce_f64");
+            hipLaunchKernelGGL(mv_reduce_f64, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream,
+                               A.scratch.partial, (int)A.panel_rows, A.d_panels, A.rows,
+                               A.relabeled ? A.d_inv : nullptr, yc, ldy);
+            int e = (int)hipGetLastError();
+            if (e) return e;
+        }
     }
     return 0;
+}
+
+namespace {
+template <typename IdxT, typename VinT, typename VoutT>
+int launch_batch_kernel(const ColDot &C, int L, int k, const VinT *V, int64_t ldv, VoutT *U, int64_t ldu,
+                        double *carry, hipStream_t stream)
+{
+    const int64_t gpb = L <= 8 ? 64 : 512 / L;
+    const int64_t want = (C.zp.n_chunks + gpb - 1) / gpb;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16));
+#define SPW_BATCH_CASE(LL)                                                                                          \
+    case LL:                                                                                                        \
+        hipLaunchKernelGGL((coldot_batch<IdxT, LL, VinT, VoutT>), dim3(grid), dim3(LL * gpb), 0, stream, C.d_ptr,  \
+                           (const IdxT *)C.d_idx, (const double *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz,             \
+                           C.zp.n_chunks, k, V, ldv, U, ldu, carry);                                                \
+        break;
+    switch (L) {
+        SPW_BATCH_CASE(1)
+        SPW_BATCH_CASE(2)
+        SPW_BATCH_CASE(4)
+        SPW_BATCH_CASE(8)
+        SPW_BATCH_CASE(16)
+        SPW_BATCH_CASE(32)
+        SPW_BATCH_CASE(64)
+    default: return (int)hipErrorInvalidValue;
+    }
+#undef SPW_BATCH_CASE
+    return (int)hipGetLastError();
+}
+
+template <typename VinT, typename VoutT>
+int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VinT *V,
+                       int64_t ldv, VoutT *U, int64_t ldu, hipStream_t stream)
+{
+    int e;
+    if (C.n_empty > 0) {
+        ProfScope ps(stream, "zero_cols_batch");
+        hipLaunchKernelGGL(zero_cols_batch<VoutT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
+                           C.d_empty, C.n_empty, k, U, ldu);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (C.nnz == 0) return 0;
+    int L = 1;
+    while (L < k) L <<= 1;
+    {
+        ProfScope ps(stream, "coldot_batch");
+        if (inv) {
+            hipLaunchKernelGGL(gather_rows<VinT>, dim3(blocks_for(C.rows * k, 256)), dim3(256), 0, stream, inv,
+                               C.rows, k, V, ldv, A.scratch.vperm);
+            if ((e = (int)hipGetLastError())) return e;
+            e = C.idx_kind == IdxKind::U16
+                    ? launch_batch_kernel<uint16_t, double, VoutT>(C, L, k, A.scratch.vperm, k, U, ldu,
+                                                                  A.scratch.carry, stream)
+                    : launch_batch_kernel<int32_t, double, VoutT>(C, L, k, A.scratch.vperm, k, U, ldu,
+                                                                 A.scratch.carry, stream);
+        } else {
+            e = C.idx_kind == IdxKind::U16
+                    ? launch_batch_kernel<uint16_t, VinT, VoutT>(C, L, k, V, ldv, U, ldu, A.scratch.carry, stream)
+                    : launch_batch_kernel<int32_t, VinT, VoutT>(C, L, k, V, ldv, U, ldu, A.scratch.carry, stream);
+        }
+        if (e) return e;
+    }
+    if (C.n_zones > 0) {
+        ProfScope ps(stream, "zone_fixup_batch");
+        hipLaunchKernelGGL(zone_fixup_batch<VoutT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+                           C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    return 0;
+}
+}  // namespace
+
+int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (A.value_storage != SPW_F64 || k < 1 || k > 64) return (int)hipErrorNotSupported;
+    if (C.cols == 0) return 0;
+    if (vdt == SPW_F64)
+        return coldot_batch_typed<double, double>(A, C, inv, k, (const double *)V, ldv, (double *)U, ldu, stream);
+    if (vdt == SPW_F32)
+        return coldot_batch_typed<float, float>(A, C, inv, k, (const float *)V, ldv, (float *)U, ldu, stream);
+    return (int)hipErrorNotSupported;
+}
+
+template <typename T>
+__global__ void zero_fill_rows(T *__restrict__ out, int64_t rows, int k, int64_t ld)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    out[r * ld + (g - r * k)] = (T)0;
+}
+
+int launch_zero_fill(spw_dtype vdt, int32_t k, void *out, int64_t ld, int64_t rows, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (rows <= 0) return 0;
+    if (vdt == SPW_F64)
+        hipLaunchKernelGGL(zero_fill_rows<double>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, (double *)out,
+                           rows, (int)k, ld);
+    else
+        hipLaunchKernelGGL(zero_fill_rows<float>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, (float *)out,
+                           rows, (int)k, ld);
+    return (int)hipGetLastError();
 }
 
 }  // namespace spw

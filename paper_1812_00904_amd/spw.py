@@ -36,7 +36,7 @@ class CreateOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("value_storage", ctypes.c_int),
                 ("chunk_nnz", ctypes.c_int32), ("relabel", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("device", ctypes.c_int32), ("transpose", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -46,7 +46,8 @@ class MatrixInfo(ctypes.Structure):
                 ("chunk_nnz", ctypes.c_int64), ("n_chunks", ctypes.c_int64), ("n_zones", ctypes.c_int64),
                 ("n_panels", ctypes.c_int64), ("panel_rows", ctypes.c_int64),
                 ("mv_workgroups", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
-                ("relabeled", ctypes.c_int32), ("device", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("relabeled", ctypes.c_int32), ("device", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("has_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -135,7 +136,7 @@ def spw_info(h: int) -> dict:
     info = MatrixInfo()
     info.struct_size = ctypes.sizeof(MatrixInfo)
     _check(load().spw_info(h, ctypes.byref(info)))
-    return {name: getattr(info, name) for name, _ in MatrixInfo._fields_ if name != "struct_size"}
+    return {name: getattr(info, name) for name, _ in MatrixInfo._fields_ if name not in ("struct_size", "reserved")}
 
 
 def _vec_dtype(t: torch.Tensor) -> int:

@@ -1,0 +1,156 @@
+"""GPU parity of the multi-RHS forms (k right-hand sides in one pass) and of the
+binary32-vector forms, through the C ABI, against the CPU oracle.
+
+binary64 vectors: |gpu - oracle| <= 1e-13 * sum|a||x| per component.
+binary32 vectors: the oracle runs in binary64 on the binary32 inputs (promoted
+exactly); the bar is 1e-5 * sum|a||x| per component.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spw():
+    from paper_1812_00904_amd import spw as mod
+    mod.load()
+    assert torch.cuda.is_available()
+    return mod
+
+
+def check(got, ref, d, what, tol):
+    assert got.shape == ref.shape, what
+    assert not np.isnan(got).any(), "%s: unwritten components" % what
+    err = np.abs(got - ref)
+    bad = err > tol * d
+    if bad.any():
+        i = np.argwhere(bad)[0]
+        raise AssertionError("%s: %d entries off; first %s: got %r want %r d=%r"
+                             % (what, int(bad.sum()), tuple(i), got[tuple(i)], ref[tuple(i)], d[tuple(i)]))
+
+
+def block(rows, k, seed, stream, dtype, pad):
+    """rows x k block with leading dimension k + pad, as a strided view of a wider tensor."""
+    a = synth.vector(rows * k, seed, stream).reshape(rows, k)
+    if dtype == torch.float32:
+        a = a.astype(np.float32).astype(np.float64)      # the values the GPU sees
+    full = torch.full((rows, k + pad), float("nan"), dtype=dtype)
+    full[:, :k] = torch.from_numpy(a).to(dtype)
+    return a, full.cuda()[:, :k]
+
+
+def run_case(spw, A, fmt, k, dtype, pad, seed, name, opts=None, reps=1):
+    m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
+    print("batch case %s fmt=%d k=%d dtype=%s pad=%d m=%d n=%d nnz=%d" % (name, fmt, k, dtype, pad, m, n, A.nnz),
+          flush=True)
+    M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, **(opts or {}))
+    X, Xd = block(n, k, seed, 1, dtype, pad)
+    V, Vd = block(m, k, seed, 2, dtype, pad)
+    outs = []
+    for _ in range(reps):
+        Yf = torch.full((m, k + pad), float("nan"), dtype=dtype, device="cuda")
+        Uf = torch.full((n, k + pad), float("nan"), dtype=dtype, device="cuda")
+        spw.spw_mv_batch(M.handle, Xd, Yf[:, :k])
+        spw.spw_vtm_batch(M.handle, Vd, Uf[:, :k])
+        torch.cuda.synchronize()
+        outs.append((Yf.double().cpu().numpy(), Uf.double().cpu().numpy()))
+    M.close()
+    Y, U = outs[0]
+    # padding columns untouched
+    assert np.isnan(Y[:, k:]).all() and np.isnan(U[:, k:]).all()
+    if fmt == 0:
+        Yr, DY = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
+        Ur, DU = oracle.vtm_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, V, with_d=True)
+    else:
+        Yr, DY = oracle.mv_csr_batch(A.n, A.m, A.ptr, A.idx, A.val, X, with_d=True)
+        Ur, DU = oracle.vtm_csr_batch(A.n, A.m, A.ptr, A.idx, A.val, V, with_d=True)
+    tol = 1e-13 if dtype == torch.float64 else 1e-5
+    check(Y[:, :k], Yr, DY, "%s mv_batch" % name, tol)
+    check(U[:, :k], Ur, DU, "%s vtm_batch" % name, tol)
+    for r in range(1, reps):
+        assert np.array_equal(outs[r][0], Y, equal_nan=True) and np.array_equal(outs[r][1], U, equal_nan=True), \
+            "not bit-identical"
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("k", [1, 3, 4, 16, 64])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_small_config(spw, fmt, k, dtype):
+    A = synth.config_matrix("c0", scale=0.2 if k < 64 else 0.05)
+    run_case(spw, A, fmt, k, dtype, pad=1 if k % 2 else 0, seed=k, name="c0", reps=2)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "wide_index"])
+def test_batch_structures(spw, fmt, case):
+    if case == "ragged":
+        A = synth.random_csc(37, 5000, 5.0, 3, values="lognormal")
+    elif case == "many_empty":
+        A = synth.random_csc(300, 20000, 3.0, 4, empty_frac=0.8)
+    elif case == "dense_cols":
+        L = np.r_[np.full(300, 2), [6000] * 3, np.full(500, 1), [6000], np.full(77, 3)]
+        A = synth.from_lengths(6000, L, 5, row_alpha=0.8, values="lognormal")
+    elif case == "tiny":
+        A = synth.random_csc(3, 4, 2.0, 6)
+    else:
+        A = synth.random_csc(70000, 3000, 12.0, 10, values="lognormal", row_alpha=0.8)
+    run_case(spw, A, fmt, 5, torch.float64, pad=3, seed=7, name=case)
+    run_case(spw, A, fmt, 8, torch.float32, pad=0, seed=8, name=case)
+
+
+def test_batch_scaled_batching_config(spw):
+    A = synth.config_matrix("c2", scale=0.05)
+    for k in (4, 16):
+        run_case(spw, A, 0, k, torch.float64, pad=0, seed=k, name="c2x0.05")
+    run_case(spw, A, 0, 16, torch.float32, pad=0, seed=3, name="c2x0.05")
+
+
+def test_plain_binary32_vectors(spw):
+    A = synth.config_matrix("c0", scale=0.3)
+    M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val)
+    x = synth.vector(A.n, 3, 1).astype(np.float32)
+    v = synth.vector(A.m, 3, 2).astype(np.float32)
+    y = M.mv(torch.from_numpy(x).cuda()).double().cpu().numpy()
+    u = M.vtm(torch.from_numpy(v).cuda()).double().cpu().numpy()
+    yr, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x.astype(np.float64), with_d=True)
+    ur, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v.astype(np.float64), with_d=True)
+    check(y, yr, dy, "f32 mv", 1e-5)
+    check(u, ur, du, "f32 vtm", 1e-5)
+    M.close()
+
+
+def test_batch_column_equals_plain_call(spw):
+    A = synth.config_matrix("c0", scale=0.2)
+    M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val)
+    k = 4
+    X = torch.from_numpy(synth.vector(A.n * k, 9, 1).reshape(A.n, k)).cuda()
+    Y = M.mv_batch(X)
+    for c in range(k):
+        y = M.mv(X[:, c].contiguous())
+        d = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, np.abs(A.val), np.abs(X[:, c].cpu().numpy()))
+        assert np.all(np.abs(Y[:, c].cpu().numpy() - y.cpu().numpy()) <= 2e-13 * d)
+    M.close()
+
+
+def test_transpose_off_is_reported(spw):
+    A = synth.config_matrix("c0", scale=0.05)
+    M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val, transpose=0)
+    assert M.info()["has_transpose"] == 0
+    # binary64 blocks fall back to one scatter pass per column
+    X = torch.from_numpy(synth.vector(A.n * 6, 4, 1).reshape(A.n, 6)).cuda()
+    Y = M.mv_batch(X).cpu().numpy()
+    Yr, DY = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X.cpu().numpy(), with_d=True)
+    check(Y, Yr, DY, "transpose off mv_batch", 1e-13)
+    # binary32 blocks need the transpose
+    with pytest.raises(spw.SpwError) as ei:
+        M.mv_batch(X.float())
+    assert ei.value.status_name == "SPW_ERR_UNSUPPORTED"
+    # the other direction does not need it
+    V = torch.ones((A.m, 2), dtype=torch.float64, device="cuda")
+    M.vtm_batch(V)
+    M.close()
