@@ -14,7 +14,10 @@ Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line.  Also reports, outside the timed steps: the tall mirror
 (the same arrays read as a 2e7 x 50,000 CSR matrix), per-kernel roofline
-figures, plain-call latency percentiles, and the CPU oracle timed on the host.
+figures, plain-call latency percentiles, reduced-precision value storage on
+the same matrix (binary32 / bfloat16 values, binary32 vectors, with their
+error against binary64 products), multi-RHS blocks on the 5e7-nonzero
+batching matrix, and the CPU oracle timed on the host.
 
 `--pmc-summary DIR` turns rocprofv3 counter output (FETCH_SIZE / WRITE_SIZE
 runs of `--profile-run`) into the traffic summary under profiles/.
@@ -131,6 +134,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tall", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS section")
+    ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision storage section")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
     ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
@@ -202,12 +206,12 @@ def main():
         avg = tot / max(launches, 1)
         kernels[name] = {"launches": launches, "avg_us": round(avg * 1e3, 2)}
     one_op = model_bytes(A.m, A.n, A.nnz)
-    for name, op in (("mv_bucket_f64", "mv"), ("vtm_wave_f64", "vtm")):
+    for name, op in (("mv_bucket", "mv"), ("vtm_wave", "vtm")):
         if name in kernels:
             gbs = one_op / (kernels[name]["avg_us"] * 1e-6) / 1e9
             kernels[name]["achieved_GBps"] = round(gbs, 1)
             kernels[name]["op"] = op
-    dom = max(("mv_bucket_f64", "vtm_wave_f64"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
+    dom = max(("mv_bucket", "vtm_wave"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
     traffic = read_traffic()
     tr_val = None
     if traffic and ("%s_bytes_per_launch" % dom) in traffic:
@@ -243,6 +247,9 @@ def main():
                          "vtm_GBps": round(one_op / (percentile(tvtm, 50) * 1e-3) / 1e9, 1)}
         T.close()
         del yt, ut
+
+    if not args.no_precision:
+        extra["precision"] = bench_precision(args, A, M, xd, vd)
 
     if not args.no_batch:
         M.close()
@@ -283,18 +290,102 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
+def _time_each(fn, reps):
+    """Median and p99 of `reps` event-timed calls (ms)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    ts = [a.elapsed_time(b) for a, b in ev]
+    return percentile(ts, 50), percentile(ts, 99)
+
+
+def _err_stats(got, ref, d):
+    """max / p99 / median of |got - ref| / d over the entries with d > 0, and the
+    number of entries with d == 0 that are not exactly zero."""
+    import torch
+    got = got.double()
+    pos = d > 0
+    r = ((got - ref).abs()[pos] / d[pos]).float()
+    bad_zero = int(((got != 0) & ~pos).sum().item())
+    if r.numel() == 0:
+        return {"max": 0.0, "p99": 0.0, "median": 0.0, "nonzero_where_d_is_0": bad_zero}
+    q = torch.quantile(r[torch.randperm(r.numel(), device=r.device)[:1 << 24]],
+                       torch.tensor([0.5, 0.99], device=r.device))
+    return {"max": float(r.max().item()), "p99": float(q[1].item()), "median": float(q[0].item()),
+            "nonzero_where_d_is_0": bad_zero}
+
+
+def bench_precision(args, A, M, xd, vd):
+    """Binary32 and bfloat16 value storage on the 2e8-nonzero wide matrix with
+    binary32 vectors: effective GB/s of each product (values 4 or 2 bytes, vector
+    entries 4 bytes in the byte model) and the error of its output, per entry
+    relative to d = sum |a| |x|, against (i) binary64 products with the original
+    values and (ii) binary64 products with the stored values (both run by the
+    binary64 path of this library, whose parity with the CPU oracle is tested
+    to 1e-13 * d)."""
+    import torch
+    from paper_1812_00904_amd import SPW_CSC, SpwMatrix, spw_round_values
+    x32, v32 = xd.float(), vd.float()
+    xw, vw = x32.double(), v32.double()
+    reps = max(args.steps // 2, 10)
+    Mabs = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, abs(A.val), transpose=0)
+    dy, du = Mabs.mv(xw.abs()), Mabs.vtm(vw.abs())
+    Mabs.close()
+    y_o, u_o = M.mv(xw), M.vtm(vw)
+    res = {"workload": "same wide CSC matrix, binary32 vectors", "rows": []}
+    for name, code, sv in (("f32", 1, 4), ("bf16", 2, 2)):
+        t = time.perf_counter()
+        S = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, value_storage=code, transpose=0)
+        create_s = time.perf_counter() - t
+        y = torch.empty(A.m, dtype=torch.float32, device="cuda")
+        u = torch.empty(A.n, dtype=torch.float32, device="cuda")
+        mv50, mv99 = _time_each(lambda: S.mv(x32, y), reps)
+        vt50, vt99 = _time_each(lambda: S.vtm(v32, u), reps)
+        S.mv(x32, y)
+        S.vtm(v32, u)
+        R = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, spw_round_values(code, A.val), transpose=0)
+        y_r, u_r = R.mv(xw), R.vtm(vw)
+        R.close()
+        by = model_bytes(A.m, A.n, A.nnz, sv=sv, sx=4)
+        row = {"values": name, "vectors": "f32", "device_bytes": S.info()["device_bytes"],
+               "create_s": round(create_s, 2),
+               "mv_ms_p50": round(mv50, 4), "mv_ms_p99": round(mv99, 4),
+               "vtm_ms_p50": round(vt50, 4), "vtm_ms_p99": round(vt99, 4),
+               "model_bytes": by, "mv_GBps": round(by / (mv50 * 1e-3) / 1e9, 1),
+               "vtm_GBps": round(by / (vt50 * 1e-3) / 1e9, 1),
+               "mv_err_vs_stored_values": _err_stats(y, y_r, dy),
+               "vtm_err_vs_stored_values": _err_stats(u, u_r, du),
+               "mv_err_vs_original_values": _err_stats(y, y_o, dy),
+               "vtm_err_vs_original_values": _err_stats(u, u_o, du)}
+        S.close()
+        del y, u, y_r, u_r
+        torch.cuda.empty_cache()
+        res["rows"].append(row)
+        print("[bench] precision %s" % row, file=sys.stderr, flush=True)
+    return res
+
+
 def bench_batched(args):
     """Multi-RHS blocks on the batching matrix (m=20,000, n=5e6, ~5e7 nonzeros):
     one fused pass for k right-hand sides against k plain single-vector calls,
-    binary64 and binary32 vectors, both directions."""
+    binary64 (values and vectors) and binary32 (values and vectors), both
+    directions.  Each row names the kernel plan the library picks for that k."""
     import torch
     import synth
-    from paper_1812_00904_amd import SPW_CSC, SpwMatrix
+    from paper_1812_00904_amd import SPW_CSC, SPW_F32, SpwMatrix
     A = synth.config_matrix("c2", scale=args.scale)
-    M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
     res = {"workload": "wide CSC m=%d n=%d nnz=%d (Zipf(1.1) lengths + 100 half-dense columns, Zipf(0.8) rows)"
                        % (A.m, A.n, A.nnz), "rows": []}
     for dtype, sx in ((torch.float64, 8), (torch.float32, 4)):
+        M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val,
+                      **({} if sx == 8 else {"value_storage": SPW_F32}))
+        info = M.info()
         for k in (1, 4, 16, 64):
             X = torch.rand((A.n, k), dtype=dtype, device="cuda") * 2 - 1
             V = torch.rand((A.m, k), dtype=dtype, device="cuda") * 2 - 1
@@ -317,9 +408,9 @@ def bench_batched(args):
                     M.vtm(vs[c], us[c])
             t_pmv = _time(plain_mv, reps)
             t_pvtm = _time(plain_vtm, reps)
-            by = model_bytes(A.m, A.n, A.nnz, k=k, sx=sx)
-            by1 = model_bytes(A.m, A.n, A.nnz, k=1, sx=sx)
-            row = {"dtype": "f64" if sx == 8 else "f32", "k": k,
+            by = model_bytes(A.m, A.n, A.nnz, k=k, sv=sx, sx=sx)
+            by1 = model_bytes(A.m, A.n, A.nnz, k=1, sv=sx, sx=sx)
+            row = {"dtype": "f64" if sx == 8 else "f32", "k": k, "plan": batch_plan(info, k),
                    "mv_batch_ms": round(t_mv, 4), "vtm_batch_ms": round(t_vtm, 4),
                    "mv_plain_k_calls_ms": round(t_pmv, 4), "vtm_plain_k_calls_ms": round(t_pvtm, 4),
                    "mv_batch_GBps": round(by / (t_mv * 1e-3) / 1e9, 1),
@@ -331,8 +422,28 @@ def bench_batched(args):
             print("[bench] batched %s" % row, file=sys.stderr, flush=True)
             del X, V, Y, U, xs, vs, ys, us
             torch.cuda.empty_cache()
-    M.close()
+        M.close()
     return res
+
+
+def batch_plan(info, k):
+    """The kernel configuration the library uses for a k-wide block (its fixed rule)."""
+    L = 1
+    while L < k:
+        L *= 2
+    gpb = 64 if L <= 8 else 512 // L
+    if k == 1 or k <= 4:
+        mv = ("%d scatter pass(es): %d row panel(s) of %d rows in LDS, %d workgroups x 4 waves, blocks of 1024 "
+              "nonzeros" % (k, info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
+    else:
+        mv = ("column dots over the kept transpose: chunks of 1024 nonzeros, %d-lane groups, %d groups "
+              "(%d threads) per workgroup" % (L, gpb, L * gpb))
+    if k == 1:
+        vtm = "column dots: chunks of 1024 nonzeros, one wave per chunk, 512-thread persistent workgroups"
+    else:
+        vtm = ("column dots: chunks of 1024 nonzeros, %d-lane groups, %d groups (%d threads) per workgroup"
+               % (L, gpb, L * gpb))
+    return {"mv": mv, "vtm": vtm, "chunk_nnz": info["chunk_nnz"]}
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str):
@@ -359,7 +470,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
         if copy:
             cal = (1 << 20) / (sorted(copy)[len(copy) // 2])   # KiB expected / KiB read
         out.append("%s_copy_calibration=%s" % (counter, "%.4f" % cal if cal else "none"))
-        for name in ("mv_bucket_f64", "vtm_wave_f64", "mv_reduce_f64", "zone_fixup_f64", "gather_f64", "zero_cols_f64"):
+        for name in ("mv_bucket", "vtm_wave", "mv_reduce", "zone_fixup", "gather_vec", "zero_cols"):
             vals = [v for k, v in rows if name in k]
             if vals:
                 med = sorted(vals)[len(vals) // 2] * 1024.0 * (cal or 1.0)

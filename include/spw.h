@@ -63,7 +63,10 @@ typedef struct spw_matrix_s *spw_matrix;
 /* Creation options.  Zero-initialise, set struct_size = sizeof(spw_create_opts),
  * or call spw_create_opts_default.  NULL opts means defaults.
  *   value_storage : F64 (default), F32 or BF16 -- the stored nonzero values are
- *                   rounded once from the given binary64 values, to nearest even.
+ *                   rounded once from the given binary64 values, to nearest even
+ *                   (BF16 directly from binary64, no double rounding); a value
+ *                   that overflows the storage type is SPW_ERR_BAD_MATRIX.
+ *                   Products promote stored values exactly to binary64.
  *   chunk_nnz     : nonzeros per column-dot chunk (0 = automatic; this build
  *                   supports only its default, 1024).
  *   relabel       : -1 automatic, 0 off, 1 on.  On: rows are renumbered inside
@@ -75,10 +78,9 @@ typedef struct spw_matrix_s *spw_matrix;
  *   device        : HIP device ordinal, -1 = the current device.
  *   transpose     : -1 (default) or 1 also keeps the transpose, which the
  *                   multi-RHS products of the long-to-short direction (CSC A x,
- *                   CSR v^T A) use for k > 4 and the binary32-vector forms of
- *                   that direction need; 0 saves that memory: binary64 blocks
- *                   then run one scatter pass per column and binary32 ones
- *                   return SPW_ERR_UNSUPPORTED. */
+ *                   CSR v^T A) use for k > 4 (one pass over A for all k
+ *                   columns); 0 saves that memory, and those blocks then run
+ *                   one scatter pass per column. */
 typedef struct {
     uint32_t struct_size;
     spw_dtype value_storage;
@@ -141,8 +143,10 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *out);
 
 /* y := A x (Section I; for CSC, Section III's nonzero-split product).
  * x: device, n entries of type vdt; y: device, m entries of type vdt.
- * vdt: SPW_F64, or SPW_F32 (binary32 vectors; accumulation is binary32 with
- * compensated sums inside a workgroup and binary64 across workgroups). */
+ * vdt: SPW_F64 or SPW_F32 (binary32 vectors).  Whatever the vector and
+ * storage types, every product and sum is formed in binary64 (products of
+ * binary32 or bfloat16 values with binary32 entries are exact there), carries
+ * and partial vectors are binary64, and each output is rounded once to vdt. */
 spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream);
 
 /* u^T := v^T A (Section I; for CSC, Section IV-A's per-column dot with zone sums).
@@ -160,7 +164,13 @@ spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, i
 spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv,
                          void *U, int64_t ldu, void *stream);
 
-/* ---------------------------------------------------------- host-only plan */
+/* ---------------------------------------------------------- host-only helpers */
+
+/* Rounds n binary64 values the way spw_create stores them for `storage`
+ * (nearest, ties to even) and returns them promoted back to binary64, so that
+ * a caller can form the exact matrix a product uses.  in/out are host arrays
+ * (may be the same).  SPW_ERR_BAD_MATRIX names the first value that overflows. */
+spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, double *out);
 
 /* The chunk / zone plan the transpose product uses, computed on the host from a
  * column pointer array (no device needed).  Chunk c holds positions

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -123,6 +124,91 @@ spw_status validate(int64_t outer, int64_t inner, int64_t nnz, const int64_t *pt
     return SPW_OK;
 }
 
+// ------------------------------------------------------------ value storage
+// Stored values are rounded once from the given binary64 value to nearest,
+// ties to even.  binary32: the C conversion (round-to-nearest-even is the
+// default mode).  bfloat16 (8 significant bits, binary32's exponent range,
+// gradual underflow down to 2^-133): rounded directly from the binary64 bits,
+// so there is no double rounding through binary32.
+int64_t storage_bytes(spw_dtype t) { return t == SPW_F64 ? 8 : t == SPW_F32 ? 4 : 2; }
+
+// Returns false when the rounded value is not finite.
+bool round_f32(double x, double *out)
+{
+    const float f = (float)x;
+    *out = (double)f;
+    return std::isfinite(f) || !std::isfinite(x);
+}
+
+bool round_bf16(double x, double *out)
+{
+    uint64_t b;
+    std::memcpy(&b, &x, 8);
+    const uint64_t mag = b & 0x7FFFFFFFFFFFFFFFull;
+    const int bexp = (int)(mag >> 52);
+    if (bexp == 0x7FF) {                      // inf / nan stay as they are
+        *out = x;
+        return true;
+    }
+    if (mag == 0 || bexp == 0) {              // zero or a binary64 subnormal (far below 2^-134)
+        *out = std::copysign(0.0, x);
+        return true;
+    }
+    const int e = bexp - 1023;                // x = sig * 2^(e-52), sig in [2^52, 2^53)
+    const uint64_t sig = (mag & ((1ull << 52) - 1)) | (1ull << 52);
+    const int qe = std::max(e, -126) - 7;     // exponent of the last kept bit
+    const int drop = qe - (e - 52);           // low bits of sig below that bit (>= 45)
+    uint64_t q = 0;
+    if (drop < 64) {
+        q = sig >> drop;
+        const uint64_t rem = sig & ((1ull << drop) - 1), half = 1ull << (drop - 1);
+        if (rem > half || (rem == half && (q & 1))) ++q;
+    }
+    const double r = std::ldexp((double)q, qe);
+    *out = std::copysign(r, x);
+    return r <= 3.3895313892515355e38;        // largest finite bfloat16, (2 - 2^-7) * 2^127
+}
+
+// Rounds n values to `storage`; on overflow returns the first bad position.
+int64_t round_values(spw_dtype storage, int64_t n, const double *in, double *out)
+{
+    std::vector<int64_t> bad(16, -1);
+    const int64_t per = (n + 15) / 16;
+    std::vector<std::thread> th;
+    for (int t = 0; t < 16; ++t) {
+        const int64_t a = t * per, b = std::min(n, a + per);
+        if (a >= b) break;
+        th.emplace_back([&, t, a, b] {
+            for (int64_t p = a; p < b; ++p) {
+                double r = in[p];
+                const bool ok = storage == SPW_F32 ? round_f32(in[p], &r)
+                                                   : storage == SPW_BF16 ? round_bf16(in[p], &r) : true;
+                out[p] = r;
+                if (!ok && bad[(size_t)t] < 0) bad[(size_t)t] = p;
+            }
+        });
+    }
+    for (auto &t : th) t.join();
+    for (int64_t v : bad)
+        if (v >= 0) return v;
+    return -1;
+}
+
+// Writes rounded value r (exactly representable in `storage`) at element slot.
+void put_value(spw_dtype storage, void *base, int64_t slot, double r)
+{
+    if (storage == SPW_F64) {
+        static_cast<double *>(base)[slot] = r;
+    } else if (storage == SPW_F32) {
+        static_cast<float *>(base)[slot] = (float)r;
+    } else {
+        const float f = (float)r;
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        static_cast<uint16_t *>(base)[slot] = (uint16_t)(u >> 16);
+    }
+}
+
 struct DeviceGuard {
     int prev = -1;
     bool changed = false;
@@ -152,7 +238,7 @@ struct DeviceGuard {
 // Column-dot storage of a rows x cols CSC matrix (ptr over columns, rows[]
 // already in the numbering the kernel will use).
 spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, const int64_t *ptr,
-                        const int32_t *rowi, const double *val)
+                        const int32_t *rowi, const double *val, spw_dtype storage)
 {
     const int64_t nnz = ptr[cols];
     C.rows = rows;
@@ -198,13 +284,14 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
         C.d_idx = d;
     }
     {
-        std::vector<double> vi((size_t)zpad, 0.0);
+        const int64_t es = storage_bytes(storage), G = 16 / es;
+        std::vector<uint8_t> vi((size_t)(zpad * es), 0);
         parallel_for(nnz, [&](int64_t a, int64_t b) {
-            for (int64_t p = a; p < b; ++p) vi[(size_t)ilv(p, 2)] = val[p];
+            for (int64_t p = a; p < b; ++p) put_value(storage, vi.data(), ilv(p, G), val[p]);
         });
-        double *d = nullptr;
-        if ((st = dev_alloc(A, &d, zpad, "values"))) return st;
-        if ((st = h2d(d, vi.data(), (size_t)zpad * 8, "values"))) return st;
+        uint8_t *d = nullptr;
+        if ((st = dev_alloc(A, &d, zpad * es, "values"))) return st;
+        if ((st = h2d(d, vi.data(), vi.size(), "values"))) return st;
         C.d_val = d;
     }
     build_zone_plan(cols, ptr, WCH, C.zp);
@@ -237,6 +324,8 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
 spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *rowi, const double *val,
                             int64_t panel_rows_opt)
 {
+    const spw_dtype storage = A.value_storage;
+    const int64_t es = storage_bytes(storage), GV = 16 / es;
     const int64_t rows = A.rows, cols = A.cols, nnz = A.nnz;
     const int64_t BLK = mv_block_nnz();
     const int64_t NB = mv_waves();
@@ -371,7 +460,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
                 const int32_t jj = l / 64, ln = l % 64;
                 cb.packed[((jj / 4) * 64 + ln) * 4 + jj % 4] =
                     ((uint32_t)(r - (int64_t)g.panel * R) << 16) | (uint32_t)(j - cb.col_base);
-                cb.val[((jj / 2) * 64 + ln) * 2 + jj % 2] = val[sp];
+                cb.val[((jj / GV) * 64 + ln) * GV + jj % GV] = val[sp];
             }
         }
     });
@@ -388,7 +477,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
     if (nblk * BLK >= ((int64_t)1 << 31)) return fail(SPW_ERR_UNSUPPORTED, "scatter-product storage exceeds 2^31 slots");
     const int64_t nslots = std::max<int64_t>(nblk, 1) * BLK;
     std::vector<uint32_t> packed((size_t)nslots, 0u);
-    std::vector<double> mval((size_t)nslots, 0.0);
+    std::vector<uint8_t> mval((size_t)(nslots * es), 0);
     std::vector<int32_t> bdesc((size_t)(2 * std::max<int64_t>(nblk, 1)), 0);
     parallel_for(W, [&](int64_t wa, int64_t wb) {
         for (int64_t w = wa; w < wb; ++w)
@@ -398,7 +487,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
                     bdesc[(size_t)(2 * id)] = bk.col_base;
                     bdesc[(size_t)(2 * id + 1)] = bk.count;
                     std::memcpy(&packed[(size_t)(id * BLK)], bk.packed, (size_t)BLK * sizeof(uint32_t));
-                    std::memcpy(&mval[(size_t)(id * BLK)], bk.val, (size_t)BLK * sizeof(double));
+                    for (int64_t q = 0; q < BLK; ++q) put_value(storage, mval.data(), id * BLK + q, bk.val[q]);
                     ++id;
                 }
             }
@@ -409,8 +498,12 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
     spw_status st;
     if ((st = dev_alloc(A, &A.d_mpacked, nslots, "block words"))) return st;
     if ((st = h2d(A.d_mpacked, packed.data(), (size_t)nslots * 4, "block words"))) return st;
-    if ((st = dev_alloc(A, &A.d_mval, nslots, "block values"))) return st;
-    if ((st = h2d(A.d_mval, mval.data(), (size_t)nslots * 8, "block values"))) return st;
+    {
+        uint8_t *d = nullptr;
+        if ((st = dev_alloc(A, &d, nslots * es, "block values"))) return st;
+        if ((st = h2d(d, mval.data(), mval.size(), "block values"))) return st;
+        A.d_mval = d;
+    }
     if ((st = dev_alloc(A, &A.d_mblocks, (int64_t)bdesc.size(), "block table"))) return st;
     if ((st = h2d(A.d_mblocks, bdesc.data(), bdesc.size() * 4, "block table"))) return st;
     if ((st = dev_alloc(A, &A.d_wg_blk, std::max<int64_t>((int64_t)wg_blk.size(), 1), "workgroup table"))) return st;
@@ -507,8 +600,8 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
             return fail(SPW_ERR_INVALID_ARG, "spw_create: opts.struct_size must be sizeof(spw_create_opts)");
         opts = *opts_in;
     }
-    if (opts.value_storage != SPW_F64)
-        return fail(SPW_ERR_UNSUPPORTED, "spw_create: value_storage other than F64 is not available yet");
+    if (opts.value_storage != SPW_F64 && opts.value_storage != SPW_F32 && opts.value_storage != SPW_BF16)
+        return fail(SPW_ERR_INVALID_ARG, "spw_create: bad value_storage");
     const int64_t chunk = opts.chunk_nnz > 0 ? opts.chunk_nnz : vtm_chunk_default();
     if (chunk != vtm_chunk_default())
         return fail(SPW_ERR_UNSUPPORTED, "spw_create: chunk_nnz must be " + std::to_string(vtm_chunk_default()));
@@ -523,6 +616,17 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
         if (st) return st;
     } else if (ptr[cols] != nnz) {
         return fail(SPW_ERR_BAD_MATRIX, "ptr[last] must equal nnz");
+    }
+
+    // values as stored (rounded once), promoted back to binary64 for the builders
+    std::vector<double> rounded;
+    if (opts.value_storage != SPW_F64 && nnz > 0) {
+        rounded.resize((size_t)nnz);
+        const int64_t bad = round_values(opts.value_storage, nnz, val, rounded.data());
+        if (bad >= 0)
+            return fail(SPW_ERR_BAD_MATRIX, "position " + std::to_string(bad) + ": value " + std::to_string(val[bad]) +
+                                                " overflows the value storage type");
+        val = rounded.data();
     }
 
     DeviceGuard dg(opts.device);
@@ -572,7 +676,7 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
             for (int64_t p = a; p < b; ++p) rowi[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
         });
     }
-    if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val))) return st;
+    if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val, A->value_storage))) return st;
 
     // The transpose (caller's numbering), used by the multi-RHS scatter
     // products: its column dots are the rows of B.
@@ -591,7 +695,8 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
                     tval[(size_t)dst] = val[p];
                 }
         }
-        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data()))) return st;
+        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data(), A->value_storage)))
+            return st;
     }
 
     // Scatter-product storage.
@@ -664,17 +769,14 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     spw_status st = alloc_scratch(*A, k);
     if (st) return st;
     int e;
-    if (k == 1 && ldi == 1 && ldo == 1 && vdt == SPW_F64) {
-        e = scatter ? launch_mv(*A, vdt, k, in, ldi, out, ldo, stream) : launch_vtm(*A, vdt, k, in, ldi, out, ldo, stream);
-    } else if (scatter && vdt == SPW_F64 && (k <= 4 || !A->cdt.built)) {
-        // few binary64 right-hand sides: one scatter pass per column (reads A
-        // k times, x once per column) beats gathering rows of X per nonzero
+    if (k == 1 && ldi == 1 && ldo == 1) {
+        e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
+    } else if (scatter && (k <= 4 || !A->cdt.built)) {
+        // few right-hand sides (or no transpose kept): one scatter pass per
+        // column, which reads A k times but gathers x once per nonzero
         e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
     } else if (scatter) {
         // k right-hand sides in one pass: column dots over the kept transpose
-        if (!A->cdt.built && A->nnz > 0)
-            return fail(SPW_ERR_UNSUPPORTED, std::string(fname) +
-                                                 ": this form needs the transpose (spw_create_opts.transpose = 0 dropped it)");
         if (A->nnz == 0) {
             e = launch_zero_fill(vdt, k, out, ldo, A->rows, stream);   // no nonzeros: all outputs are zero
         } else {
@@ -709,6 +811,17 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
                          void *stream)
 {
     return run_product(A, false, vdt, k, V, ldv, U, ldu, stream, "spw_vtm_batch");
+}
+
+spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, double *out)
+{
+    if (storage != SPW_F64 && storage != SPW_F32 && storage != SPW_BF16)
+        return fail(SPW_ERR_INVALID_ARG, "spw_round_values: bad storage type");
+    if (n < 0 || (n > 0 && (!in || !out))) return fail(SPW_ERR_INVALID_ARG, "spw_round_values: bad argument");
+    const int64_t bad = round_values(storage, n, in, out);
+    if (bad >= 0)
+        return fail(SPW_ERR_BAD_MATRIX, "position " + std::to_string(bad) + ": value overflows the storage type");
+    return SPW_OK;
 }
 
 spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int64_t *n_chunks, int64_t *n_zones,

@@ -49,9 +49,9 @@ struct PanelDesc {
 enum class IdxKind : int32_t { U16 = 0, I32 = 1 };
 
 // Column-dot storage of a short-by-long CSC matrix: int32 column starts (plus
-// a padding window), 2- or 4-byte rows and binary64 values, both interleaved
-// inside each chunk (see the column-dot kernel), the chunk/zone plan and the
-// columns without nonzeros.
+// a padding window), 2- or 4-byte rows and values in the storage type (8, 4
+// or 2 bytes), both interleaved inside each chunk (see the column-dot kernel),
+// the chunk/zone plan and the columns without nonzeros.
 struct ColDot {
     int64_t rows = 0, cols = 0, nnz = 0;
     IdxKind idx_kind = IdxKind::U16;
@@ -70,7 +70,7 @@ struct ColDot {
 struct Scratch {
     double *partial = nullptr;    // mv_wgs * panel_rows * kcap  (binary64 partial sums)
     double *carry = nullptr;      // 2 * max chunks * kcap
-    double *vperm = nullptr;      // rows * kcap  (renumbered input of the column dots)
+    double *vperm = nullptr;      // rows * kcap elements of 8 bytes (renumbered input of the column dots)
     int32_t kcap = 0;
 };
 
@@ -93,7 +93,7 @@ struct spw_matrix_s {
     // range and per wave (a set of the panel's rows), blocks of 512 nonzeros
     int64_t panel_rows = 0, n_panels = 0;
     uint32_t *d_mpacked = nullptr;      // (panel-local row << 16) | (column - block column base)
-    double *d_mval = nullptr;
+    void *d_mval = nullptr;             // values in the storage type, interleaved like d_mpacked
     int32_t *d_mblocks = nullptr;       // per block: column base, count
     int32_t *d_wg_blk = nullptr;        // per workgroup: waves+1 offsets into the blocks
     int64_t n_mblocks = 0;
@@ -111,8 +111,9 @@ namespace spw {
 // ------------------------------------------------------------ launch glue
 // All return hipError_t as int (0 = success).  Implemented in spw_kernels.hip.
 
-int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv,
-               void *u, int64_t ldu, void *stream);
+// Single-vector column dots (u = B^T v) over A.cd.
+int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, const void *v, void *u, void *stream);
+// Scatter product y = B x, k times over strided columns of X (ldx) and Y (ldy).
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
               void *y, int64_t ldy, void *stream);
 // Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
@@ -126,7 +127,7 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
 int64_t mv_block_nnz();
 int64_t mv_waves();
 int64_t vtm_chunk_default();
-int64_t vtm_hot_rows_limit();
+int64_t vtm_hot_rows_limit(spw_dtype vdt);
 int64_t vtm_slice_window();
 int device_cu_count(int device);
 

@@ -43,6 +43,86 @@ constexpr int WAVE = 64;
 // Native vector types: non-temporal loads need them.
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// A stored bfloat16 value: the high half of a binary32 number.
+struct Bf16 {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ double bf16_bits_to_f64(uint32_t h) { return (double)__uint_as_float(h << 16); }
+
+// Elements per 16 bytes of a stored value type.
+template <typename ValT> struct ValGroup;
+template <> struct ValGroup<double> {
+    static constexpr int G = 2;
+};
+template <> struct ValGroup<float> {
+    static constexpr int G = 4;
+};
+template <> struct ValGroup<Bf16> {
+    static constexpr int G = 8;
+};
+
+// One stored value, promoted exactly to binary64.
+__device__ __forceinline__ double val_at(const double *v, int64_t s) { return v[s]; }
+__device__ __forceinline__ double val_at(const float *v, int64_t s) { return (double)v[s]; }
+__device__ __forceinline__ double val_at(const Bf16 *v, int64_t s) { return bf16_bits_to_f64(v[s].bits); }
+
+// N stored values of one lane from an interleaved run: 16-byte group g of
+// lane l sits at byte (g*64 + l)*16.  get() promotes exactly to binary64; all
+// accumulation is binary64.
+template <typename ValT, int N> struct ValRaw;
+template <int N> struct ValRaw<double, N> {
+    double a[N];
+    __device__ __forceinline__ void load(const double *base, int lane)
+    {
+#pragma unroll
+        for (int g = 0; g < N / 2; ++g) {
+            const f64x2_t w =
+                __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(base + (int64_t)(g * 64 + lane) * 2));
+            a[2 * g] = w.x;
+            a[2 * g + 1] = w.y;
+        }
+    }
+    __device__ __forceinline__ double get(int i) const { return a[i]; }
+};
+template <int N> struct ValRaw<float, N> {
+    float a[N];
+    __device__ __forceinline__ void load(const float *base, int lane)
+    {
+#pragma unroll
+        for (int g = 0; g < N / 4; ++g) {
+            const f32x4_t w =
+                __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(base + (int64_t)(g * 64 + lane) * 4));
+            a[4 * g] = w.x;
+            a[4 * g + 1] = w.y;
+            a[4 * g + 2] = w.z;
+            a[4 * g + 3] = w.w;
+        }
+    }
+    __device__ __forceinline__ double get(int i) const { return (double)a[i]; }
+};
+template <int N> struct ValRaw<Bf16, N> {
+    uint32_t w[N / 2];
+    __device__ __forceinline__ void load(const Bf16 *base, int lane)
+    {
+        const uint16_t *b = reinterpret_cast<const uint16_t *>(base);
+#pragma unroll
+        for (int g = 0; g < N / 8; ++g) {
+            const u32x4_t q =
+                __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(b + (int64_t)(g * 64 + lane) * 8));
+            w[4 * g] = q.x;
+            w[4 * g + 1] = q.y;
+            w[4 * g + 2] = q.z;
+            w[4 * g + 3] = q.w;
+        }
+    }
+    __device__ __forceinline__ double get(int i) const
+    {
+        return bf16_bits_to_f64((w[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu);
+    }
+};
 
 // All lanes of the wave see each other's LDS writes after this point.  Only
 // the LDS counter is waited on, so loads of later data stay in flight (a wave's
@@ -146,9 +226,9 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 // Reduces one chunk whose products are in `prod` (lane-owned positions
 // p0 .. p0+ITEMS-1): cs[k] is the start of column jlo+k.  Inlined twice, with
 // cs in LDS or in global memory, so that each copy uses the matching loads.
-template <int ITEMS>
+template <int ITEMS, typename VecT>
 __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double *prod, int s, int e, int jlo,
-                                                 int ncol, int64_t c, int lane, double *__restrict__ u,
+                                                 int ncol, int64_t c, int lane, VecT *__restrict__ u,
                                                  double *__restrict__ carry)
 {
     const int p0 = s + lane * ITEMS;
@@ -175,7 +255,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
                         hk = k;
                         multi = true;
                     } else {
-                        u[jlo + k] = run;        // column wholly inside this lane
+                        u[jlo + k] = (VecT)run;  // column wholly inside this lane
                     }
                     do {
                         ++k;
@@ -201,7 +281,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
             const bool before = cs[kk] < s, after = cs[kk + 1] > e;
             if (before) carry[2 * c] = value;
             else if (after) carry[2 * c + 1] = value;
-            else u[jlo + kk] = value;
+            else u[jlo + kk] = (VecT)value;
         };
         if (multi) {
             // the lane's first column ends inside it: add what earlier lanes hold
@@ -213,25 +293,26 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
     }
 }
 
-template <typename IdxT, int ITEMS, int SLW> struct VtmChunk {
-    double a[ITEMS];
+template <typename IdxT, typename ValT, int ITEMS, int SLW> struct VtmChunk {
+    ValRaw<ValT, ITEMS> a;
     IdxRaw<IdxT, ITEMS> r;
     int32_t sl[SLW];
 };
 
-template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT>
-__global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
-    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const double *__restrict__ val,
+template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT, typename ValT, typename VecT>
+__global__ __launch_bounds__(BLOCK) void vtm_wave(
+    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const ValT *__restrict__ val,
     const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks,
-    const double *__restrict__ v, int vhot, double *__restrict__ u, double *__restrict__ carry)
+    const VecT *__restrict__ v, int vhot, VecT *__restrict__ u, double *__restrict__ carry)
 {
     constexpr int NW = BLOCK / WAVE;
     constexpr int WCH = WAVE * ITEMS;
     constexpr int SLW = SLICE_W / WAVE;
     extern __shared__ double lds[];
-    double *vh = lds;
+    VecT *vh = reinterpret_cast<VecT *>(lds);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    int32_t *slice = reinterpret_cast<int32_t *>(lds + vhot) + wave * SLICE_W;
+    const int hot_bytes = (vhot * (int)sizeof(VecT) + 15) & ~15;
+    int32_t *slice = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(lds) + hot_bytes) + wave * SLICE_W;
     const int lane = threadIdx.x & (WAVE - 1);
 
     for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
@@ -244,24 +325,18 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
     // Two chunk buffers used alternately (no register copies, so no wait for
     // data still in flight): while one chunk is reduced, the next one's
     // values, indices and column-start window are being fetched.
-    VtmChunk<IdxT, ITEMS, SLW> A, B;
-    auto load_chunk = [&](VtmChunk<IdxT, ITEMS, SLW> &C, int64_t cc, int jl) {
+    typedef VtmChunk<IdxT, ValT, ITEMS, SLW> Chunk;
+    Chunk A, B;
+    auto load_chunk = [&](Chunk &C, int64_t cc, int jl) {
         const int64_t cb = cc * WCH;
-#pragma unroll
-        for (int q = 0; q < ITEMS / 2; ++q) {
-            const f64x2_t w = __builtin_nontemporal_load(
-                reinterpret_cast<const f64x2_t *>(val + cb + (int64_t)(q * WAVE + lane) * 2));
-            C.a[2 * q] = w.x;
-            C.a[2 * q + 1] = w.y;
-        }
+        C.a.load(val + cb, lane);
         C.r.load(idx + cb, lane);
 #pragma unroll
         for (int t = 0; t < SLW; ++t) C.sl[t] = ptr[jl + lane + t * WAVE];
     };
     // Reduces chunk cc held in C, after issuing the loads of chunk cn into N
     // (when cn < nchunks).  jlo/jhi describe cc, jln describes cn.
-    auto step = [&](VtmChunk<IdxT, ITEMS, SLW> &C, VtmChunk<IdxT, ITEMS, SLW> &N, int64_t cc, int jlo, int jhi,
-                    int64_t cn, int jln) {
+    auto step = [&](Chunk &C, Chunk &N, int64_t cc, int jlo, int jhi, int64_t cn, int jln) {
         const int s = (int)(cc * WCH);
         const int e = (int)min((int64_t)s + WCH, nnz);
         const int ncol = jhi - jlo + 2;           // starts of columns jlo .. jhi+1
@@ -275,10 +350,10 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
             // selected pointer would become a flat load, which waits for every
             // outstanding load)
             const int ri = C.r.get(i);
-            const double lv = vh[min(ri, vhot - 1)];
-            double gv = 0.0;
+            const VecT lv = vh[min(ri, vhot - 1)];
+            VecT gv = 0;
             if (ri >= vhot) gv = v[ri];
-            prod[i] = C.a[i] * (ri < vhot ? lv : gv);
+            prod[i] = C.a.get(i) * (double)(ri < vhot ? lv : gv);
         }
         // The gathers must land before the next chunk's loads are issued: the
         // load counter is in order, so waiting for them later would also wait
@@ -286,8 +361,8 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
         __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
         if (cn < nchunks) load_chunk(N, cn, jln);
         wave_sync();
-        if (in_lds) vtm_reduce_chunk<ITEMS>(slice, prod, s, e, jlo, ncol, cc, lane, u, carry);
-        else vtm_reduce_chunk<ITEMS>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, u, carry);
+        if (in_lds) vtm_reduce_chunk<ITEMS, VecT>(slice, prod, s, e, jlo, ncol, cc, lane, u, carry);
+        else vtm_reduce_chunk<ITEMS, VecT>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, u, carry);
         wave_sync();                              // slice reads done before it is rewritten
     };
 
@@ -315,29 +390,32 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave_f64(
 }
 
 // Columns without nonzeros: u_j = 0.
-__global__ void zero_cols_f64(const int32_t *__restrict__ cols, int64_t count, double *__restrict__ u)
+template <typename VecT>
+__global__ void zero_cols(const int32_t *__restrict__ cols, int64_t count, VecT *__restrict__ u)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < count) u[cols[i]] = 0.0;
+    if (i < count) u[cols[i]] = (VecT)0;
 }
 
 // Zone reduction: u[j_k] = right carry of the first chunk + left carries of the
 // following chunks of S_k, in ascending chunk order.
-__global__ void zone_fixup_f64(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
-                               const int32_t *__restrict__ zlast, int64_t nz,
-                               const double *__restrict__ carry, double *__restrict__ u)
+template <typename VecT>
+__global__ void zone_fixup(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
+                           const int32_t *__restrict__ zlast, int64_t nz, const double *__restrict__ carry,
+                           VecT *__restrict__ u)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= nz) return;
     const int a = zfirst[k], b = zlast[k];
     double s = carry[2 * a + 1];
     for (int c = a + 1; c <= b; ++c) s += carry[2 * c];
-    u[zcol[k]] = s;
+    u[zcol[k]] = (VecT)s;
 }
 
 // Renumber a short vector: out[r] = in[inv[r]].
-__global__ void gather_f64(const int32_t *__restrict__ inv, int64_t len, const double *__restrict__ in,
-                           double *__restrict__ out)
+template <typename VecT>
+__global__ void gather_vec(const int32_t *__restrict__ inv, int64_t len, const VecT *__restrict__ in,
+                           VecT *__restrict__ out)
 {
     const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r < len) out[r] = in[inv[r]];
@@ -363,14 +441,15 @@ __global__ void gather_f64(const int32_t *__restrict__ inv, int64_t len, const d
 constexpr int MV_ITEMS = 16;
 constexpr int MV_BLK = WAVE * MV_ITEMS;
 
-struct MvBlk {
+template <typename ValT> struct MvBlk {
     uint32_t w[MV_ITEMS];
-    double a[MV_ITEMS];
+    ValRaw<ValT, MV_ITEMS> a;
     int2 bd;
 };
 
-__device__ __forceinline__ void mv_load(MvBlk &B, const uint32_t *__restrict__ packed, const double *__restrict__ val,
-                                        const int2 *__restrict__ blocks, int b, int lane)
+template <typename ValT>
+__device__ __forceinline__ void mv_load(MvBlk<ValT> &B, const uint32_t *__restrict__ packed,
+                                        const ValT *__restrict__ val, const int2 *__restrict__ blocks, int b, int lane)
 {
     B.bd = blocks[b];
     const int64_t base = (int64_t)b * MV_BLK;
@@ -383,19 +462,13 @@ __device__ __forceinline__ void mv_load(MvBlk &B, const uint32_t *__restrict__ p
         B.w[4 * g + 2] = q.z;
         B.w[4 * g + 3] = q.w;
     }
-#pragma unroll
-    for (int g = 0; g < MV_ITEMS / 2; ++g) {
-        const f64x2_t d =
-            __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(val + base + (int64_t)(g * 64 + lane) * 2));
-        B.a[2 * g] = d.x;
-        B.a[2 * g + 1] = d.y;
-    }
+    B.a.load(val + base, lane);
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
-    const uint32_t *__restrict__ packed, const double *__restrict__ val, const int2 *__restrict__ blocks,
-    const int32_t *__restrict__ wg_blk, const double *__restrict__ x, int64_t ldx, double *__restrict__ partial,
+template <int BLOCK, typename ValT, typename VecT>
+__global__ __launch_bounds__(BLOCK) void mv_bucket(
+    const uint32_t *__restrict__ packed, const ValT *__restrict__ val, const int2 *__restrict__ blocks,
+    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, double *__restrict__ partial,
     int panel_rows)
 {
     constexpr int NW = BLOCK / WAVE;
@@ -409,17 +482,17 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
     // Two block buffers used alternately (no register copies, so no wait for
     // data still in flight): while block b is added, the x entries of block
     // b+1 and the words/values of block b+2 are being fetched.
-    MvBlk B0, B1;
-    double x0[MV_ITEMS], x1[MV_ITEMS];
+    MvBlk<ValT> B0, B1;
+    VecT x0[MV_ITEMS], x1[MV_ITEMS];
     // padding slots hold word 0, so their gather reads x[column base]: no branch
-    auto gather = [&](const MvBlk &B, double *xv) {
+    auto gather = [&](const MvBlk<ValT> &B, VecT *xv) {
 #pragma unroll
         for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[(int64_t)(B.bd.x + (int)(B.w[j] & 0xFFFFu)) * ldx];
     };
-    auto add_block = [&](const MvBlk &B, const double *xv, double *p, uint32_t *row) {
+    auto add_block = [&](const MvBlk<ValT> &B, const VecT *xv, double *p, uint32_t *row) {
 #pragma unroll
         for (int j = 0; j < MV_ITEMS; ++j) {
-            p[j] = B.a[j] * xv[j];
+            p[j] = B.a.get(j) * (double)xv[j];
             row[j] = B.w[j] >> 16;
         }
     };
@@ -462,9 +535,9 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket_f64(
 // lanes share a row: lane t adds workgroups t, t+8, t+16, ... in ascending
 // order, then the eight sums are combined by a fixed butterfly, so the order
 // of every addition is fixed.
-__global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows,
-                              const PanelDesc *__restrict__ panels, int64_t rows,
-                              const int32_t *__restrict__ inv, double *__restrict__ y, int64_t ldy)
+template <typename VecT>
+__global__ void mv_reduce(const double *__restrict__ partial, int panel_rows, const PanelDesc *__restrict__ panels,
+                          int64_t rows, const int32_t *__restrict__ inv, VecT *__restrict__ y, int64_t ldy)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t r = g >> 3;
@@ -481,7 +554,7 @@ __global__ void mv_reduce_f64(const double *__restrict__ partial, int panel_rows
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
     s += __shfl_xor(s, 4, 8);
-    if (live && t == 0) y[(int64_t)(inv ? inv[r] : r) * ldy] = s;
+    if (live && t == 0) y[(int64_t)(inv ? inv[r] : r) * ldy] = (VecT)s;
 }
 
 // ------------------------------------------------------------------------
@@ -503,13 +576,13 @@ template <> struct IdxSlot<int32_t> {
     static constexpr int G = 4;
 };
 
-template <typename IdxT, int L, typename VinT, typename VoutT>
+template <typename IdxT, int L, typename ValT, typename VinT, typename VoutT>
 __global__ __launch_bounds__(L * (L <= 8 ? 64 : 512 / L)) void coldot_batch(
-    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const double *__restrict__ val,
+    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const ValT *__restrict__ val,
     const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks, int k,
     const VinT *__restrict__ V, int64_t ldv, VoutT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
 {
-    constexpr int WCH = 1024, ITEMS = 16, GI = IdxSlot<IdxT>::G;
+    constexpr int WCH = 1024, ITEMS = 16, GI = IdxSlot<IdxT>::G, GV = ValGroup<ValT>::G;
     constexpr int GPB = L <= 8 ? 64 : 512 / L;    // groups per workgroup
     constexpr int SL = 128;                       // column starts kept in LDS per group
     constexpr int T = L >= 8 ? L : 8;             // positions a group fetches per step
@@ -552,7 +625,7 @@ __global__ __launch_bounds__(L * (L <= 8 ? 64 : 512 / L)) void coldot_batch(
                 r[q] = 0;
                 if (pp < e) {
                     const int o = pp - s, ln = o / ITEMS, i = o % ITEMS;
-                    a[q] = val[s + ((i >> 1) * 64 + ln) * 2 + (i & 1)];
+                    a[q] = val_at(val, s + ((i / GV) * 64 + ln) * GV + i % GV);
                     r[q] = (int)idx[s + ((i / GI) * 64 + ln) * GI + i % GI];
                 }
             }
@@ -621,13 +694,13 @@ __global__ void zero_cols_batch(const int32_t *__restrict__ cols, int64_t count,
 // Renumber the rows of a k-wide block: out[r*k + c] = in[inv[r]*ldv + c].
 template <typename VinT>
 __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k, const VinT *__restrict__ in,
-                            int64_t ldv, double *__restrict__ out)
+                            int64_t ldv, VinT *__restrict__ out)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= rows * k) return;
     const int64_t r = g / k;
     const int cc = (int)(g - r * k);
-    out[g] = (double)in[(int64_t)inv[r] * ldv + cc];
+    out[g] = in[(int64_t)inv[r] * ldv + cc];
 }
 
 constexpr int VTM_BLOCK = 512;
@@ -652,9 +725,112 @@ struct ProfScope {
 };
 
 template <typename K>
-void allow_full_lds(K kernel)
+bool allow_full_lds(K kernel)
 {
     (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    return true;
+}
+
+// Calls fn(ValT(), VecT()) for the stored value type and the vector type.
+template <typename Fn>
+int with_types(spw_dtype storage, spw_dtype vdt, Fn &&fn)
+{
+    const bool v64 = vdt == SPW_F64;
+    switch (storage) {
+    case SPW_F64: return v64 ? fn(double(), double()) : fn(double(), float());
+    case SPW_F32: return v64 ? fn(float(), double()) : fn(float(), float());
+    case SPW_BF16: return v64 ? fn(Bf16(), double()) : fn(Bf16(), float());
+    }
+    return (int)hipErrorNotSupported;
+}
+
+int64_t hot_rows_limit(size_t vec_bytes)
+{
+    return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / (int64_t)vec_bytes;
+}
+
+template <typename ValT, typename VecT>
+int vtm_typed(const spw_matrix_s &A, const VecT *v, VecT *u, hipStream_t stream)
+{
+    const ColDot &C = A.cd;
+    int e;
+    if (C.cols == 0) return 0;
+    if (C.n_empty > 0) {
+        ProfScope ps(stream, "zero_cols");
+        hipLaunchKernelGGL(zero_cols<VecT>, dim3(blocks_for(C.n_empty, 256)), dim3(256), 0, stream, C.d_empty,
+                           C.n_empty, u);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (C.nnz == 0) return 0;
+    const VecT *vin = v;
+    if (A.relabeled) {
+        ProfScope ps(stream, "gather_vec");
+        VecT *vp = reinterpret_cast<VecT *>(A.scratch.vperm);
+        hipLaunchKernelGGL(gather_vec<VecT>, dim3(blocks_for(A.rows, 256)), dim3(256), 0, stream, A.d_inv, A.rows, v,
+                           vp);
+        if ((e = (int)hipGetLastError())) return e;
+        vin = vp;
+    }
+    {
+        ProfScope ps(stream, "vtm_wave");
+        if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
+        const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT)));
+        const size_t lds = (((size_t)vhot * sizeof(VecT) + 15) & ~(size_t)15) + (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
+        const int cus = device_cu_count(A.device);
+        const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
+        static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t, ValT, VecT>) &&
+                                 allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t, ValT, VecT>);
+        (void)attr;
+        if (C.idx_kind == IdxKind::U16)
+            hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t, ValT, VecT>), dim3(grid),
+                               dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const uint16_t *)C.d_idx,
+                               (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz, C.zp.n_chunks, vin, vhot, u,
+                               A.scratch.carry);
+        else
+            hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t, ValT, VecT>), dim3(grid),
+                               dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const int32_t *)C.d_idx,
+                               (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz, C.zp.n_chunks, vin, vhot, u,
+                               A.scratch.carry);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (C.n_zones > 0) {
+        ProfScope ps(stream, "zone_fixup");
+        hipLaunchKernelGGL(zone_fixup<VecT>, dim3(blocks_for(C.n_zones, 256)), dim3(256), 0, stream, C.d_zone_col,
+                           C.d_zone_first, C.d_zone_last, C.n_zones, A.scratch.carry, u);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    return 0;
+}
+
+// k right-hand sides run as k passes of the scatter kernel over strided
+// columns of X and Y.
+template <typename ValT, typename VecT>
+int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT *y, int64_t ldy, hipStream_t stream)
+{
+    if (A.rows == 0) return 0;
+    static const bool attr = allow_full_lds(mv_bucket<MV_BLOCK, ValT, VecT>);
+    (void)attr;
+    int e;
+    for (int32_t c = 0; c < k; ++c) {
+        if (A.mv_wgs > 0) {
+            ProfScope ps(stream, "mv_bucket");
+            const size_t lds = (size_t)A.panel_rows * 8;
+            hipLaunchKernelGGL((mv_bucket<MV_BLOCK, ValT, VecT>), dim3((unsigned)A.mv_wgs), dim3(MV_BLOCK), lds,
+                               stream, (const uint32_t *)A.d_mpacked, (const ValT *)A.d_mval,
+                               (const int2 *)A.d_mblocks, A.d_wg_blk, x + c, ldx, A.scratch.partial,
+                               (int)A.panel_rows);
+            if ((e = (int)hipGetLastError())) return e;
+        }
+        {
+            ProfScope ps(stream, "mv_reduce");
+            hipLaunchKernelGGL(mv_reduce<VecT>, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream,
+                               A.scratch.partial, (int)A.panel_rows, A.d_panels, A.rows,
+                               A.relabeled ? A.d_inv : nullptr, y + c, ldy);
+            if ((e = (int)hipGetLastError())) return e;
+        }
+    }
+    return 0;
 }
 
 }  // namespace
@@ -668,7 +844,7 @@ int64_t mv_block_nnz() { return MV_BLK; }
 int64_t mv_waves() { return MV_BLOCK / WAVE; }
 int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
 int64_t vtm_slice_window() { return VTM_SLICE_W; }
-int64_t vtm_hot_rows_limit() { return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / 8; }
+int64_t vtm_hot_rows_limit(spw_dtype vdt) { return hot_rows_limit(vdt == SPW_F64 ? 8 : 4); }
 
 int device_cu_count(int device)
 {
@@ -677,105 +853,27 @@ int device_cu_count(int device)
     return cus > 0 ? cus : 256;
 }
 
-int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv, void *u,
-               int64_t ldu, void *stream_)
+int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, const void *v, void *u, void *stream)
 {
-    hipStream_t stream = (hipStream_t)stream_;
-    if (vdt != SPW_F64 || k != 1 || ldv != 1 || ldu != 1 || A.value_storage != SPW_F64)
-        return (int)hipErrorNotSupported;
-    double *uo = (double *)u;
-    if (A.cd.cols == 0) return 0;
-    if (A.cd.n_empty > 0) {
-        ProfScope ps(stream, "zero_cols_f64");
-        hipLaunchKernelGGL(zero_cols_f64, dim3(blocks_for(A.cd.n_empty, 256)), dim3(256), 0, stream, A.cd.d_empty,
-                           A.cd.n_empty, uo);
-        int e = (int)hipGetLastError();
-        if (e) return e;
-    }
-    if (A.cd.nnz == 0) return 0;
-    const double *vin = (const double *)v;
-    if (A.relabeled) {
-        ProfScope ps(stream, "gather_f64");
-        hipLaunchKernelGGL(gather_f64, dim3(blocks_for(A.rows, 256)), dim3(256), 0, stream, A.d_inv, A.rows,
-                           vin, A.scratch.vperm);
-        vin = A.scratch.vperm;
-    }
-    {
-        ProfScope ps(stream, "vtm_wave_f64");
-        if (A.cd.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
-        const int vhot = (int)std::min<int64_t>(A.rows, vtm_hot_rows_limit());
-        const size_t lds = (size_t)vhot * 8 + (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
-        const int cus = device_cu_count(A.device);
-        const int64_t wgs_needed = (A.cd.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
-        static bool attr = false;
-        if (!attr) {
-            allow_full_lds(vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t>);
-            allow_full_lds(vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>);
-            attr = true;
-        }
-        if (A.cd.idx_kind == IdxKind::U16)
-            hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, A.cd.d_ptr, (const uint16_t *)A.cd.d_idx,
-                               (const double *)A.cd.d_val, A.cd.d_cjlo, A.cd.d_cjhi, A.cd.nnz, A.cd.zp.n_chunks, vin, vhot, uo,
-                               A.scratch.carry);
-        else
-            hipLaunchKernelGGL((vtm_wave_f64<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, A.cd.d_ptr, (const int32_t *)A.cd.d_idx,
-                               (const double *)A.cd.d_val, A.cd.d_cjlo, A.cd.d_cjhi, A.cd.nnz, A.cd.zp.n_chunks, vin, vhot, uo,
-                               A.scratch.carry);
-        int e = (int)hipGetLastError();
-        if (e) return e;
-    }
-    if (A.cd.n_zones > 0) {
-        ProfScope ps(stream, "zone_fixup_f64");
-        hipLaunchKernelGGL(zone_fixup_f64, dim3(blocks_for(A.cd.n_zones, 256)), dim3(256), 0, stream, A.cd.d_zone_col,
-                           A.cd.d_zone_first, A.cd.d_zone_last, A.cd.n_zones, A.scratch.carry, uo);
-        int e = (int)hipGetLastError();
-        if (e) return e;
-    }
-    return 0;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        return vtm_typed<ValT, VecT>(A, (const VecT *)v, (VecT *)u, (hipStream_t)stream);
+    });
 }
 
-int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx, void *y,
-              int64_t ldy, void *stream_)
+int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx, void *y, int64_t ldy,
+              void *stream)
 {
-    // k right-hand sides run as k passes of the scatter kernel over strided
-    // columns of X and Y (the multi-RHS path uses this for small k)
-    hipStream_t stream = (hipStream_t)stream_;
-    if (vdt != SPW_F64 || A.value_storage != SPW_F64) return (int)hipErrorNotSupported;
-    if (A.rows == 0) return 0;
-    static bool attr = false;
-    if (!attr) {
-        allow_full_lds(mv_bucket_f64<MV_BLOCK>);
-        attr = true;
-    }
-    for (int32_t c = 0; c < k; ++c) {
-        const double *xc = (const double *)x + c;
-        double *yc = (double *)y + c;
-        if (A.mv_wgs > 0) {
-            ProfScope ps(stream, "mv_bucket_f64");
-            const size_t lds = (size_t)A.panel_rows * 8;
-            hipLaunchKernelGGL((mv_bucket_f64<MV_BLOCK>), dim3((unsigned)A.mv_wgs), dim3(MV_BLOCK), lds, stream,
-                               (const uint32_t *)A.d_mpacked, (const double *)A.d_mval, (const int2 *)A.d_mblocks,
-                               A.d_wg_blk, xc, ldx, A.scratch.partial, (int)A.panel_rows);
-            int e = (int)hipGetLastError();
-            if (e) return e;
-        }
-        {
-            ProfScope ps(stream, "mv_reduce_f64");
-            hipLaunchKernelGGL(mv_reduce_f64, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream,
-                               A.scratch.partial, (int)A.panel_rows, A.d_panels, A.rows,
-                               A.relabeled ? A.d_inv : nullptr, yc, ldy);
-            int e = (int)hipGetLastError();
-            if (e) return e;
-        }
-    }
-    return 0;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        return mv_typed<ValT, VecT>(A, k, (const VecT *)x, ldx, (VecT *)y, ldy, (hipStream_t)stream);
+    });
 }
 
 namespace {
-template <typename IdxT, typename VinT, typename VoutT>
+template <typename IdxT, typename ValT, typename VinT, typename VoutT>
 int launch_batch_kernel(const ColDot &C, int L, int k, const VinT *V, int64_t ldv, VoutT *U, int64_t ldu,
                         double *carry, hipStream_t stream)
 {
@@ -784,8 +882,8 @@ int launch_batch_kernel(const ColDot &C, int L, int k, const VinT *V, int64_t ld
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16));
 #define SPW_BATCH_CASE(LL)                                                                                          \
     case LL:                                                                                                        \
-        hipLaunchKernelGGL((coldot_batch<IdxT, LL, VinT, VoutT>), dim3(grid), dim3(LL * gpb), 0, stream, C.d_ptr,  \
-                           (const IdxT *)C.d_idx, (const double *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz,             \
+        hipLaunchKernelGGL((coldot_batch<IdxT, LL, ValT, VinT, VoutT>), dim3(grid), dim3(LL * gpb), 0, stream,     \
+                           C.d_ptr, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz,      \
                            C.zp.n_chunks, k, V, ldv, U, ldu, carry);                                                \
         break;
     switch (L) {
@@ -802,14 +900,14 @@ int launch_batch_kernel(const ColDot &C, int L, int k, const VinT *V, int64_t ld
     return (int)hipGetLastError();
 }
 
-template <typename VinT, typename VoutT>
-int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VinT *V,
-                       int64_t ldv, VoutT *U, int64_t ldu, hipStream_t stream)
+template <typename ValT, typename VecT>
+int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VecT *V,
+                       int64_t ldv, VecT *U, int64_t ldu, hipStream_t stream)
 {
     int e;
     if (C.n_empty > 0) {
         ProfScope ps(stream, "zero_cols_batch");
-        hipLaunchKernelGGL(zero_cols_batch<VoutT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(zero_cols_batch<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
                            C.d_empty, C.n_empty, k, U, ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
@@ -818,25 +916,24 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
     while (L < k) L <<= 1;
     {
         ProfScope ps(stream, "coldot_batch");
+        const VecT *Vin = V;
+        int64_t ldin = ldv;
         if (inv) {
-            hipLaunchKernelGGL(gather_rows<VinT>, dim3(blocks_for(C.rows * k, 256)), dim3(256), 0, stream, inv,
-                               C.rows, k, V, ldv, A.scratch.vperm);
+            VecT *vp = reinterpret_cast<VecT *>(A.scratch.vperm);
+            hipLaunchKernelGGL(gather_rows<VecT>, dim3(blocks_for(C.rows * k, 256)), dim3(256), 0, stream, inv,
+                               C.rows, k, V, ldv, vp);
             if ((e = (int)hipGetLastError())) return e;
-            e = C.idx_kind == IdxKind::U16
-                    ? launch_batch_kernel<uint16_t, double, VoutT>(C, L, k, A.scratch.vperm, k, U, ldu,
-                                                                  A.scratch.carry, stream)
-                    : launch_batch_kernel<int32_t, double, VoutT>(C, L, k, A.scratch.vperm, k, U, ldu,
-                                                                 A.scratch.carry, stream);
-        } else {
-            e = C.idx_kind == IdxKind::U16
-                    ? launch_batch_kernel<uint16_t, VinT, VoutT>(C, L, k, V, ldv, U, ldu, A.scratch.carry, stream)
-                    : launch_batch_kernel<int32_t, VinT, VoutT>(C, L, k, V, ldv, U, ldu, A.scratch.carry, stream);
+            Vin = vp;
+            ldin = k;
         }
+        e = C.idx_kind == IdxKind::U16
+                ? launch_batch_kernel<uint16_t, ValT, VecT, VecT>(C, L, k, Vin, ldin, U, ldu, A.scratch.carry, stream)
+                : launch_batch_kernel<int32_t, ValT, VecT, VecT>(C, L, k, Vin, ldin, U, ldu, A.scratch.carry, stream);
         if (e) return e;
     }
     if (C.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup_batch");
-        hipLaunchKernelGGL(zone_fixup_batch<VoutT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(zone_fixup_batch<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
                            C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
@@ -845,16 +942,16 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
 }  // namespace
 
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream_)
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream)
 {
-    hipStream_t stream = (hipStream_t)stream_;
-    if (A.value_storage != SPW_F64 || k < 1 || k > 64) return (int)hipErrorNotSupported;
+    if (k < 1 || k > 64) return (int)hipErrorNotSupported;
     if (C.cols == 0) return 0;
-    if (vdt == SPW_F64)
-        return coldot_batch_typed<double, double>(A, C, inv, k, (const double *)V, ldv, (double *)U, ldu, stream);
-    if (vdt == SPW_F32)
-        return coldot_batch_typed<float, float>(A, C, inv, k, (const float *)V, ldv, (float *)U, ldu, stream);
-    return (int)hipErrorNotSupported;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
+                                              (hipStream_t)stream);
+    });
 }
 
 template <typename T>

@@ -68,6 +68,7 @@ SIGNATURES = {
     "spw_vtm": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
     "spw_mv_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_vtm_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
+    "spw_round_values": (ctypes.c_int, [ctypes.c_int, _I64, _VP, _VP]),
     "spw_plan_zones": (ctypes.c_int, [_I64, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                       _VP, _VP, _VP, _VP]),
     "spw_profile_enable": (ctypes.c_int, [_I32]),
@@ -174,6 +175,14 @@ def spw_vtm_batch(h: int, V: torch.Tensor, U: torch.Tensor, stream=None):
     k = V.shape[1]
     _check(load().spw_vtm_batch(h, _vec_dtype(V), k, V.data_ptr(), V.stride(0), U.data_ptr(), U.stride(0),
                                 _stream_ptr(stream)))
+
+
+def spw_round_values(storage: int, val) -> np.ndarray:
+    """Host-only: the values spw_create stores for `storage`, promoted to float64."""
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    out = np.empty_like(val)
+    _check(load().spw_round_values(storage, val.size, val.ctypes.data, out.ctypes.data))
+    return out
 
 
 def spw_plan_zones(n: int, ptr, chunk_nnz: int):

@@ -145,3 +145,56 @@ def test_plan_zones_edge_cases(spw):
     # boundaries that fall exactly on column starts cut nothing
     owned, zc, _, _ = spw.spw_plan_zones(4, np.array([0, 4, 8, 12, 16], dtype=np.int64), 4)
     assert zc.size == 0 and owned.tolist() == [0, 1, 2, 3, 4]
+
+
+# ---------------------------------------------------------------------------
+# Create-time value rounding (host code of the library) against the oracle's
+# rounding, which is pinned to the hardware binary32 conversion and to the
+# bfloat16 definition in test_oracle_pins.
+# ---------------------------------------------------------------------------
+def _rounding_inputs():
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(50000) * np.exp2(rng.integers(-150, 127, 50000))
+    # ties and near-ties of both formats, subnormal range, signed zeros
+    t = [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -24, 1.0 + 3 * 2.0 ** -24,
+         1.0 + 2.0 ** -8 + 2.0 ** -40, 2.0 ** -134, 3 * 2.0 ** -134, 2.0 ** -149, 2.0 ** -150,
+         3 * 2.0 ** -150, 2.0 ** -126 * (1 - 2.0 ** -9), 0.0, -0.0, 1e-300, -1e-310]
+    return np.concatenate([x, t, [-v for v in t]])
+
+
+@pytest.mark.parametrize("fmt,storage", [("f32", 1), ("bf16", 2)])
+def test_library_rounding_matches_oracle(spw, fmt, storage):
+    x = _rounding_inputs()
+    ours = spw.spw_round_values(storage, x)
+    ref = oracle.round_array(x, fmt)
+    assert np.array_equal(ours.view(np.uint64), ref.view(np.uint64))
+
+
+def test_library_rounding_f64_is_identity(spw):
+    x = _rounding_inputs()
+    assert np.array_equal(spw.spw_round_values(0, x).view(np.uint64), x.view(np.uint64))
+
+
+def test_library_rounding_reports_overflow(spw):
+    # largest finite bfloat16 is (2 - 2^-7) * 2^127; halfway to 2^128 rounds to even = overflow
+    big = (2 - 2.0 ** -7) * 2.0 ** 127
+    assert spw.spw_round_values(2, np.array([big]))[0] == big
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_round_values, 2, np.array([1.0, (2 - 2.0 ** -8) * 2.0 ** 127]))
+    assert "position 1" in msg
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_round_values, 1, np.array([0.0, 0.0, 1e39]))
+    # a bad storage type is an argument error
+    _expect(spw, "SPW_ERR_INVALID_ARG", spw.spw_round_values, 7, np.array([1.0]))
+
+
+def test_create_rejects_value_overflow_before_device_use(spw):
+    ptr = np.array([0, 1, 3], dtype=np.int64)
+    idx = np.array([0, 0, 1], dtype=np.int32)
+    val = np.array([1.0, 3.4e38, 1e39])   # 3.4e38 fits binary32, not bfloat16
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 2, ptr, idx, val,
+                  spw.create_opts(value_storage=spw.SPW_F32))
+    assert "position 2" in msg
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 2, 2, ptr, idx, val,
+                  spw.create_opts(value_storage=spw.SPW_BF16))
+    assert "position 1" in msg
+    _expect(spw, "SPW_ERR_INVALID_ARG", spw.spw_create, spw.SPW_CSC, 2, 2, ptr, idx, val,
+            spw.create_opts(value_storage=5))

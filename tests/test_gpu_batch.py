@@ -137,19 +137,19 @@ def test_batch_column_equals_plain_call(spw):
     M.close()
 
 
-def test_transpose_off_is_reported(spw):
+def test_transpose_off_falls_back_to_scatter_passes(spw):
     A = synth.config_matrix("c0", scale=0.05)
     M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val, transpose=0)
     assert M.info()["has_transpose"] == 0
-    # binary64 blocks fall back to one scatter pass per column
-    X = torch.from_numpy(synth.vector(A.n * 6, 4, 1).reshape(A.n, 6)).cuda()
-    Y = M.mv_batch(X).cpu().numpy()
-    Yr, DY = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X.cpu().numpy(), with_d=True)
-    check(Y, Yr, DY, "transpose off mv_batch", 1e-13)
-    # binary32 blocks need the transpose
-    with pytest.raises(spw.SpwError) as ei:
-        M.mv_batch(X.float())
-    assert ei.value.status_name == "SPW_ERR_UNSUPPORTED"
+    # without the transpose, k-wide blocks run one scatter pass per column
+    X = synth.vector(A.n * 6, 4, 1).reshape(A.n, 6)
+    Yr, DY = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
+    Y = M.mv_batch(torch.from_numpy(X).cuda()).cpu().numpy()
+    check(Y, Yr, DY, "transpose off mv_batch f64", 1e-13)
+    X32 = X.astype(np.float32)
+    Yr32, DY32 = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X32.astype(np.float64), with_d=True)
+    Y32 = M.mv_batch(torch.from_numpy(X32).cuda()).double().cpu().numpy()
+    check(Y32, Yr32, DY32, "transpose off mv_batch f32", 1e-5)
     # the other direction does not need it
     V = torch.ones((A.m, 2), dtype=torch.float64, device="cuda")
     M.vtm_batch(V)
