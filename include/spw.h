@@ -164,6 +164,96 @@ spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, i
 spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv,
                          void *U, int64_t ldu, void *stream);
 
+/* ----------------------------------------------------------------- serving */
+
+/* A server keeps many created matrices resident and serves product requests
+ * submitted from any thread.  Queued requests for the same matrix, operation
+ * and vector type are merged into one group (continuous batching: requests
+ * that arrive while earlier groups run join the next group) and issued on one
+ * of a few HIP streams, at most `depth` groups per stream.  A group's columns
+ * run as column-dot passes of up to 8 columns that read the matrix once per
+ * pass, or as one scatter pass per column, and every column is reduced exactly
+ * as a lone single-vector call would reduce it: a request's output is
+ * bit-identical whatever else it was batched with.  The memory a matrix holds
+ * (spw_matrix_info.device_bytes, after its scratch grows to 8 columns at
+ * registration) is charged to the server's HBM budget. */
+typedef struct spw_server_s *spw_server;
+
+typedef enum { SPW_OP_MV = 0 /* y := A x */, SPW_OP_VTM = 1 /* u^T := v^T A */ } spw_op;
+
+/* Zero-initialise and set struct_size, or call spw_serve_opts_default. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t max_inflight;      /* requests queued or running; submit beyond it is SPW_ERR_BUSY (4096) */
+    int64_t hbm_budget_bytes;  /* device bytes registered matrices may hold (64 GiB) */
+    int32_t streams;           /* HIP streams, default priority, 1..16 (4) */
+    int32_t depth;             /* groups in flight per stream (2) */
+    int32_t max_batch_cols;    /* columns merged into one group (64) */
+    int32_t device;            /* HIP device ordinal, -1 = current (-1) */
+    int32_t start_paused;      /* 1: issue nothing until spw_serve_resume (0) */
+    int32_t reserved[7];
+} spw_serve_opts;
+
+/* One request: k columns, laid out as for spw_mv_batch / spw_vtm_batch
+ * (row-major, leading dimensions ldi, ldo >= k).  in/out are device buffers
+ * owned by the caller that must stay valid until the request completes. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t matrix;            /* handle returned by spw_serve_register */
+    spw_op op;
+    spw_dtype vdt;             /* SPW_F64 or SPW_F32 */
+    int32_t k;                 /* 1..64 */
+    const void *in;
+    int64_t ldi;
+    void *out;
+    int64_t ldo;
+    uint64_t tag;              /* the caller's; not interpreted */
+} spw_request;
+
+/* Counters since creation.  Latency is host time from submit to the moment
+ * the completion thread sees the request's group finish. */
+typedef struct {
+    uint32_t struct_size;
+    int64_t submitted, completed, rejected_busy;
+    int64_t groups;            /* groups issued */
+    int64_t merged_requests;   /* requests that shared a group with others */
+    int64_t passes;            /* kernel passes over a matrix */
+    int64_t inflight;          /* queued or running now */
+    int64_t registered;
+    int64_t hbm_budget_bytes, hbm_used_bytes;
+    double latency_p50_us, latency_p99_us, latency_mean_us;
+    double model_bytes;        /* sum over completed requests of the algorithmic bytes:
+                                  nnz*(value bytes + 4) + 4*(long dim + 1) + k*(m + n)*vector bytes */
+    double busy_seconds;       /* first submit to last completion */
+    double gbps;               /* model_bytes / busy_seconds / 1e9 */
+} spw_server_stats;
+
+spw_status spw_serve_opts_default(spw_serve_opts *opts);
+/* Starts the dispatcher and one completion thread per stream.  NULL opts means
+ * defaults.  SPW_ERR_INVALID_ARG for bad options, SPW_ERR_DEVICE without a GPU. */
+spw_status spw_serve_create(spw_server *out, const spw_serve_opts *opts);
+/* Makes A resident in the server and returns its handle (0, 1, ...).  The
+ * caller keeps ownership of A and must not destroy it or use it outside the
+ * server until the server is destroyed.  SPW_ERR_BUDGET when A would exceed
+ * the budget (A stays usable; its scratch may have grown). */
+spw_status spw_serve_register(spw_server s, spw_matrix A, int32_t *handle);
+/* Queues a request; *ticket identifies it.  SPW_ERR_BUSY at max_inflight,
+ * SPW_ERR_SHUTDOWN while the server is being destroyed, SPW_ERR_INVALID_ARG
+ * for a bad request (checked before queueing). */
+spw_status spw_serve_submit(spw_server s, const spw_request *r, uint64_t *ticket);
+/* Starts issuing when the server was created paused (no-op otherwise). */
+spw_status spw_serve_resume(spw_server s);
+/* *done = 1 when the request has completed (its output is valid). Returns the
+ * request's error if it failed on the device. */
+spw_status spw_serve_poll(spw_server s, uint64_t ticket, int32_t *done);
+/* Blocks until the request completes, or timeout_us passes (< 0: no limit):
+ * SPW_ERR_TIMEOUT then, and the request stays queued or running. */
+spw_status spw_serve_wait(spw_server s, uint64_t ticket, int64_t timeout_us);
+spw_status spw_serve_stats(spw_server s, spw_server_stats *out);
+/* Stops accepting requests, runs everything queued (also when paused), waits
+ * for it, and frees the server's threads and streams.  NULL is a no-op. */
+spw_status spw_serve_destroy(spw_server s);
+
 /* ---------------------------------------------------------- host-only helpers */
 
 /* Rounds n binary64 values the way spw_create stores them for `storage`

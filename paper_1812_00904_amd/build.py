@@ -18,6 +18,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed fp32 instructions stay off: the compiler must not form v_pk_* fp32 ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # products and sums are rounded separately, as written: kernels that share
+    # an arithmetic sequence then give identical bits
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-result",
 ]
 

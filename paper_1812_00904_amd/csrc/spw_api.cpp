@@ -59,7 +59,7 @@ spw_status dev_alloc(spw_matrix_s &A, T **out, int64_t count, const char *what)
         return fail(SPW_ERR_OUT_OF_MEMORY, std::string("hipMalloc failed for ") + what + " (" +
                                                std::to_string(bytes) + " bytes)");
     }
-    A.allocations.push_back(p);
+    A.allocations.emplace_back(p, (int64_t)bytes);
     A.device_bytes += (int64_t)bytes;
     *out = (T *)p;
     return SPW_OK;
@@ -77,7 +77,7 @@ spw_status h2d(void *dst, const void *src, size_t bytes, const char *what)
 
 void free_all(spw_matrix_s *A)
 {
-    for (void *p : A->allocations) (void)hipFree(p);
+    for (auto &a : A->allocations) (void)hipFree(a.first);
     A->allocations.clear();
 }
 
@@ -513,15 +513,28 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
     return SPW_OK;
 }
 
-spw_status alloc_scratch(spw_matrix_s &A, int32_t k)
+}  // namespace
+
+spw_status grow_scratch(spw_matrix_s &A, int32_t k)
 {
+    spw_status st;
+    if (!A.scratch.partial) {
+        // partial sums of the scatter product: one column at a time
+        if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows, "partial sums")))
+            return st;
+    }
     if (A.scratch.kcap >= k) return SPW_OK;
-    // grow: free the old buffers (they are tracked in allocations)
-    auto drop = [&](void *p) {
+    // grow the k-wide buffers: free the old ones once the device is idle
+    auto drop = [&](double *&p) {
         if (!p) return;
-        auto it = std::find(A.allocations.begin(), A.allocations.end(), p);
-        if (it != A.allocations.end()) A.allocations.erase(it);
+        for (size_t i = 0; i < A.allocations.size(); ++i)
+            if (A.allocations[i].first == p) {
+                A.device_bytes -= A.allocations[i].second;
+                A.allocations.erase(A.allocations.begin() + (long)i);
+                break;
+            }
         (void)hipFree(p);
+        p = nullptr;
     };
     if (A.scratch.kcap > 0) {
         if (hipDeviceSynchronize() != hipSuccess) {
@@ -529,13 +542,9 @@ spw_status alloc_scratch(spw_matrix_s &A, int32_t k)
             return fail(SPW_ERR_DEVICE, "hipDeviceSynchronize failed while growing scratch");
         }
     }
-    drop(A.scratch.partial);
     drop(A.scratch.carry);
     drop(A.scratch.vperm);
-    A.scratch = Scratch{};
-    spw_status st;
-    if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows * k, "partial sums")))
-        return st;
+    A.scratch.kcap = 0;
     const int64_t nch = std::max<int64_t>(A.cd.zp.n_chunks, A.cdt.zp.n_chunks);
     if ((st = dev_alloc(A, &A.scratch.carry, std::max<int64_t>(2 * nch, 1) * k, "carries"))) return st;
     if ((st = dev_alloc(A, &A.scratch.vperm, std::max<int64_t>(A.rows, 1) * k, "renumbered vector"))) return st;
@@ -543,7 +552,6 @@ spw_status alloc_scratch(spw_matrix_s &A, int32_t k)
     return SPW_OK;
 }
 
-}  // namespace
 }  // namespace spw
 
 using namespace spw;
@@ -703,7 +711,7 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     if (rows > 0) {
         if ((st = build_mv_storage(*A, ptr, rowi.data(), val, opts.panel_rows))) return st;
     }
-    if ((st = alloc_scratch(*A, 1))) return st;
+    if ((st = grow_scratch(*A, 1))) return st;
     if (hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         return fail(SPW_ERR_DEVICE, "device error during spw_create");
@@ -766,7 +774,7 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": NULL vector");
     DeviceGuard dg(A->device);
     if (dg.st) return dg.st;
-    spw_status st = alloc_scratch(*A, k);
+    spw_status st = grow_scratch(*A, k);
     if (st) return st;
     int e;
     if (k == 1 && ldi == 1 && ldo == 1) {
@@ -783,7 +791,9 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
     } else {
-        e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
+        // column dots: the chunk is read once per pass of up to 8 columns and
+        // each column is reduced exactly as a single vector would be
+        e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     }
     if (e == (int)hipErrorNotSupported)
         return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");

@@ -12,6 +12,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "spw.h"
@@ -68,7 +69,7 @@ struct ColDot {
 };
 
 struct Scratch {
-    double *partial = nullptr;    // mv_wgs * panel_rows * kcap  (binary64 partial sums)
+    double *partial = nullptr;    // mv_wgs * panel_rows  (binary64 partial sums of one column)
     double *carry = nullptr;      // 2 * max chunks * kcap
     double *vperm = nullptr;      // rows * kcap elements of 8 bytes (renumbered input of the column dots)
     int32_t kcap = 0;
@@ -103,7 +104,7 @@ struct spw_matrix_s {
 
     spw::Scratch scratch;
     int64_t device_bytes = 0;
-    std::vector<void *> allocations;
+    std::vector<std::pair<void *, int64_t>> allocations;   // device buffers and their sizes
 };
 
 namespace spw {
@@ -113,7 +114,21 @@ namespace spw {
 
 // Single-vector column dots (u = B^T v) over A.cd.
 int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, const void *v, void *u, void *stream);
-// Scatter product y = B x, k times over strided columns of X (ldx) and Y (ldy).
+// Column dots for k <= 8 columns in one pass: column c reads in[c] (stride
+// ldi[c]) and writes out[c] (stride ldo[c]); in/out/ldi/ldo are host arrays.
+// Every column is bit-identical to launch_vtm on it.
+int launch_vtm_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
+                    void *const *out, const int64_t *ldo, void *stream);
+// Column dots for k columns of row-major V (ldv) into U (ldu), at most 8
+// columns per pass; every column is bit-identical to launch_vtm on it.
+int launch_vtm_multi(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv, void *u,
+                     int64_t ldu, void *stream);
+// Scatter products for k columns with their own bases and strides (host
+// arrays), one pass each.
+int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
+                   void *const *out, const int64_t *ldo, void *stream);
+// Scatter product y = B x, k times over strided columns of X (ldx) and Y (ldy);
+// every column is bit-identical to the k = 1 product on it.
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
               void *y, int64_t ldy, void *stream);
 // Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
@@ -138,5 +153,9 @@ void profile_end(void *stream, void *token);
 
 // Error text for the calling thread (spw_api.cpp).
 void set_error(const std::string &msg);
+
+// Makes the handle's scratch hold k-wide carries and renumbered inputs (and
+// the one-column partial sums); growing waits for the device (spw_api.cpp).
+spw_status grow_scratch(spw_matrix_s &A, int32_t k);
 
 }  // namespace spw

@@ -172,6 +172,18 @@ template <int N> struct IdxRaw<int32_t, N> {     // N 4-byte indices
     __device__ __forceinline__ int get(int i) const { return (int)w[i]; }
 };
 
+// Output columns of a multi-vector pass, each with its own base and stride
+// (the columns may belong to different requests).
+constexpr int MULTI_MAX = 8;
+template <typename VecT> struct ColOut {
+    VecT *u[MULTI_MAX];
+    int64_t ld[MULTI_MAX];
+};
+template <typename VecT> struct ColIn {
+    const VecT *v[MULTI_MAX];
+    int64_t ld[MULTI_MAX];
+};
+
 // ------------------------------------------------------------------------
 // Segmented sums across a wave.
 //
@@ -226,10 +238,12 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 // Reduces one chunk whose products are in `prod` (lane-owned positions
 // p0 .. p0+ITEMS-1): cs[k] is the start of column jlo+k.  Inlined twice, with
 // cs in LDS or in global memory, so that each copy uses the matching loads.
+// u is the output column (entry j at u[j*ldu]); carry slot (2c+side) of this
+// column is carry[(2c+side)*kk + col].
 template <int ITEMS, typename VecT>
 __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double *prod, int s, int e, int jlo,
-                                                 int ncol, int64_t c, int lane, VecT *__restrict__ u,
-                                                 double *__restrict__ carry)
+                                                 int ncol, int64_t c, int lane, VecT *__restrict__ u, int64_t ldu,
+                                                 double *__restrict__ carry, int kk, int col)
 {
     const int p0 = s + lane * ITEMS;
     const int my_n = max(0, min(ITEMS, e - p0));
@@ -255,7 +269,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
                         hk = k;
                         multi = true;
                     } else {
-                        u[jlo + k] = (VecT)run;  // column wholly inside this lane
+                        u[(int64_t)(jlo + k) * ldu] = (VecT)run;   // column wholly inside this lane
                     }
                     do {
                         ++k;
@@ -277,11 +291,11 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
     const int prev_k = __shfl_up(o.k, 1, WAVE);
     const int next_hk = __shfl_down(hk, 1, WAVE);
     if (my_n > 0) {
-        auto emit = [&](int kk, double value) {
-            const bool before = cs[kk] < s, after = cs[kk + 1] > e;
-            if (before) carry[2 * c] = value;
-            else if (after) carry[2 * c + 1] = value;
-            else u[jlo + kk] = (VecT)value;
+        auto emit = [&](int kcol, double value) {
+            const bool before = cs[kcol] < s, after = cs[kcol + 1] > e;
+            if (before) carry[(2 * c) * kk + col] = value;
+            else if (after) carry[(2 * c + 1) * kk + col] = value;
+            else u[(int64_t)(jlo + kcol) * ldu] = (VecT)value;
         };
         if (multi) {
             // the lane's first column ends inside it: add what earlier lanes hold
@@ -299,23 +313,38 @@ template <typename IdxT, typename ValT, int ITEMS, int SLW> struct VtmChunk {
     int32_t sl[SLW];
 };
 
-template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT, typename ValT, typename VecT>
+// MULTI = false: one vector (k = 1, v and out.u[0] unit-stride).
+// MULTI = true: k <= MULTI_MAX columns; v is a row-major rows x k block and
+// column col goes to out.u[col] with stride out.ld[col].  Each chunk is loaded
+// once and reduced once per column with exactly the single-vector arithmetic,
+// so every column equals the single-vector result bit for bit.  The hot rows
+// are staged in LDS as vh[r*k + col].
+template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT, typename ValT, typename VecT, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void vtm_wave(
     const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const ValT *__restrict__ val,
     const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks,
-    const VecT *__restrict__ v, int vhot, VecT *__restrict__ u, double *__restrict__ carry)
+    const VecT *__restrict__ v, int k, int vhot, ColOut<VecT> out, double *__restrict__ carry)
 {
+    if (!MULTI) k = 1;
+    const int64_t ldv = k;
     constexpr int NW = BLOCK / WAVE;
     constexpr int WCH = WAVE * ITEMS;
     constexpr int SLW = SLICE_W / WAVE;
     extern __shared__ double lds[];
     VecT *vh = reinterpret_cast<VecT *>(lds);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int hot_bytes = (vhot * (int)sizeof(VecT) + 15) & ~15;
+    const int hot_bytes = (vhot * k * (int)sizeof(VecT) + 15) & ~15;
     int32_t *slice = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(lds) + hot_bytes) + wave * SLICE_W;
     const int lane = threadIdx.x & (WAVE - 1);
 
-    for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
+    if (MULTI) {
+        for (int i = threadIdx.x; i < vhot * k; i += BLOCK) {
+            const int r = i / k;
+            vh[i] = v[(int64_t)r * ldv + (i - r * k)];
+        }
+    } else {
+        for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
+    }
     __syncthreads();
 
     const int64_t stride = (int64_t)gridDim.x * NW;
@@ -343,26 +372,34 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
         const bool in_lds = ncol <= SLICE_W;
 #pragma unroll
         for (int t = 0; t < SLW; ++t) slice[lane + t * WAVE] = C.sl[t];
-        double prod[ITEMS];
+        for (int col = 0; col < k; ++col) {
+            double prod[ITEMS];
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            // the LDS read and the global read stay separate instructions (a
-            // selected pointer would become a flat load, which waits for every
-            // outstanding load)
-            const int ri = C.r.get(i);
-            const VecT lv = vh[min(ri, vhot - 1)];
-            VecT gv = 0;
-            if (ri >= vhot) gv = v[ri];
-            prod[i] = C.a.get(i) * (double)(ri < vhot ? lv : gv);
+            for (int i = 0; i < ITEMS; ++i) {
+                // the LDS read and the global read stay separate instructions (a
+                // selected pointer would become a flat load, which waits for
+                // every outstanding load)
+                const int ri = C.r.get(i);
+                const VecT lv = vh[min(ri, vhot - 1) * k + col];
+                VecT gv = 0;
+                if (ri >= vhot) gv = v[(int64_t)ri * ldv + col];
+                prod[i] = C.a.get(i) * (double)(ri < vhot ? lv : gv);
+            }
+            if (col == 0) {
+                // The gathers must land before the next chunk's loads are
+                // issued: the load counter is in order, so waiting for them
+                // later would also wait for the prefetch.
+                __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
+                if (cn < nchunks) load_chunk(N, cn, jln);
+                wave_sync();
+            }
+            VecT *uc = MULTI ? out.u[col] : out.u[0];
+            const int64_t ldu = MULTI ? out.ld[col] : 1;
+            if (in_lds)
+                vtm_reduce_chunk<ITEMS, VecT>(slice, prod, s, e, jlo, ncol, cc, lane, uc, ldu, carry, k, col);
+            else
+                vtm_reduce_chunk<ITEMS, VecT>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, uc, ldu, carry, k, col);
         }
-        // The gathers must land before the next chunk's loads are issued: the
-        // load counter is in order, so waiting for them later would also wait
-        // for the prefetch.
-        __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
-        if (cn < nchunks) load_chunk(N, cn, jln);
-        wave_sync();
-        if (in_lds) vtm_reduce_chunk<ITEMS, VecT>(slice, prod, s, e, jlo, ncol, cc, lane, u, carry);
-        else vtm_reduce_chunk<ITEMS, VecT>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, u, carry);
         wave_sync();                              // slice reads done before it is rewritten
     };
 
@@ -691,6 +728,45 @@ __global__ void zero_cols_batch(const int32_t *__restrict__ cols, int64_t count,
     U[(int64_t)cols[i] * ldu + (g - i * k)] = (VoutT)0;
 }
 
+// Multi-vector helpers over column tables (k <= MULTI_MAX columns).
+template <typename VecT>
+__global__ void zero_cols_tab(const int32_t *__restrict__ cols, int64_t count, int k, ColOut<VecT> out)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= count * k) return;
+    const int64_t i = g / k;
+    const int c = (int)(g - i * k);
+    out.u[c][(int64_t)cols[i] * out.ld[c]] = (VecT)0;
+}
+
+template <typename VecT>
+__global__ void zone_fixup_tab(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
+                               const int32_t *__restrict__ zlast, int64_t nz, int k,
+                               const double *__restrict__ carry, ColOut<VecT> out)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nz * k) return;
+    const int64_t z = g / k;
+    const int cc = (int)(g - z * k);
+    const int a = zfirst[z], b = zlast[z];
+    double s = carry[(2 * (int64_t)a + 1) * k + cc];
+    for (int c = a + 1; c <= b; ++c) s += carry[(2 * (int64_t)c) * k + cc];
+    out.u[cc][(int64_t)zcol[z] * out.ld[cc]] = (VecT)s;
+}
+
+// out[r*k + c] = column c of the table at caller row inv[r] (or r).
+template <typename VecT>
+__global__ void gather_tab(const int32_t *__restrict__ inv, int64_t rows, int k, ColIn<VecT> in,
+                           VecT *__restrict__ out)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    const int c = (int)(g - r * k);
+    const int64_t src = inv ? inv[r] : r;
+    out[g] = in.v[c][src * in.ld[c]];
+}
+
 // Renumber the rows of a k-wide block: out[r*k + c] = in[inv[r]*ldv + c].
 template <typename VinT>
 __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k, const VinT *__restrict__ in,
@@ -749,6 +825,25 @@ int64_t hot_rows_limit(size_t vec_bytes)
     return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / (int64_t)vec_bytes;
 }
 
+template <typename IdxT, typename ValT, typename VecT, bool MULTI>
+int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
+{
+    const ColDot &C = A.cd;
+    if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
+    const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT) * (size_t)k));
+    const size_t lds = (((size_t)vhot * k * sizeof(VecT) + 15) & ~(size_t)15) +
+                       (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
+    const int cus = device_cu_count(A.device);
+    const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
+    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, IdxT, ValT, VecT, MULTI>);
+    (void)attr;
+    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, IdxT, ValT, VecT, MULTI>), dim3(grid),
+                       dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_cjlo,
+                       C.d_cjhi, C.nnz, C.zp.n_chunks, vin, k, vhot, out, A.scratch.carry);
+    return (int)hipGetLastError();
+}
+
 template <typename ValT, typename VecT>
 int vtm_typed(const spw_matrix_s &A, const VecT *v, VecT *u, hipStream_t stream)
 {
@@ -773,26 +868,12 @@ int vtm_typed(const spw_matrix_s &A, const VecT *v, VecT *u, hipStream_t stream)
     }
     {
         ProfScope ps(stream, "vtm_wave");
-        if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
-        const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT)));
-        const size_t lds = (((size_t)vhot * sizeof(VecT) + 15) & ~(size_t)15) + (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
-        const int cus = device_cu_count(A.device);
-        const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
-        static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t, ValT, VecT>) &&
-                                 allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t, ValT, VecT>);
-        (void)attr;
-        if (C.idx_kind == IdxKind::U16)
-            hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, uint16_t, ValT, VecT>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const uint16_t *)C.d_idx,
-                               (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz, C.zp.n_chunks, vin, vhot, u,
-                               A.scratch.carry);
-        else
-            hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, int32_t, ValT, VecT>), dim3(grid),
-                               dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const int32_t *)C.d_idx,
-                               (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz, C.zp.n_chunks, vin, vhot, u,
-                               A.scratch.carry);
-        if ((e = (int)hipGetLastError())) return e;
+        ColOut<VecT> out{};
+        out.u[0] = u;
+        out.ld[0] = 1;
+        e = C.idx_kind == IdxKind::U16 ? launch_vtm_wave<uint16_t, ValT, VecT, false>(A, vin, 1, out, stream)
+                                       : launch_vtm_wave<int32_t, ValT, VecT, false>(A, vin, 1, out, stream);
+        if (e) return e;
     }
     if (C.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup");
@@ -801,6 +882,59 @@ int vtm_typed(const spw_matrix_s &A, const VecT *v, VecT *u, hipStream_t stream)
         if ((e = (int)hipGetLastError())) return e;
     }
     return 0;
+}
+
+// Up to MULTI_MAX columns in one pass, each with its own input and output
+// base and stride; every column is bit-identical to the single-vector product.
+template <typename ValT, typename VecT>
+int vtm_cols_typed(const spw_matrix_s &A, int k, const ColIn<VecT> &in, const ColOut<VecT> &out,
+                   hipStream_t stream)
+{
+    const ColDot &C = A.cd;
+    int e;
+    if (C.cols == 0) return 0;
+    if (C.n_empty > 0) {
+        ProfScope ps(stream, "zero_cols");
+        hipLaunchKernelGGL(zero_cols_tab<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
+                           C.d_empty, C.n_empty, k, out);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (C.nnz == 0) return 0;
+    VecT *vp = reinterpret_cast<VecT *>(A.scratch.vperm);
+    {
+        // the k inputs, renumbered when the rows are, as one rows x k block
+        ProfScope ps(stream, "gather_vec");
+        hipLaunchKernelGGL(gather_tab<VecT>, dim3(blocks_for(A.rows * k, 256)), dim3(256), 0, stream,
+                           A.relabeled ? A.d_inv : nullptr, A.rows, k, in, vp);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    {
+        ProfScope ps(stream, "vtm_wave_multi");
+        e = C.idx_kind == IdxKind::U16 ? launch_vtm_wave<uint16_t, ValT, VecT, true>(A, vp, k, out, stream)
+                                       : launch_vtm_wave<int32_t, ValT, VecT, true>(A, vp, k, out, stream);
+        if (e) return e;
+    }
+    if (C.n_zones > 0) {
+        ProfScope ps(stream, "zone_fixup");
+        hipLaunchKernelGGL(zone_fixup_tab<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+                           C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, out);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    return 0;
+}
+
+template <typename VecT>
+void fill_tables(int k, const void *const *in, const int64_t *ldi, void *const *out, const int64_t *ldo,
+                 ColIn<VecT> &ti, ColOut<VecT> &to)
+{
+    ti = ColIn<VecT>{};
+    to = ColOut<VecT>{};
+    for (int c = 0; c < k; ++c) {
+        ti.v[c] = (const VecT *)in[c];
+        ti.ld[c] = ldi[c];
+        to.u[c] = (VecT *)out[c];
+        to.ld[c] = ldo[c];
+    }
 }
 
 // k right-hand sides run as k passes of the scatter kernel over strided
@@ -862,6 +996,41 @@ int launch_vtm(const spw_matrix_s &A, spw_dtype vdt, const void *v, void *u, voi
     });
 }
 
+int launch_vtm_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
+                    void *const *out, const int64_t *ldo, void *stream)
+{
+    if (k < 1 || k > MULTI_MAX) return (int)hipErrorInvalidValue;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        ColIn<VecT> ti;
+        ColOut<VecT> to;
+        fill_tables<VecT>(k, in, ldi, out, ldo, ti, to);
+        return vtm_cols_typed<ValT, VecT>(A, k, ti, to, (hipStream_t)stream);
+    });
+}
+
+int launch_vtm_multi(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv, void *u,
+                     int64_t ldu, void *stream)
+{
+    const size_t es = vdt == SPW_F64 ? 8 : 4;
+    for (int c0 = 0; c0 < k; c0 += MULTI_MAX) {
+        const int kk = std::min(MULTI_MAX, k - c0);
+        const void *in[MULTI_MAX];
+        void *out[MULTI_MAX];
+        int64_t li[MULTI_MAX], lo[MULTI_MAX];
+        for (int c = 0; c < kk; ++c) {
+            in[c] = (const char *)v + (size_t)(c0 + c) * es;
+            out[c] = (char *)u + (size_t)(c0 + c) * es;
+            li[c] = ldv;
+            lo[c] = ldu;
+        }
+        const int e = launch_vtm_cols(A, vdt, kk, in, li, out, lo, stream);
+        if (e) return e;
+    }
+    return 0;
+}
+
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx, void *y, int64_t ldy,
               void *stream)
 {
@@ -870,6 +1039,16 @@ int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, in
         using VecT = decltype(xt);
         return mv_typed<ValT, VecT>(A, k, (const VecT *)x, ldx, (VecT *)y, ldy, (hipStream_t)stream);
     });
+}
+
+int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
+                   void *const *out, const int64_t *ldo, void *stream)
+{
+    for (int c = 0; c < k; ++c) {
+        const int e = launch_mv(A, vdt, 1, in[c], ldi[c], out[c], ldo[c], stream);
+        if (e) return e;
+    }
+    return 0;
 }
 
 namespace {

@@ -50,6 +50,30 @@ class MatrixInfo(ctypes.Structure):
                 ("has_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+SPW_OP_MV, SPW_OP_VTM = 0, 1
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_inflight", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("max_batch_cols", ctypes.c_int32), ("device", ctypes.c_int32), ("start_paused", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("matrix", ctypes.c_int32), ("op", ctypes.c_int),
+                ("vdt", ctypes.c_int), ("k", ctypes.c_int32), ("in_", ctypes.c_void_p), ("ldi", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("ldo", ctypes.c_int64), ("tag", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32)] + \
+        [(n, ctypes.c_int64) for n in ("submitted", "completed", "rejected_busy", "groups", "merged_requests",
+                                       "passes", "inflight", "registered", "hbm_budget_bytes", "hbm_used_bytes")] + \
+        [(n, ctypes.c_double) for n in ("latency_p50_us", "latency_p99_us", "latency_mean_us", "model_bytes",
+                                        "busy_seconds", "gbps")]
+
+
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
@@ -69,6 +93,15 @@ SIGNATURES = {
     "spw_mv_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_vtm_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_round_values": (ctypes.c_int, [ctypes.c_int, _I64, _VP, _VP]),
+    "spw_serve_opts_default": (ctypes.c_int, [ctypes.POINTER(ServeOpts)]),
+    "spw_serve_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServeOpts)]),
+    "spw_serve_register": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_I32)]),
+    "spw_serve_submit": (ctypes.c_int, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "spw_serve_resume": (ctypes.c_int, [_VP]),
+    "spw_serve_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_I32)]),
+    "spw_serve_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, _I64]),
+    "spw_serve_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
+    "spw_serve_destroy": (ctypes.c_int, [_VP]),
     "spw_plan_zones": (ctypes.c_int, [_I64, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                       _VP, _VP, _VP, _VP]),
     "spw_profile_enable": (ctypes.c_int, [_I32]),
@@ -259,6 +292,74 @@ class SpwMatrix:
         if self.handle:
             spw_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A serving instance over resident matrices (see the serving part of
+    include/spw.h).  Requests keep references to their tensors until they
+    are waited for."""
+
+    def __init__(self, **opts):
+        o = ServeOpts()
+        _check(load().spw_serve_opts_default(ctypes.byref(o)))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        h = _VP()
+        _check(load().spw_serve_create(ctypes.byref(h), ctypes.byref(o)))
+        self.handle = h.value
+        self._keep = {}
+
+    def register(self, M: SpwMatrix) -> int:
+        out = _I32()
+        _check(load().spw_serve_register(self.handle, M.handle, ctypes.byref(out)))
+        return out.value
+
+    def submit(self, matrix: int, op: int, X: torch.Tensor, Y: torch.Tensor, tag: int = 0) -> int:
+        """X, Y: device tensors, 1-D (k = 1) or 2-D row-major (rows x k)."""
+        _dev(X, "in"), _dev(Y, "out")
+        k = 1 if X.dim() == 1 else X.shape[1]
+        r = Request()
+        r.struct_size = ctypes.sizeof(Request)
+        r.matrix, r.op, r.vdt, r.k = matrix, op, _vec_dtype(X), k
+        r.in_, r.ldi = X.data_ptr(), (1 if X.dim() == 1 else X.stride(0))
+        r.out, r.ldo = Y.data_ptr(), (1 if Y.dim() == 1 else Y.stride(0))
+        r.tag = tag
+        t = ctypes.c_uint64()
+        _check(load().spw_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (X, Y)
+        return t.value
+
+    def resume(self):
+        _check(load().spw_serve_resume(self.handle))
+
+    def poll(self, ticket: int) -> bool:
+        d = _I32()
+        _check(load().spw_serve_poll(self.handle, ticket, ctypes.byref(d)))
+        if d.value:
+            self._keep.pop(ticket, None)
+        return bool(d.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        _check(load().spw_serve_wait(self.handle, ticket, timeout_us))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        st.struct_size = ctypes.sizeof(ServerStats)
+        _check(load().spw_serve_stats(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_ if n != "struct_size"}
+
+    def close(self):
+        if self.handle:
+            _check(load().spw_serve_destroy(self.handle))
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:
