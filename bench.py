@@ -135,6 +135,10 @@ def main():
     ap.add_argument("--no-tall", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS section")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision storage section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--serving-requests", type=int, default=10000)
+    ap.add_argument("--serving-loads", default="0.7",
+                    help="comma-separated offered loads, as fractions of the plain path's capacity")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
     ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
@@ -256,6 +260,10 @@ def main():
         del xd, vd, yd, ud
         torch.cuda.empty_cache()
         extra["batched"] = bench_batched(args)
+
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        extra["serving"] = bench_serving(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -422,6 +430,152 @@ def bench_batched(args):
             print("[bench] batched %s" % row, file=sys.stderr, flush=True)
             del X, V, Y, U, xs, vs, ys, us
             torch.cuda.empty_cache()
+        M.close()
+    return res
+
+
+def bench_serving(args):
+    """64 resident matrices (32 wide CSC, 32 tall CSR; shapes log-uniform) and a
+    stream of requests (k = 1..8 columns, A x or v^T A, binary64 or binary32
+    vectors) with Poisson arrivals.  The plain path runs each request as k
+    single-vector calls on one stream in arrival order; its capacity (requests
+    per second back to back) sets the offered loads.  The server runs the same
+    arrivals with continuous batching over 4 streams.  Latency is host time
+    from submission to completion as seen by a host thread."""
+    import threading
+    import numpy as np
+    import torch
+    import synth
+    from paper_1812_00904_amd import SPW_CSC, SPW_CSR, SPW_OP_MV, Server, SpwMatrix
+    t0 = time.perf_counter()
+    specs = synth.serving_specs()
+    mats, io = [], []
+    for sp in specs:
+        A = synth.serving_matrix(sp)
+        if sp["tall"]:
+            M = SpwMatrix(SPW_CSR, A.n, A.m, A.ptr, A.idx, A.val, transpose=0)
+        else:
+            M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, transpose=0)
+        mats.append(M)
+        bufs = {}
+        for dt in (torch.float64, torch.float32):
+            # row-major 8-column blocks (server) and contiguous columns (plain path)
+            bufs[dt] = {
+                "x_blk": torch.rand((M.n, 8), dtype=dt, device="cuda") * 2 - 1,
+                "v_blk": torch.rand((M.m, 8), dtype=dt, device="cuda") * 2 - 1,
+                "y_blk": torch.empty((M.m, 8), dtype=dt, device="cuda"),
+                "u_blk": torch.empty((M.n, 8), dtype=dt, device="cuda")}
+            b = bufs[dt]
+            b["x_col"] = [b["x_blk"][:, c].contiguous() for c in range(8)]
+            b["v_col"] = [b["v_blk"][:, c].contiguous() for c in range(8)]
+            b["y_col"] = [torch.empty(M.m, dtype=dt, device="cuda") for _ in range(8)]
+            b["u_col"] = [torch.empty(M.n, dtype=dt, device="cuda") for _ in range(8)]
+        io.append(bufs)
+        del A
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nreq = args.serving_requests
+    R = synth.serving_requests(nreq, len(mats))
+    dts = [torch.float32 if f else torch.float64 for f in R["f32"]]
+    model = []
+    for i in range(nreq):
+        M = mats[R["matrix"][i]]
+        info = M.info()
+        sx = 4 if dts[i] == torch.float32 else 8
+        model.append(info["nnz"] * 12 + 4 * (info["inner_cols"] + 1) + int(R["k"][i]) * sx * (M.m + M.n))
+    total_bytes = float(sum(model))
+    print("[bench] serving: %d matrices (%.2e nonzeros) ready in %.1fs" %
+          (len(mats), sum(M.info()["nnz"] for M in mats), setup_s), file=sys.stderr, flush=True)
+
+    def plain_issue(i, stream):
+        M, b, k = mats[R["matrix"][i]], io[R["matrix"][i]][dts[i]], int(R["k"][i])
+        for c in range(k):
+            if R["op"][i] == SPW_OP_MV:
+                M.mv(b["x_col"][c], b["y_col"][c], stream)
+            else:
+                M.vtm(b["v_col"][c], b["u_col"][c], stream)
+
+    stream = torch.cuda.Stream()
+    # capacity of the plain path: every request back to back
+    with torch.cuda.stream(stream):
+        for i in range(min(200, nreq)):
+            plain_issue(i, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(nreq):
+        plain_issue(i, stream)
+    torch.cuda.synchronize()
+    cap_s = time.perf_counter() - t
+    capacity = nreq / cap_s
+    res = {"workload": "64 resident matrices (32 wide CSC + 32 tall CSR), %d requests" % nreq,
+           "total_nnz": int(sum(M.info()["nnz"] for M in mats)), "setup_s": round(setup_s, 1),
+           "plain_back_to_back_s": round(cap_s, 3), "plain_capacity_req_per_s": round(capacity, 1),
+           "plain_back_to_back_GBps": round(total_bytes / cap_s / 1e9, 1), "loads": []}
+
+    def run_plain(gaps):
+        events = [torch.cuda.Event() for _ in range(nreq)]
+        t_sub = [0.0] * nreq
+        t_done = [0.0] * nreq
+
+        def completer():
+            for i in range(nreq):
+                while t_sub[i] == 0.0:
+                    time.sleep(0)
+                events[i].synchronize()
+                t_done[i] = time.perf_counter()
+        th = threading.Thread(target=completer)
+        th.start()
+        start = time.perf_counter()
+        due = start
+        for i in range(nreq):
+            due += gaps[i]
+            while time.perf_counter() < due:
+                pass
+            now = time.perf_counter()
+            plain_issue(i, stream)
+            events[i].record(stream)
+            t_sub[i] = now
+        th.join()
+        lat = [(t_done[i] - t_sub[i]) * 1e6 for i in range(nreq)]
+        span = max(t_done) - start
+        return lat, span
+
+    def run_server(gaps):
+        S = Server(streams=4, hbm_budget_bytes=64 << 30)
+        hs = [S.register(M) for M in mats]
+        tickets = []
+        start = time.perf_counter()
+        due = start
+        for i in range(nreq):
+            due += gaps[i]
+            while time.perf_counter() < due:
+                pass
+            b, k = io[R["matrix"][i]][dts[i]], int(R["k"][i])
+            if R["op"][i] == SPW_OP_MV:
+                X, Y = b["x_blk"][:, :k], b["y_blk"][:, :k]
+            else:
+                X, Y = b["v_blk"][:, :k], b["u_blk"][:, :k]
+            tickets.append(S.submit(hs[R["matrix"][i]], int(R["op"][i]), X, Y))
+        for tk in tickets:
+            S.wait(tk)
+        st = S.stats()
+        S.close()
+        return st
+
+    for load in [float(x) for x in args.serving_loads.split(",") if x]:
+        gaps = R["gap"] / (load * capacity)
+        lat, span = run_plain(gaps)
+        st = run_server(gaps)
+        row = {"offered_load": load, "rate_req_per_s": round(load * capacity, 1),
+               "plain": {"p50_us": round(percentile(lat, 50), 1), "p99_us": round(percentile(lat, 99), 1),
+                         "GBps": round(total_bytes / span / 1e9, 1)},
+               "server": {"p50_us": round(st["latency_p50_us"], 1), "p99_us": round(st["latency_p99_us"], 1),
+                          "GBps": round(st["gbps"], 1), "groups": st["groups"],
+                          "merged_requests": st["merged_requests"], "passes": st["passes"],
+                          "hbm_used_GB": round(st["hbm_used_bytes"] / 1e9, 2)}}
+        res["loads"].append(row)
+        print("[bench] serving %s" % row, file=sys.stderr, flush=True)
+    for M in mats:
         M.close()
     return res
 

@@ -296,6 +296,48 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
     }
     build_zone_plan(cols, ptr, WCH, C.zp);
     C.n_zones = (int64_t)C.zp.zone_col.size();
+    {
+        // Column-start bits (bit i of lane l of chunk c: position c*W + l*I + i
+        // is the first nonzero of its column) and per-chunk descriptions: the
+        // column of the first position, the chunk's runs ("segments") of
+        // positions in one column with the table of their columns, and flags.
+        const int64_t nch = C.zp.n_chunks;
+        std::vector<uint16_t> heads((size_t)std::max<int64_t>(nch * 64, 1), 0);
+        for (int64_t j = 0; j < cols; ++j)
+            if (ptr[j] < ptr[j + 1]) {
+                const int64_t p = ptr[j], o = p % WCH;
+                heads[(size_t)((p / WCH) * 64 + o / ITEMS)] |= (uint16_t)(1u << (o % ITEMS));
+            }
+        std::vector<int32_t> cinfo((size_t)(4 * std::max<int64_t>(nch, 1)), 0);
+        std::vector<int32_t> segcol;
+        segcol.reserve((size_t)(cols + nch + 1));
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t cs = c * WCH, ce = std::min(cs + WCH, nnz);
+            const int64_t jlo = C.zp.jlo[(size_t)c], jhi = C.zp.jhi[(size_t)c];
+            const int64_t seg0 = (int64_t)segcol.size();
+            segcol.push_back((int32_t)jlo);
+            for (int64_t j = jlo + 1; j <= jhi; ++j)
+                if (ptr[j] < ptr[j + 1]) segcol.push_back((int32_t)j);
+            const int64_t nseg = (int64_t)segcol.size() - seg0;
+            int32_t flags = 0;
+            if (ptr[jlo] == cs) flags |= 1;                      // the first position starts its column
+            if (ce < nnz && ptr[jhi + 1] > ce) flags |= 2;       // the last column continues
+            if (nseg == jhi - jlo + 1) flags |= 4;               // no empty column inside
+            int32_t *ci = &cinfo[(size_t)(4 * c)];
+            ci[0] = (int32_t)jlo;
+            ci[1] = (int32_t)seg0;
+            ci[2] = (int32_t)nseg;
+            ci[3] = flags;
+        }
+        if (segcol.size() >= ((size_t)1 << 31)) return fail(SPW_ERR_UNSUPPORTED, "segment table exceeds 2^31 entries");
+        if ((st = dev_alloc(A, &C.d_heads, (int64_t)heads.size(), "column-start bits"))) return st;
+        if ((st = h2d(C.d_heads, heads.data(), heads.size() * 2, "column-start bits"))) return st;
+        if ((st = dev_alloc(A, &C.d_cinfo, (int64_t)cinfo.size(), "chunk descriptions"))) return st;
+        if ((st = h2d(C.d_cinfo, cinfo.data(), cinfo.size() * 4, "chunk descriptions"))) return st;
+        if ((st = dev_alloc(A, &C.d_segcol, std::max<int64_t>((int64_t)segcol.size(), 1), "segment columns")))
+            return st;
+        if ((st = h2d(C.d_segcol, segcol.data(), segcol.size() * 4, "segment columns"))) return st;
+    }
     if ((st = dev_alloc(A, &C.d_cjlo, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;
     if ((st = h2d(C.d_cjlo, C.zp.jlo.data(), C.zp.jlo.size() * 4, "chunk table"))) return st;
     if ((st = dev_alloc(A, &C.d_cjhi, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;

@@ -52,7 +52,8 @@ enum class IdxKind : int32_t { U16 = 0, I32 = 1 };
 // Column-dot storage of a short-by-long CSC matrix: int32 column starts (plus
 // a padding window), 2- or 4-byte rows and values in the storage type (8, 4
 // or 2 bytes), both interleaved inside each chunk (see the column-dot kernel),
-// the chunk/zone plan and the columns without nonzeros.
+// column-start bits and segment tables per chunk, the chunk/zone plan and the
+// columns without nonzeros.
 struct ColDot {
     int64_t rows = 0, cols = 0, nnz = 0;
     IdxKind idx_kind = IdxKind::U16;
@@ -65,6 +66,9 @@ struct ColDot {
     int64_t n_empty = 0;
     int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
     int64_t n_zones = 0;
+    uint16_t *d_heads = nullptr;        // per chunk and lane: column-start bits of the lane's positions
+    int32_t *d_cinfo = nullptr;         // per chunk: first column, first segment, segments, flags
+    int32_t *d_segcol = nullptr;        // per chunk segment: its column
     bool built = false;
 };
 

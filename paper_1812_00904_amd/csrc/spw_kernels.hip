@@ -235,46 +235,59 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 // Dynamic LDS: vhot doubles, then SLICE_W column starts per wave.  Columns
 // without nonzeros are written by zero_cols, not here.
 // ------------------------------------------------------------------------
+// Per-chunk description used by the column dots (built on the host):
+//   jlo   : column holding the chunk's first position
+//   seg0  : index of the chunk's first entry in the segment-to-column table
+//   nseg  : number of segments (runs of positions in one column) in the chunk
+//   flags : CHUNK_START_HEAD  the first position starts its column
+//           CHUNK_END_CONT    the last column continues into the next chunk
+//           CHUNK_DENSE       no empty column inside: segment q is column jlo+q
+constexpr int CHUNK_START_HEAD = 1, CHUNK_END_CONT = 2, CHUNK_DENSE = 4;
+
 // Reduces one chunk whose products are in `prod` (lane-owned positions
-// p0 .. p0+ITEMS-1): cs[k] is the start of column jlo+k.  Inlined twice, with
-// cs in LDS or in global memory, so that each copy uses the matching loads.
-// u is the output column (entry j at u[j*ldu]); carry slot (2c+side) of this
-// column is carry[(2c+side)*kk + col].
+// p0 .. p0+ITEMS-1).  `mask` bit i is set when position p0+i is the first
+// nonzero of its column, so column boundaries are register bit tests.  Runs
+// are numbered by segment inside the chunk; the lane's first segment number
+// is the count of column starts after the chunk's first position in earlier
+// lanes (a wave prefix sum).  u is the output column (entry j at u[j*ldu]);
+// carry slot (2c+side) of this column is carry[(2c+side)*kk + col].
 template <int ITEMS, typename VecT>
-__device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double *prod, int s, int e, int jlo,
-                                                 int ncol, int64_t c, int lane, VecT *__restrict__ u, int64_t ldu,
-                                                 double *__restrict__ carry, int kk, int col)
+__device__ __forceinline__ void vtm_reduce_chunk(const double *prod, uint32_t mask, int s, int e, int4 ci,
+                                                 const int32_t *__restrict__ segcol, int64_t c, int lane,
+                                                 VecT *__restrict__ u, int64_t ldu, double *__restrict__ carry,
+                                                 int kk, int col)
 {
     const int p0 = s + lane * ITEMS;
     const int my_n = max(0, min(ITEMS, e - p0));
+    const int jlo = ci.x, seg0 = ci.y, last_seg = ci.z - 1, flags = ci.w;
+    const bool dense = (flags & CHUNK_DENSE) != 0;
+    auto column = [&](int q) -> int64_t { return dense ? (int64_t)jlo + q : (int64_t)segcol[seg0 + q]; };
+    // column starts after position s in this lane, and in all earlier lanes
+    const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
+    const int cnt = __popc(after_s);
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const int t = __shfl_up(incl, off, WAVE);
+        if (lane >= off) incl += t;
+    }
     double head_sum = 0.0, run = 0.0;
     int hk, k;
     bool multi = false;
     if (my_n > 0) {
-        int lo = 0, hi = ncol - 2;                // largest k with cs[k] <= p0
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cs[mid] <= p0) lo = mid;
-            else hi = mid - 1;
-        }
-        k = lo;
-        int nxtc = cs[k + 1];
+        k = incl - cnt + (lane > 0 ? (int)(mask & 1u) : 0);   // segment of the lane's first position
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if (i < my_n) {
-                const int p = p0 + i;
-                if (p >= nxtc) {
+                if (i > 0 && ((mask >> i) & 1u)) {
                     if (!multi) {
                         head_sum = run;
                         hk = k;
                         multi = true;
                     } else {
-                        u[(int64_t)(jlo + k) * ldu] = (VecT)run;   // column wholly inside this lane
+                        u[column(k) * ldu] = (VecT)run;   // column wholly inside this lane
                     }
-                    do {
-                        ++k;
-                        nxtc = cs[k + 1];
-                    } while (nxtc <= p);
+                    ++k;
                     run = 0.0;
                 }
                 run += prod[i];
@@ -291,11 +304,12 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
     const int prev_k = __shfl_up(o.k, 1, WAVE);
     const int next_hk = __shfl_down(hk, 1, WAVE);
     if (my_n > 0) {
-        auto emit = [&](int kcol, double value) {
-            const bool before = cs[kcol] < s, after = cs[kcol + 1] > e;
+        auto emit = [&](int q, double value) {
+            const bool before = q == 0 && !(flags & CHUNK_START_HEAD);
+            const bool after = q == last_seg && (flags & CHUNK_END_CONT);
             if (before) carry[(2 * c) * kk + col] = value;
             else if (after) carry[(2 * c + 1) * kk + col] = value;
-            else u[(int64_t)(jlo + kcol) * ldu] = (VecT)value;
+            else u[column(q) * ldu] = (VecT)value;
         };
         if (multi) {
             // the lane's first column ends inside it: add what earlier lanes hold
@@ -307,10 +321,10 @@ __device__ __forceinline__ void vtm_reduce_chunk(const int32_t *cs, const double
     }
 }
 
-template <typename IdxT, typename ValT, int ITEMS, int SLW> struct VtmChunk {
+template <typename IdxT, typename ValT, int ITEMS> struct VtmChunk {
     ValRaw<ValT, ITEMS> a;
     IdxRaw<IdxT, ITEMS> r;
-    int32_t sl[SLW];
+    uint32_t mask;              // column-start bits of the lane's positions
 };
 
 // MULTI = false: one vector (k = 1, v and out.u[0] unit-stride).
@@ -319,22 +333,19 @@ template <typename IdxT, typename ValT, int ITEMS, int SLW> struct VtmChunk {
 // once and reduced once per column with exactly the single-vector arithmetic,
 // so every column equals the single-vector result bit for bit.  The hot rows
 // are staged in LDS as vh[r*k + col].
-template <int BLOCK, int ITEMS, int SLICE_W, typename IdxT, typename ValT, typename VecT, bool MULTI>
+template <int BLOCK, int ITEMS, typename IdxT, typename ValT, typename VecT, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void vtm_wave(
-    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const ValT *__restrict__ val,
-    const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks,
+    const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
+    const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks,
     const VecT *__restrict__ v, int k, int vhot, ColOut<VecT> out, double *__restrict__ carry)
 {
     if (!MULTI) k = 1;
     const int64_t ldv = k;
     constexpr int NW = BLOCK / WAVE;
     constexpr int WCH = WAVE * ITEMS;
-    constexpr int SLW = SLICE_W / WAVE;
     extern __shared__ double lds[];
     VecT *vh = reinterpret_cast<VecT *>(lds);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
-    const int hot_bytes = (vhot * k * (int)sizeof(VecT) + 15) & ~15;
-    int32_t *slice = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(lds) + hot_bytes) + wave * SLICE_W;
     const int lane = threadIdx.x & (WAVE - 1);
 
     if (MULTI) {
@@ -353,25 +364,20 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
 
     // Two chunk buffers used alternately (no register copies, so no wait for
     // data still in flight): while one chunk is reduced, the next one's
-    // values, indices and column-start window are being fetched.
-    typedef VtmChunk<IdxT, ValT, ITEMS, SLW> Chunk;
+    // values, indices and column-start bits are being fetched.
+    typedef VtmChunk<IdxT, ValT, ITEMS> Chunk;
     Chunk A, B;
-    auto load_chunk = [&](Chunk &C, int64_t cc, int jl) {
+    auto load_chunk = [&](Chunk &C, int64_t cc) {
         const int64_t cb = cc * WCH;
         C.a.load(val + cb, lane);
         C.r.load(idx + cb, lane);
-#pragma unroll
-        for (int t = 0; t < SLW; ++t) C.sl[t] = ptr[jl + lane + t * WAVE];
+        C.mask = heads[cc * WAVE + lane];
     };
-    // Reduces chunk cc held in C, after issuing the loads of chunk cn into N
-    // (when cn < nchunks).  jlo/jhi describe cc, jln describes cn.
-    auto step = [&](Chunk &C, Chunk &N, int64_t cc, int jlo, int jhi, int64_t cn, int jln) {
+    // Reduces chunk cc held in C (description ci), after issuing the loads of
+    // chunk cn into N (when cn < nchunks).
+    auto step = [&](Chunk &C, Chunk &N, int64_t cc, int4 ci, int64_t cn) {
         const int s = (int)(cc * WCH);
         const int e = (int)min((int64_t)s + WCH, nnz);
-        const int ncol = jhi - jlo + 2;           // starts of columns jlo .. jhi+1
-        const bool in_lds = ncol <= SLICE_W;
-#pragma unroll
-        for (int t = 0; t < SLW; ++t) slice[lane + t * WAVE] = C.sl[t];
         for (int col = 0; col < k; ++col) {
             double prod[ITEMS];
 #pragma unroll
@@ -390,37 +396,26 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
                 // issued: the load counter is in order, so waiting for them
                 // later would also wait for the prefetch.
                 __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
-                if (cn < nchunks) load_chunk(N, cn, jln);
-                wave_sync();
+                if (cn < nchunks) load_chunk(N, cn);
             }
             VecT *uc = MULTI ? out.u[col] : out.u[0];
             const int64_t ldu = MULTI ? out.ld[col] : 1;
-            if (in_lds)
-                vtm_reduce_chunk<ITEMS, VecT>(slice, prod, s, e, jlo, ncol, cc, lane, uc, ldu, carry, k, col);
-            else
-                vtm_reduce_chunk<ITEMS, VecT>(ptr + jlo, prod, s, e, jlo, ncol, cc, lane, uc, ldu, carry, k, col);
+            vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
         }
-        wave_sync();                              // slice reads done before it is rewritten
     };
 
-    // chunk sequence c, c + stride, ...; column ranges are loaded one step ahead
-    int jlo0 = cjlo[c], jhi0 = cjhi[c];
-    load_chunk(A, c, jlo0);
+    // chunk sequence c, c + stride, ...; chunk descriptions are loaded one step ahead
+    int4 ci0 = cinfo[c];
+    load_chunk(A, c);
     for (;;) {
         const int64_t c1 = c + stride;
-        int jlo1 = 0, jhi1 = 0;
-        if (c1 < nchunks) {
-            jlo1 = cjlo[c1];
-            jhi1 = cjhi[c1];
-        }
-        step(A, B, c, jlo0, jhi0, c1, jlo1);
+        int4 ci1 = make_int4(0, 0, 0, 0);
+        if (c1 < nchunks) ci1 = cinfo[c1];
+        step(A, B, c, ci0, c1);
         if (c1 >= nchunks) break;
         const int64_t c2 = c1 + stride;
-        if (c2 < nchunks) {
-            jlo0 = cjlo[c2];
-            jhi0 = cjhi[c2];
-        }
-        step(B, A, c1, jlo1, jhi1, c2, jlo0);
+        if (c2 < nchunks) ci0 = cinfo[c2];
+        step(B, A, c1, ci1, c2);
         if (c2 >= nchunks) break;
         c = c2;
     }
@@ -820,10 +815,7 @@ int with_types(spw_dtype storage, spw_dtype vdt, Fn &&fn)
     return (int)hipErrorNotSupported;
 }
 
-int64_t hot_rows_limit(size_t vec_bytes)
-{
-    return (LDS_BYTES - (VTM_BLOCK / WAVE) * VTM_SLICE_W * 4 - 256) / (int64_t)vec_bytes;
-}
+int64_t hot_rows_limit(size_t vec_bytes) { return (LDS_BYTES - 256) / (int64_t)vec_bytes; }
 
 template <typename IdxT, typename ValT, typename VecT, bool MULTI>
 int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
@@ -831,16 +823,15 @@ int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<
     const ColDot &C = A.cd;
     if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
     const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT) * (size_t)k));
-    const size_t lds = (((size_t)vhot * k * sizeof(VecT) + 15) & ~(size_t)15) +
-                       (size_t)(VTM_BLOCK / WAVE) * VTM_SLICE_W * 4;
+    const size_t lds = std::max<size_t>((size_t)vhot * k * sizeof(VecT), 16);
     const int cus = device_cu_count(A.device);
     const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
-    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, IdxT, ValT, VecT, MULTI>);
+    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
     (void)attr;
-    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, VTM_SLICE_W, IdxT, ValT, VecT, MULTI>), dim3(grid),
-                       dim3(VTM_BLOCK), lds, stream, C.d_ptr, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_cjlo,
-                       C.d_cjhi, C.nnz, C.zp.n_chunks, vin, k, vhot, out, A.scratch.carry);
+    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>), dim3(grid), dim3(VTM_BLOCK), lds,
+                       stream, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,
+                       C.d_segcol, C.nnz, C.zp.n_chunks, vin, k, vhot, out, A.scratch.carry);
     return (int)hipGetLastError();
 }
 

@@ -148,8 +148,12 @@ def wide(m: int, n: int, nnz: int, seed: int, len_alpha: float = 1.1, n_dense: i
     cdf = np.cumsum(pmf) / pmf.sum()
     cdf[-1] = 1.0
     rng = np.random.Generator(np.random.PCG64(s_len))
-    lengths = (np.searchsorted(cdf, rng.random(n), side="right") + 1).astype(np.int64)
-    np.minimum(lengths, K, out=lengths)
+    if target < 1.0:
+        # fewer nonzeros than columns: a column holds one nonzero with probability target
+        lengths = (rng.random(n) < target).astype(np.int64)
+    else:
+        lengths = (np.searchsorted(cdf, rng.random(n), side="right") + 1).astype(np.int64)
+        np.minimum(lengths, K, out=lengths)
     if n_dense:
         rd = np.random.Generator(np.random.PCG64(s_dense))
         cols = rd.choice(n, size=min(n_dense, n), replace=False)
@@ -208,3 +212,41 @@ def to_dense(A: Sparse) -> np.ndarray:
         s, e = A.ptr[j], A.ptr[j + 1]
         D[A.idx[s:e], j] = A.val[s:e]
     return D
+
+
+# --------------------------------------------------------------------------
+# Serving workload: many resident matrices and a stream of requests
+# --------------------------------------------------------------------------
+def serving_specs(count: int = 64, seed: int | None = None) -> list:
+    """Shapes of the resident matrices: m ~ logU[500, 5e4], n ~ logU[5e4, 5e6],
+    nnz ~ logU[1e5, 5e7] clamped to m*n/2; the first half are used as wide CSC
+    matrices, the second half as tall CSR matrices (the transposed arrays of a
+    generated wide one)."""
+    sid = SEED_BASE + CONFIG_IDS["c4"] if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([sid, 1])))
+    out = []
+    for i in range(count):
+        m = int(round(np.exp(rng.uniform(np.log(500), np.log(5e4)))))
+        n = int(round(np.exp(rng.uniform(np.log(5e4), np.log(5e6)))))
+        nnz = int(round(np.exp(rng.uniform(np.log(1e5), np.log(5e7)))))
+        nnz = min(nnz, m * n // 2)
+        out.append({"id": i, "m": m, "n": n, "nnz": nnz, "tall": i >= count // 2, "seed": sid * 1000 + i})
+    return out
+
+
+def serving_matrix(spec: dict) -> Sparse:
+    """The wide m x n matrix of a spec: the small-matrix generator (truncated
+    Zipf(1.1) column lengths, 5 dense columns, uniform rows and values)."""
+    return wide(spec["m"], spec["n"], spec["nnz"], spec["seed"], len_alpha=1.1,
+                n_dense=min(5, spec["n"]), dense_fill=1.0, row_alpha=None, values="uniform")
+
+
+def serving_requests(count: int, n_matrices: int, seed: int | None = None) -> dict:
+    """Request stream: matrix uniform, operation A x / v^T A 50/50, k ~ U{1..8},
+    vector type binary64 / binary32 50/50, exponential inter-arrival gaps of
+    mean 1 (scale by 1/rate)."""
+    sid = SEED_BASE + CONFIG_IDS["c4"] if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([sid, 2])))
+    return {"matrix": rng.integers(0, n_matrices, count), "op": rng.integers(0, 2, count),
+            "k": rng.integers(1, 9, count), "f32": rng.random(count) < 0.5,
+            "gap": rng.exponential(1.0, count)}
