@@ -615,6 +615,11 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
     out = ["# HBM traffic per launch, from rocprofv3 --pmc runs of `bench.py --profile-run`",
            "# FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
            "# the same counter on a 1 GiB device copy (copy_ kernel) to exactly 1 GiB.",
+           "# command: rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -- python3 bench.py --profile-run ; "
+           "rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -- python3 bench.py --profile-run ; "
+           "python3 bench.py --pmc-summary <fetch_dir> <write_dir>",
+           "# workload: wide CSC m=50000 n=2e7 nnz=200201679 (the benchmark matrix), binary64 values and "
+           "vectors, k=1",
            "kernel_source_sha256_16=%s" % kernel_hash()]
     per = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):

@@ -774,10 +774,20 @@ __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k
     out[g] = in[(int64_t)inv[r] * ldv + cc];
 }
 
-constexpr int VTM_BLOCK = 512;
+#ifndef SPW_VTM_BLOCK
+#define SPW_VTM_BLOCK 512
+#endif
+#ifndef SPW_VTM_WG_PER_CU
+#define SPW_VTM_WG_PER_CU 1
+#endif
+#ifndef SPW_MV_BLOCK
+#define SPW_MV_BLOCK 256
+#endif
+constexpr int VTM_BLOCK = SPW_VTM_BLOCK;
+constexpr int VTM_WG_PER_CU = SPW_VTM_WG_PER_CU;   // resident workgroups per CU (they share the LDS)
 constexpr int VTM_ITEMS = 16;
 constexpr int VTM_SLICE_W = 256;
-constexpr int MV_BLOCK = 256;
+constexpr int MV_BLOCK = SPW_MV_BLOCK;
 constexpr int LDS_BYTES = 160 * 1024;
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -815,7 +825,7 @@ int with_types(spw_dtype storage, spw_dtype vdt, Fn &&fn)
     return (int)hipErrorNotSupported;
 }
 
-int64_t hot_rows_limit(size_t vec_bytes) { return (LDS_BYTES - 256) / (int64_t)vec_bytes; }
+int64_t hot_rows_limit(size_t vec_bytes) { return (LDS_BYTES / VTM_WG_PER_CU - 256) / (int64_t)vec_bytes; }
 
 template <typename IdxT, typename ValT, typename VecT, bool MULTI>
 int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
@@ -826,7 +836,7 @@ int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<
     const size_t lds = std::max<size_t>((size_t)vhot * k * sizeof(VecT), 16);
     const int cus = device_cu_count(A.device);
     const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cus, wgs_needed));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
     static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
     (void)attr;
     hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>), dim3(grid), dim3(VTM_BLOCK), lds,
