@@ -833,9 +833,8 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
     } else {
-        // column dots: the chunk is read once per pass of up to 8 columns and
-        // each column is reduced exactly as a single vector would be
-        e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
+        // column dots for k columns in one pass over the matrix
+        e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
     }
     if (e == (int)hipErrorNotSupported)
         return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");

@@ -590,110 +590,267 @@ __global__ void mv_reduce(const double *__restrict__ partial, int panel_rows, co
 }
 
 // ------------------------------------------------------------------------
-// Multi-RHS column dots: U = C^T V for k right-hand sides (V is rows x k and U
-// is cols x k, both row-major with leading dimensions ldv, ldu).  A group of
-// L lanes (L = k rounded up to a power of two) walks one 1024-nonzero chunk in
-// storage order, lane c carrying the running dot of the current column with
-// column c of V; the 64/L groups of a wave take different chunks.  Columns are
-// cut at chunk boundaries exactly as in the single-vector kernel, with k-wide
-// carries: carry[(2*chunk + side)*k + c].  The chunk storage is the same
-// interleaved layout, so positions are mapped to their slots here.  Columns
-// without nonzeros are written by zero_cols_batch.
+// Multi-RHS column dots, tiled: U = C^T V for 2 <= k <= 64 right-hand sides.
+// One wave per 1,024-position chunk.  Lane g*L + c is column lane c (L = k
+// rounded up to a power of two) of sub-group g (S = 64/L sub-groups), and
+// sub-group g walks positions [g*16L, (g+1)*16L) of the chunk in batches of 8
+// (layout lanes g*L .. g*L+L-1 of the interleaved storage; the L lanes of a
+// sub-group read the same words).  Column boundaries come from the
+// column-start bits as in the single-vector kernel, with sub-groups in place
+// of lanes: a sub-group's interior columns are final, its first and last runs
+// are joined across sub-groups by the segmented scan, and chunk-cut columns
+// leave k-wide carries.  V is row-major (leading dimension ldv): the L lanes of
+// a sub-group read one contiguous row segment per item, so every v gather
+// touches one or two cache lines.  Products are fused multiply-adds.  Loads
+// run ahead of the arithmetic: indices two batches ahead, values and v
+// entries one batch ahead, across chunk boundaries.
 // ------------------------------------------------------------------------
-template <typename IdxT> struct IdxSlot;
-template <> struct IdxSlot<uint16_t> {
-    static constexpr int G = 8;
+template <typename IdxT> struct Idx8;            // indices of items half*8 .. half*8+7 of one layout lane
+template <> struct Idx8<uint16_t> {
+    uint32_t w[4];
+    __device__ __forceinline__ void load(const uint16_t *cb, int ll, int half)
+    {
+        const u32x4_t q = *reinterpret_cast<const u32x4_t *>(cb + (int64_t)(half * 64 + ll) * 8);
+        w[0] = q.x;
+        w[1] = q.y;
+        w[2] = q.z;
+        w[3] = q.w;
+    }
+    __device__ __forceinline__ int get(int j) const { return (int)((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu); }
 };
-template <> struct IdxSlot<int32_t> {
-    static constexpr int G = 4;
+template <> struct Idx8<int32_t> {
+    uint32_t w[8];
+    __device__ __forceinline__ void load(const int32_t *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const u32x4_t q = *reinterpret_cast<const u32x4_t *>(cb + (int64_t)((half * 2 + p) * 64 + ll) * 4);
+            w[4 * p] = q.x;
+            w[4 * p + 1] = q.y;
+            w[4 * p + 2] = q.z;
+            w[4 * p + 3] = q.w;
+        }
+    }
+    __device__ __forceinline__ int get(int j) const { return (int)w[j]; }
+};
+template <typename ValT> struct Val8;           // values of items half*8 .. half*8+7 of one layout lane
+template <> struct Val8<double> {
+    double a[8];
+    __device__ __forceinline__ void load(const double *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const f64x2_t q = *reinterpret_cast<const f64x2_t *>(cb + (int64_t)((half * 4 + p) * 64 + ll) * 2);
+            a[2 * p] = q.x;
+            a[2 * p + 1] = q.y;
+        }
+    }
+    __device__ __forceinline__ double get(int j) const { return a[j]; }
+};
+template <> struct Val8<float> {
+    float a[8];
+    __device__ __forceinline__ void load(const float *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const f32x4_t q = *reinterpret_cast<const f32x4_t *>(cb + (int64_t)((half * 2 + p) * 64 + ll) * 4);
+            a[4 * p] = q.x;
+            a[4 * p + 1] = q.y;
+            a[4 * p + 2] = q.z;
+            a[4 * p + 3] = q.w;
+        }
+    }
+    __device__ __forceinline__ double get(int j) const { return (double)a[j]; }
+};
+template <> struct Val8<Bf16> {
+    uint32_t w[4];
+    __device__ __forceinline__ void load(const Bf16 *cb, int ll, int half)
+    {
+        const u32x4_t q =
+            *reinterpret_cast<const u32x4_t *>(reinterpret_cast<const uint16_t *>(cb) + (int64_t)(half * 64 + ll) * 8);
+        w[0] = q.x;
+        w[1] = q.y;
+        w[2] = q.z;
+        w[3] = q.w;
+    }
+    __device__ __forceinline__ double get(int j) const
+    {
+        return bf16_bits_to_f64((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu);
+    }
 };
 
-template <typename IdxT, int L, typename ValT, typename VinT, typename VoutT>
-__global__ __launch_bounds__(L * (L <= 8 ? 64 : 512 / L)) void coldot_batch(
-    const int32_t *__restrict__ ptr, const IdxT *__restrict__ idx, const ValT *__restrict__ val,
-    const int32_t *__restrict__ cjlo, const int32_t *__restrict__ cjhi, int64_t nnz, int64_t nchunks, int k,
-    const VinT *__restrict__ V, int64_t ldv, VoutT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
+template <typename VecT> struct TileGather {
+    VecT gv[8];                 // v at the rows of the 8 items
+    uint32_t m;                 // column-start bits of the 8 items
+};
+
+constexpr int TILE_BLOCK = 256;
+
+template <typename IdxT, typename ValT, typename VecT, int L>
+__global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
+    const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
+    const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
+    const VecT *__restrict__ V, int64_t ldv, VecT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
 {
-    constexpr int WCH = 1024, ITEMS = 16, GI = IdxSlot<IdxT>::G, GV = ValGroup<ValT>::G;
-    constexpr int GPB = L <= 8 ? 64 : 512 / L;    // groups per workgroup
-    constexpr int SL = 128;                       // column starts kept in LDS per group
-    constexpr int T = L >= 8 ? L : 8;             // positions a group fetches per step
-    constexpr int Q = T / L;                      // positions per lane per step
-    __shared__ int32_t slices[GPB * SL];
-    const int gl = threadIdx.x % L;
-    const int gid = threadIdx.x / L;
-    int32_t *slice = slices + gid * SL;
-    const bool colok = gl < k;
-    const int cl = min(gl, k - 1);                 // idle lanes read a valid column
-    const int64_t ngroups = (int64_t)gridDim.x * GPB;
-    for (int64_t c = (int64_t)blockIdx.x * GPB + gid; c < nchunks; c += ngroups) {
-        const int s = (int)(c * WCH);
-        const int e = (int)min((int64_t)s + WCH, nnz);
-        const int jlo = cjlo[c];
-        const int ncol = cjhi[c] - jlo + 2;
-        const bool in_lds = ncol <= SL;
-        if (in_lds)
-            for (int i = gl; i < ncol; i += L) slice[i] = ptr[jlo + i];
-        // the group's lanes belong to one wave, so a wave-level sync suffices
-        wave_sync();
-        int j = jlo;
-        int cend = in_lds ? slice[1] : ptr[jlo + 1];
-        bool before = (in_lds ? slice[0] : ptr[jlo]) < s;
-        double acc = 0.0;
-        auto emit = [&](int jj, double v, bool bef, bool aft) {
-            if (!colok) return;
-            if (bef) carry[(2 * c) * k + gl] = v;
-            else if (aft) carry[(2 * c + 1) * k + gl] = v;
-            else U[(int64_t)jj * ldu + gl] = (VoutT)v;
-        };
-        for (int p0 = s; p0 < e; p0 += T) {
-            // lane gl fetches positions p0 + gl + q*L
-            double a[Q];
-            int r[Q];
+    constexpr int S = WAVE / L;                   // sub-groups per wave
+    constexpr int NB = 2 * L;                     // batches of 8 per sub-group and chunk
+    constexpr int SPAN = 16 * L;                  // positions per sub-group
+    constexpr int WCH = 1024;
+    constexpr int NW = TILE_BLOCK / WAVE;
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int g = lane / L, cl = lane % L;
+    const bool colok = cl < k;
+    const int vc = min(cl, k - 1);                // idle lanes read a valid column
+    const int64_t nw = (int64_t)gridDim.x * NW;
+    const int64_t chunk0 = (int64_t)blockIdx.x * NW + wave;
+    if (chunk0 >= nchunks) return;
+    const int64_t nchunk_w = (nchunks - 1 - chunk0) / nw + 1;     // chunks of this wave
+    const int64_t nq = nchunk_w * NB;                              // batches of this wave
+    const int64_t clast = chunk0 + (nchunk_w - 1) * nw;
+
+    auto chunk_of = [&](int64_t q) __attribute__((always_inline)) { return chunk0 + (q / NB) * nw; };
+    auto load_idx = [&](Idx8<IdxT> &R, uint32_t &m, int64_t q) __attribute__((always_inline)) {
+        q = min(q, nq - 1);
+        const int64_t cc = chunk_of(q);
+        const int b = (int)(q % NB), ll = g * L + (b >> 1), half = b & 1;
+        R.load(idx + cc * WCH, ll, half);
+        m = ((uint32_t)heads[cc * WAVE + ll] >> (half * 8)) & 0xFFu;
+    };
+    auto load_val = [&](Val8<ValT> &A, int64_t q) __attribute__((always_inline)) {
+        q = min(q, nq - 1);
+        const int64_t cc = chunk_of(q);
+        const int b = (int)(q % NB);
+        A.load(val + cc * WCH, g * L + (b >> 1), b & 1);
+    };
+    auto gather = [&](TileGather<VecT> &G, const Idx8<IdxT> &R, uint32_t m) __attribute__((always_inline)) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const int pp = p0 + gl + q * L;
-                a[q] = 0.0;
-                r[q] = 0;
-                if (pp < e) {
-                    const int o = pp - s, ln = o / ITEMS, i = o % ITEMS;
-                    a[q] = val_at(val, s + ((i / GV) * 64 + ln) * GV + i % GV);
-                    r[q] = (int)idx[s + ((i / GI) * 64 + ln) * GI + i % GI];
-                }
+        for (int j = 0; j < 8; ++j) G.gv[j] = V[(int64_t)R.get(j) * ldv + vc];
+        G.m = m;
+    };
+
+    // per-chunk walk state; the next chunk's description and column-start
+    // bits are loaded one chunk ahead
+    int4 ci = make_int4(0, 0, 0, 0), ci_n = cinfo[chunk0];
+    uint32_t mask_n = heads[chunk0 * WAVE + lane];
+    int base = 0, rel = 0, hk = 0, my_n = 0, s = 0, e = 0;
+    double run = 0.0, head_sum = 0.0;
+    bool multi = false;
+    int64_t cc = chunk0;
+
+    auto column = [&](int q) __attribute__((always_inline)) -> int64_t {
+        return (ci.w & CHUNK_DENSE) ? (int64_t)ci.x + q : (int64_t)segcol[ci.y + q];
+    };
+    auto emit = [&](int q, double value) __attribute__((always_inline)) {
+        if (!colok) return;
+        const bool before = q == 0 && !(ci.w & CHUNK_START_HEAD);
+        const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
+        if (before) carry[(2 * cc) * k + cl] = value;
+        else if (after) carry[(2 * cc + 1) * k + cl] = value;
+        else U[column(q) * ldu + cl] = (VecT)value;
+    };
+    auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
+        cc = c;
+        ci = ci_n;
+        const uint32_t mask = mask_n;
+        {
+            const int64_t cn = min(c + nw, clast);
+            ci_n = cinfo[cn];
+            mask_n = heads[cn * WAVE + lane];
+        }
+        s = (int)(c * WCH);
+        e = (int)min((int64_t)s + WCH, nnz);
+        // first segment of each sub-group: column starts after position s in
+        // earlier layout lanes, plus its own first position
+        const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
+        const int cnt = __popc(after_s);
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int t = __shfl_up(incl, off, WAVE);
+            if (lane >= off) incl += t;
+        }
+        const int first_ll = g * L;
+        const int excl = __shfl(incl - cnt, first_ll, WAVE);
+        const uint32_t m0 = (uint32_t)__shfl((int)mask, first_ll, WAVE);
+        base = excl + (g > 0 ? (int)(m0 & 1u) : 0);
+        my_n = max(0, min(SPAN, e - (s + g * SPAN)));
+        rel = 0;
+        run = 0.0;
+        head_sum = 0.0;
+        multi = false;
+    };
+    auto chunk_end = [&]() __attribute__((always_inline)) {
+        const int klast = my_n > 0 ? base + rel : -2 - g;
+        const int hkey = my_n > 0 ? (multi ? base + hk : klast) : -2 - g;
+        SegPair x{run, klast};
+#pragma unroll
+        for (int off = 1; off < S; off <<= 1) {
+            const double ps = __shfl_up(x.s, off * L, WAVE);
+            const int pk = __shfl_up(x.k, off * L, WAVE);
+            if (g >= off) x = seg_op(SegPair{ps, pk}, x);
+        }
+        double prev_s = 0.0;
+        int prev_k = -1, next_hk = -1;
+        if (S > 1) {
+            prev_s = __shfl_up(x.s, L, WAVE);
+            prev_k = __shfl_up(x.k, L, WAVE);
+            next_hk = __shfl_down(hkey, L, WAVE);
+        }
+        if (my_n > 0) {
+            if (multi) {
+                double tot = head_sum;
+                if (g > 0 && prev_k == hkey) tot = prev_s + head_sum;
+                emit(hkey, tot);
             }
-            const int steps = min(T, e - p0);
+            if (g == S - 1 || next_hk != klast) emit(klast, x.s);
+        }
+    };
+    auto compute = [&](int64_t q, const Val8<ValT> &A, const TileGather<VecT> &G) __attribute__((always_inline)) {
+        const int b = (int)(q % NB);
+        if (b == 0) chunk_start(chunk_of(q));
 #pragma unroll
-            for (int t0 = 0; t0 < T; t0 += 8) {
-                // eight gathers in flight before they are used
-                double at[8], vv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int t = t0 + u;
-                    at[u] = __shfl(a[t / L], t % L, L);
-                    const int rt = __shfl(r[t / L], t % L, L);
-                    vv[u] = (double)V[(int64_t)rt * ldv + cl];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int t = t0 + u;
-                    if (t < steps) {
-                        const int p = p0 + t;
-                        while (p >= cend) {            // the current column ends before p
-                            emit(j, acc, before, false);
-                            acc = 0.0;
-                            before = false;
-                            do {
-                                ++j;
-                                cend = in_lds ? slice[j + 1 - jlo] : ptr[j + 1];
-                            } while (cend <= p);       // skip columns without nonzeros
-                        }
-                        acc += at[u] * vv[u];
+        for (int j = 0; j < 8; ++j) {
+            const int t = b * 8 + j;
+            if (t < my_n) {
+                if (t > 0 && ((G.m >> j) & 1u)) {
+                    if (!multi) {
+                        head_sum = run;
+                        hk = rel;
+                        multi = true;
+                    } else {
+                        if (colok) U[column(base + rel) * ldu + cl] = (VecT)run;   // column wholly inside
                     }
+                    ++rel;
+                    run = 0.0;
                 }
+                run = __fma_rn(A.get(j), (double)G.gv[j], run);
             }
         }
-        emit(j, acc, before, cend > e);
-        wave_sync();                                   // slice reads done before it is rewritten
+        if (b == NB - 1) chunk_end();
+    };
+
+    Val8<ValT> A0, A1;
+    Idx8<IdxT> R0, R1;
+    uint32_t m0 = 0, m1 = 0;
+    TileGather<VecT> G0, G1;
+    load_idx(R0, m0, 0);
+    load_val(A0, 0);
+    load_idx(R1, m1, 1);
+    gather(G0, R0, m0);
+    // step q: values of q+1, indices of q+2, gathers of q+1, then batch q
+    for (int64_t q = 0;; q += 2) {
+        load_val(A1, q + 1);
+        load_idx(R0, m0, q + 2);
+        gather(G1, R1, m1);
+        compute(q, A0, G0);
+        if (q + 1 >= nq) break;
+        load_val(A0, q + 2);
+        load_idx(R1, m1, q + 3);
+        gather(G0, R0, m0);
+        compute(q + 1, A1, G1);
+        if (q + 2 >= nq) break;
     }
 }
 
@@ -1053,30 +1210,42 @@ int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *
 }
 
 namespace {
-template <typename IdxT, typename ValT, typename VinT, typename VoutT>
-int launch_batch_kernel(const ColDot &C, int L, int k, const VinT *V, int64_t ldv, VoutT *U, int64_t ldu,
-                        double *carry, hipStream_t stream)
+template <typename IdxT, typename ValT, typename VecT>
+int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
+                hipStream_t stream)
 {
-    const int64_t gpb = L <= 8 ? 64 : 512 / L;
-    const int64_t want = (C.zp.n_chunks + gpb - 1) / gpb;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, 256 * 16));
-#define SPW_BATCH_CASE(LL)                                                                                          \
-    case LL:                                                                                                        \
-        hipLaunchKernelGGL((coldot_batch<IdxT, LL, ValT, VinT, VoutT>), dim3(grid), dim3(LL * gpb), 0, stream,     \
-                           C.d_ptr, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_cjlo, C.d_cjhi, C.nnz,      \
-                           C.zp.n_chunks, k, V, ldv, U, ldu, carry);                                                \
-        break;
+    int L = 2;
+    while (L < k) L <<= 1;
+    const int cus = device_cu_count(A.device);
+    const int64_t want = (C.zp.n_chunks + TILE_BLOCK / WAVE - 1) / (TILE_BLOCK / WAVE);
+    // persistent: as many workgroups as the chip keeps resident
+    auto per_cu = [](const void *kern) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, TILE_BLOCK, 0) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 1;
+        }
+        return nb;
+    };
+#define SPW_TILE_CASE(LL)                                                                                           \
+    case LL: {                                                                                                      \
+        static const int nb = per_cu((const void *)cdot_tile<IdxT, ValT, VecT, LL>);                               \
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));        \
+        hipLaunchKernelGGL((cdot_tile<IdxT, ValT, VecT, LL>), dim3(grid), dim3(TILE_BLOCK), 0, stream,              \
+                           (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,         \
+                           C.d_segcol, C.nnz, C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);                   \
+        break;                                                                                                      \
+    }
     switch (L) {
-        SPW_BATCH_CASE(1)
-        SPW_BATCH_CASE(2)
-        SPW_BATCH_CASE(4)
-        SPW_BATCH_CASE(8)
-        SPW_BATCH_CASE(16)
-        SPW_BATCH_CASE(32)
-        SPW_BATCH_CASE(64)
+        SPW_TILE_CASE(2)
+        SPW_TILE_CASE(4)
+        SPW_TILE_CASE(8)
+        SPW_TILE_CASE(16)
+        SPW_TILE_CASE(32)
+        SPW_TILE_CASE(64)
     default: return (int)hipErrorInvalidValue;
     }
-#undef SPW_BATCH_CASE
+#undef SPW_TILE_CASE
     return (int)hipGetLastError();
 }
 
@@ -1092,10 +1261,8 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
         if ((e = (int)hipGetLastError())) return e;
     }
     if (C.nnz == 0) return 0;
-    int L = 1;
-    while (L < k) L <<= 1;
     {
-        ProfScope ps(stream, "coldot_batch");
+        ProfScope ps(stream, "cdot_tile");
         const VecT *Vin = V;
         int64_t ldin = ldv;
         if (inv) {
@@ -1106,9 +1273,8 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
             Vin = vp;
             ldin = k;
         }
-        e = C.idx_kind == IdxKind::U16
-                ? launch_batch_kernel<uint16_t, ValT, VecT, VecT>(C, L, k, Vin, ldin, U, ldu, A.scratch.carry, stream)
-                : launch_batch_kernel<int32_t, ValT, VecT, VecT>(C, L, k, Vin, ldin, U, ldu, A.scratch.carry, stream);
+        e = C.idx_kind == IdxKind::U16 ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream)
+                                       : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream);
         if (e) return e;
     }
     if (C.n_zones > 0) {
