@@ -582,21 +582,22 @@ def bench_serving(args):
 
 def batch_plan(info, k):
     """The kernel configuration the library uses for a k-wide block (its fixed rule)."""
-    L = 1
+    L = 2
     while L < k:
         L *= 2
-    gpb = 64 if L <= 8 else 512 // L
-    if k == 1 or k <= 4:
+    tile = ("chunks of 1024 nonzeros, one chunk per wave: %d column lanes x %d position sub-groups of %d "
+            "nonzeros, batches of 8, 256-thread workgroups" % (L, 64 // L, 16 * L))
+    if k <= 8:
         mv = ("%d scatter pass(es): %d row panel(s) of %d rows in LDS, %d workgroups x 4 waves, blocks of 1024 "
               "nonzeros" % (k, info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
     else:
-        mv = ("column dots over the kept transpose: chunks of 1024 nonzeros, %d-lane groups, %d groups "
-              "(%d threads) per workgroup" % (L, gpb, L * gpb))
+        mv = "column dots over the kept transpose: " + tile
     if k == 1:
         vtm = "column dots: chunks of 1024 nonzeros, one wave per chunk, 512-thread persistent workgroups"
+    elif k == 2:
+        vtm = "column dots, chunk loaded once and reduced per column: chunks of 1024 nonzeros, one wave per chunk"
     else:
-        vtm = ("column dots: chunks of 1024 nonzeros, %d-lane groups, %d groups (%d threads) per workgroup"
-               % (L, gpb, L * gpb))
+        vtm = "column dots: " + tile
     return {"mv": mv, "vtm": vtm, "chunk_nnz": info["chunk_nnz"]}
 
 

@@ -78,7 +78,7 @@ typedef struct spw_matrix_s *spw_matrix;
  *   device        : HIP device ordinal, -1 = the current device.
  *   transpose     : -1 (default) or 1 also keeps the transpose, which the
  *                   multi-RHS products of the long-to-short direction (CSC A x,
- *                   CSR v^T A) use for k > 4 (one pass over A for all k
+ *                   CSR v^T A) use for k > 8 (one pass over A for all k
  *                   columns); 0 saves that memory, and those blocks then run
  *                   one scatter pass per column. */
 typedef struct {

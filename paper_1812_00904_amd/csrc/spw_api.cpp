@@ -821,7 +821,7 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     int e;
     if (k == 1 && ldi == 1 && ldo == 1) {
         e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
-    } else if (scatter && (k <= 4 || !A->cdt.built)) {
+    } else if (scatter && (k <= 8 || !A->cdt.built)) {
         // few right-hand sides (or no transpose kept): one scatter pass per
         // column, which reads A k times but gathers x once per nonzero
         e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
@@ -832,6 +832,9 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         } else {
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
+    } else if (k <= 2) {
+        // two columns: each chunk read once and reduced per column
+        e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     } else {
         // column dots for k columns in one pass over the matrix
         e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);

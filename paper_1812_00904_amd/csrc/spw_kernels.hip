@@ -679,21 +679,51 @@ template <> struct Val8<Bf16> {
     }
 };
 
-template <typename VecT> struct TileGather {
-    VecT gv[8];                 // v at the rows of the 8 items
-    uint32_t m;                 // column-start bits of the 8 items
+// BS consecutive items of one layout lane: part p holds items p*BS .. p*BS+BS-1.
+template <typename IdxT, int BS> struct IdxB;
+template <typename IdxT> struct IdxB<IdxT, 8> {
+    Idx8<IdxT> r;
+    __device__ __forceinline__ void load(const IdxT *cb, int ll, int part) { r.load(cb, ll, part); }
+    __device__ __forceinline__ int get(int j) const { return r.get(j); }
 };
+template <typename IdxT> struct IdxB<IdxT, 16> {
+    IdxRaw<IdxT, 16> r;
+    __device__ __forceinline__ void load(const IdxT *cb, int ll, int) { r.load(cb, ll); }
+    __device__ __forceinline__ int get(int j) const { return r.get(j); }
+};
+template <typename ValT, int BS> struct ValB;
+template <typename ValT> struct ValB<ValT, 8> {
+    Val8<ValT> a;
+    __device__ __forceinline__ void load(const ValT *cb, int ll, int part) { a.load(cb, ll, part); }
+    __device__ __forceinline__ double get(int j) const { return a.get(j); }
+};
+template <typename ValT> struct ValB<ValT, 16> {
+    ValRaw<ValT, 16> a;
+    __device__ __forceinline__ void load(const ValT *cb, int ll, int) { a.load(cb, ll); }
+    __device__ __forceinline__ double get(int j) const { return a.get(j); }
+};
+
+template <typename VecT, int BS> struct TileGather {
+    VecT gv[BS];                // v at the rows of the batch's items
+    uint32_t m;                 // column-start bits of the batch's items
+};
+
+#ifndef SPW_TILE_BS
+#define SPW_TILE_BS 8
+#endif
+constexpr int TILE_BS = SPW_TILE_BS;            // positions per batch
 
 constexpr int TILE_BLOCK = 256;
 
-template <typename IdxT, typename ValT, typename VecT, int L>
+template <typename IdxT, typename ValT, typename VecT, int L, int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
     const VecT *__restrict__ V, int64_t ldv, VecT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
 {
     constexpr int S = WAVE / L;                   // sub-groups per wave
-    constexpr int NB = 2 * L;                     // batches of 8 per sub-group and chunk
+    constexpr int PPL = 16 / BS;                  // batches per layout lane
+    constexpr int NB = L * PPL;                   // batches per sub-group and chunk
     constexpr int SPAN = 16 * L;                  // positions per sub-group
     constexpr int WCH = 1024;
     constexpr int NW = TILE_BLOCK / WAVE;
@@ -711,22 +741,22 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const int64_t clast = chunk0 + (nchunk_w - 1) * nw;
 
     auto chunk_of = [&](int64_t q) __attribute__((always_inline)) { return chunk0 + (q / NB) * nw; };
-    auto load_idx = [&](Idx8<IdxT> &R, uint32_t &m, int64_t q) __attribute__((always_inline)) {
+    auto load_idx = [&](IdxB<IdxT, BS> &R, uint32_t &m, int64_t q) __attribute__((always_inline)) {
         q = min(q, nq - 1);
         const int64_t cc = chunk_of(q);
-        const int b = (int)(q % NB), ll = g * L + (b >> 1), half = b & 1;
-        R.load(idx + cc * WCH, ll, half);
-        m = ((uint32_t)heads[cc * WAVE + ll] >> (half * 8)) & 0xFFu;
+        const int b = (int)(q % NB), ll = g * L + b / PPL, part = b % PPL;
+        R.load(idx + cc * WCH, ll, part);
+        m = ((uint32_t)heads[cc * WAVE + ll] >> (part * BS)) & ((1u << BS) - 1u);
     };
-    auto load_val = [&](Val8<ValT> &A, int64_t q) __attribute__((always_inline)) {
+    auto load_val = [&](ValB<ValT, BS> &A, int64_t q) __attribute__((always_inline)) {
         q = min(q, nq - 1);
         const int64_t cc = chunk_of(q);
         const int b = (int)(q % NB);
-        A.load(val + cc * WCH, g * L + (b >> 1), b & 1);
+        A.load(val + cc * WCH, g * L + b / PPL, b % PPL);
     };
-    auto gather = [&](TileGather<VecT> &G, const Idx8<IdxT> &R, uint32_t m) __attribute__((always_inline)) {
+    auto gather = [&](TileGather<VecT, BS> &G, const IdxB<IdxT, BS> &R, uint32_t m) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) G.gv[j] = V[(int64_t)R.get(j) * ldv + vc];
+        for (int j = 0; j < BS; ++j) G.gv[j] = V[(int64_t)R.get(j) * ldv + vc];
         G.m = m;
     };
 
@@ -807,12 +837,12 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
             if (g == S - 1 || next_hk != klast) emit(klast, x.s);
         }
     };
-    auto compute = [&](int64_t q, const Val8<ValT> &A, const TileGather<VecT> &G) __attribute__((always_inline)) {
+    auto compute = [&](int64_t q, const ValB<ValT, BS> &A, const TileGather<VecT, BS> &G) __attribute__((always_inline)) {
         const int b = (int)(q % NB);
         if (b == 0) chunk_start(chunk_of(q));
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int t = b * 8 + j;
+        for (int j = 0; j < BS; ++j) {
+            const int t = b * BS + j;
             if (t < my_n) {
                 if (t > 0 && ((G.m >> j) & 1u)) {
                     if (!multi) {
@@ -831,10 +861,10 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         if (b == NB - 1) chunk_end();
     };
 
-    Val8<ValT> A0, A1;
-    Idx8<IdxT> R0, R1;
+    ValB<ValT, BS> A0, A1;
+    IdxB<IdxT, BS> R0, R1;
     uint32_t m0 = 0, m1 = 0;
-    TileGather<VecT> G0, G1;
+    TileGather<VecT, BS> G0, G1;
     load_idx(R0, m0, 0);
     load_val(A0, 0);
     load_idx(R1, m1, 1);
