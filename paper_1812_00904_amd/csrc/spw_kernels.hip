@@ -35,6 +35,7 @@
 
 #include "spw_internal.h"
 
+
 namespace spw {
 namespace {
 
@@ -203,15 +204,58 @@ __device__ __forceinline__ SegPair seg_op(SegPair a, SegPair b)
     return (a.k == b.k) ? SegPair{a.s + b.s, b.k} : b;
 }
 
+// Data-parallel-primitive (DPP) moves: row_shr:n shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 pass lane 15 / 31 to the following rows
+// (row masks 0xA / 0xC).  Lanes without a source keep `old`.
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_int(int old, int src)
+{
+    return __builtin_amdgcn_update_dpp(old, src, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_double(double old, double src)
+{
+    const long long o = __double_as_longlong(old), v = __double_as_longlong(src);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)v, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(v >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Inclusive sum of an int over the lanes of a wave.
+__device__ __forceinline__ int wave_prefix_sum(int x)
+{
+    x += dpp_int<DPP_ROW_SHR1, 0xF>(0, x);
+    x += dpp_int<DPP_ROW_SHR2, 0xF>(0, x);
+    x += dpp_int<DPP_ROW_SHR4, 0xF>(0, x);
+    x += dpp_int<DPP_ROW_SHR8, 0xF>(0, x);
+    x += dpp_int<DPP_ROW_BCAST15, 0xA>(0, x);
+    x += dpp_int<DPP_ROW_BCAST31, 0xC>(0, x);
+    return x;
+}
+
+// One step of the segmented scan: combine with the pair CTRL brings in.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(SegPair &x)
+{
+    const int pk = dpp_int<CTRL, ROWS>(-1, x.k);   // -1: no source (keys of live runs are >= 0)
+    const double ps = dpp_double<CTRL, ROWS>(0.0, x.s);
+    x = seg_op(SegPair{ps, pk}, x);
+}
+
+// Segmented inclusive scan over the lanes of a wave.  The keys must not
+// decrease from lane to lane except into keys no other lane holds (then a
+// lane equal to the last lane of an earlier row shares its run from there).
 __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        const double ps = __shfl_up(x.s, off, WAVE);
-        const int pk = __shfl_up(x.k, off, WAVE);
-        if (lane >= off) x = seg_op(SegPair{ps, pk}, x);
-    }
+    seg_step<DPP_ROW_SHR1, 0xF>(x);
+    seg_step<DPP_ROW_SHR2, 0xF>(x);
+    seg_step<DPP_ROW_SHR4, 0xF>(x);
+    seg_step<DPP_ROW_SHR8, 0xF>(x);
+    seg_step<DPP_ROW_BCAST15, 0xA>(x);
+    seg_step<DPP_ROW_BCAST31, 0xC>(x);
     return x;
 }
 
@@ -265,12 +309,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const double *prod, uint32_t ma
     // column starts after position s in this lane, and in all earlier lanes
     const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
     const int cnt = __popc(after_s);
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        const int t = __shfl_up(incl, off, WAVE);
-        if (lane >= off) incl += t;
-    }
+    const int incl = wave_prefix_sum(cnt);
     double head_sum = 0.0, run = 0.0;
     int hk, k;
     bool multi = false;
