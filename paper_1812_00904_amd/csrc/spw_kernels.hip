@@ -360,6 +360,26 @@ __device__ __forceinline__ void vtm_reduce_chunk(const double *prod, uint32_t ma
     }
 }
 
+// dst[i] = src(i) for i < n, by the BLOCK threads of a workgroup, with U loads
+// in flight per thread (a load-then-store loop would wait for every load).
+template <int BLOCK, int U, typename T, typename Src>
+__device__ __forceinline__ void stage_rows(T *dst, int n, Src src)
+{
+    for (int base = 0; base < n; base += BLOCK * U) {
+        T tmp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * BLOCK + (int)threadIdx.x;
+            tmp[u] = i < n ? src(i) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + u * BLOCK + (int)threadIdx.x;
+            if (i < n) dst[i] = tmp[u];
+        }
+    }
+}
+
 template <typename IdxT, typename ValT, int ITEMS> struct VtmChunk {
     ValRaw<ValT, ITEMS> a;
     IdxRaw<IdxT, ITEMS> r;
@@ -388,12 +408,12 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
     const int lane = threadIdx.x & (WAVE - 1);
 
     if (MULTI) {
-        for (int i = threadIdx.x; i < vhot * k; i += BLOCK) {
+        stage_rows<BLOCK, 8, VecT>(vh, vhot * k, [&](int i) {
             const int r = i / k;
-            vh[i] = v[(int64_t)r * ldv + (i - r * k)];
-        }
+            return v[(int64_t)r * ldv + (i - r * k)];
+        });
     } else {
-        for (int i = threadIdx.x; i < vhot; i += BLOCK) vh[i] = v[i];
+        stage_rows<BLOCK, 16, VecT>(vh, vhot, [&](int i) { return v[i]; });
     }
     __syncthreads();
 
@@ -620,7 +640,17 @@ __global__ void mv_reduce(const double *__restrict__ partial, int panel_rows, co
         const int local = (int)(r - (int64_t)p * panel_rows);
         const PanelDesc pd = panels[p];
         const double *src = partial + (int64_t)pd.wg0 * panel_rows + local;
-        for (int w = t; w < pd.nwg; w += 8) s += src[(int64_t)w * panel_rows];
+        int w = t;
+        for (; w + 24 < pd.nwg; w += 32) {
+            // four loads in flight, added in the same order as one at a time
+            const double a0 = src[(int64_t)w * panel_rows], a1 = src[(int64_t)(w + 8) * panel_rows];
+            const double a2 = src[(int64_t)(w + 16) * panel_rows], a3 = src[(int64_t)(w + 24) * panel_rows];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; w < pd.nwg; w += 8) s += src[(int64_t)w * panel_rows];
     }
     s += __shfl_xor(s, 1, 8);
     s += __shfl_xor(s, 2, 8);
