@@ -78,7 +78,7 @@ def run_case(spw, A, fmt, k, dtype, pad, seed, name, opts=None, reps=1):
 
 
 @pytest.mark.parametrize("fmt", [0, 1])
-@pytest.mark.parametrize("k", [1, 3, 4, 16, 64])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 9, 16, 24, 33, 64])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_small_config(spw, fmt, k, dtype):
     A = synth.config_matrix("c0", scale=0.2 if k < 64 else 0.05)
