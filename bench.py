@@ -136,6 +136,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the multi-RHS section")
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision storage section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
+    ap.add_argument("--no-partition", action="store_true", help="skip the column-partitioning comparison")
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.7",
                     help="comma-separated offered loads, as fractions of the plain path's capacity")
@@ -260,6 +261,10 @@ def main():
         del xd, vd, yd, ud
         torch.cuda.empty_cache()
         extra["batched"] = bench_batched(args)
+
+    if not args.no_partition:
+        torch.cuda.empty_cache()
+        extra["partition"] = bench_partition(args)
 
     if not args.no_serving:
         torch.cuda.empty_cache()
@@ -432,6 +437,53 @@ def bench_batched(args):
             torch.cuda.empty_cache()
         M.close()
     return res
+
+
+def bench_partition(args):
+    """Nonzero partitioning (the paper's method) against column partitioning
+    (its Section V comparison) on one GPU: the same kernels and results, only
+    the assignment of work to workers differs.  Three 5e7-nonzero matrices:
+    the batching matrix in generated order, the same with columns in
+    descending length (the worst case for column partitioning), and a
+    2,000 x 100,000 matrix with uniform column lengths (the best case).
+    Reports median kernel times of single-vector products and the column
+    partition's imbalance Delta = P (max - min) / nnz over its P workers."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1812_00904_amd import SPW_CSC, SPW_PART_COLUMN, SpwMatrix
+    base = synth.config_matrix("c2", scale=args.scale)
+    mats = [("batching matrix, generated order", base),
+            ("batching matrix, columns by descending length", synth.sort_columns_by_length(base)),
+            ("uniform lengths 2000 x 100000", synth.uniform_lengths(2000, max(int(100000 * args.scale), 1), 0.274,
+                                                                    100, 100, synth.SEED_BASE + 5))]
+    reps = max(args.steps // 2, 10)
+    out = []
+    for name, A in mats:
+        x = torch.rand(A.n, dtype=torch.float64, device="cuda") * 2 - 1
+        v = torch.rand(A.m, dtype=torch.float64, device="cuda") * 2 - 1
+        y = torch.empty(A.m, dtype=torch.float64, device="cuda")
+        u = torch.empty(A.n, dtype=torch.float64, device="cuda")
+        row = {"matrix": name, "m": A.m, "n": A.n, "nnz": A.nnz}
+        for label, opts in (("nonzero", {}), ("column", {"partition": SPW_PART_COLUMN})):
+            M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, transpose=0, **opts)
+            info = M.info()
+            mv50, _ = _time_each(lambda: M.mv(x, y), reps)
+            vt50, _ = _time_each(lambda: M.vtm(v, u), reps)
+            P = info["workers"]
+            row[label] = {"mv_ms": round(mv50, 4), "vtm_ms": round(vt50, 4), "workers": P,
+                          "worker_max_nnz": info["worker_max_nnz"], "worker_min_nnz": info["worker_min_nnz"],
+                          "imbalance_pct": round(100.0 * P * (info["worker_max_nnz"] - info["worker_min_nnz"])
+                                                 / max(A.nnz, 1), 2),
+                          "zones": info["n_zones"]}
+            M.close()
+        row["vtm_column_over_nonzero"] = round(row["column"]["vtm_ms"] / row["nonzero"]["vtm_ms"], 2)
+        row["mv_column_over_nonzero"] = round(row["column"]["mv_ms"] / row["nonzero"]["mv_ms"], 2)
+        out.append(row)
+        print("[bench] partition %s" % row, file=sys.stderr, flush=True)
+        del x, v, y, u
+        torch.cuda.empty_cache()
+    return {"rows": out}
 
 
 def bench_serving(args):

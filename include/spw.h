@@ -58,6 +58,14 @@ typedef enum { SPW_CSC = 0 /* wide, column-major */, SPW_CSR = 1 /* tall, row-ma
 
 typedef enum { SPW_F64 = 0, SPW_F32 = 1, SPW_BF16 = 2 } spw_dtype;
 
+/* How the work of one product is divided among the GPU's workers. */
+typedef enum {
+    SPW_PART_NONZERO = 0,  /* equal runs of nonzeros (Section II), the default */
+    SPW_PART_COLUMN = 1    /* equal numbers of columns of the long dimension: the column
+                              partitioning the paper compares against (Section V); same
+                              results, kept for that comparison */
+} spw_partition;
+
 typedef struct spw_matrix_s *spw_matrix;
 
 /* Creation options.  Zero-initialise, set struct_size = sizeof(spw_create_opts),
@@ -76,6 +84,12 @@ typedef struct spw_matrix_s *spw_matrix;
  *   validate      : 1 (default) checks the arrays in O(nnz); 0 trusts them.
  *   panel_rows    : rows per on-chip accumulation panel for A x (0 = automatic).
  *   device        : HIP device ordinal, -1 = the current device.
+ *   partition     : SPW_PART_NONZERO (default) or SPW_PART_COLUMN.  With column
+ *                   partitioning each worker of the single-vector products (a wave
+ *                   of the column dots, a workgroup of a scatter row panel) owns an
+ *                   equal number of consecutive columns, the first `cols mod P`
+ *                   workers one more; column dots give bit-identical results in
+ *                   either mode, the scatter product the same up to rounding order.
  *   transpose     : -1 (default) or 1 also keeps the transpose, which the
  *                   multi-RHS products of the long-to-short direction (CSC A x,
  *                   CSR v^T A) use for k > 8 (one pass over A for all k
@@ -90,7 +104,8 @@ typedef struct {
     int32_t panel_rows;
     int32_t device;
     int32_t transpose;
-    int32_t reserved[7];
+    spw_partition partition;
+    int32_t reserved[6];
 } spw_create_opts;
 
 /* Read-only description of a created matrix. */
@@ -112,7 +127,10 @@ typedef struct {
     int32_t device;
     int64_t device_bytes;         /* device memory held by the handle */
     int32_t has_transpose;        /* the transpose is kept (see spw_create_opts.transpose) */
-    int32_t reserved;
+    spw_partition partition;
+    int64_t workers;              /* P: workers of the single-vector column dots (waves) */
+    int64_t worker_max_nnz;       /* nonzeros owned by the busiest / idlest of them; the paper's */
+    int64_t worker_min_nnz;       /* imbalance is P * (max - min) / nnz (Section V) */
 } spw_matrix_info;
 
 /* ---------------------------------------------------------------- matrices */

@@ -360,6 +360,55 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
     return SPW_OK;
 }
 
+// Workers of the single-vector column dots and how much each owns.  Nonzero
+// partitioning: worker w reduces chunks w, w+P, ... (the kernel's grid
+// stride).  Column partitioning (Section V's comparison): worker w owns
+// columns [j0_w, j1_w), equal counts with the first cols mod P workers one
+// more, and reduces the chunks whose first position lies in its columns.
+spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_partition part)
+{
+    const int64_t nch = C.zp.n_chunks, P = vtm_workers(A.device, nch), W = vtm_chunk_default();
+    C.n_workers = P;
+    C.worker_max_nnz = C.worker_min_nnz = 0;
+    if (nch == 0) return SPW_OK;
+    if (part == SPW_PART_NONZERO) {
+        // worker w holds chunks w, w+P, ...; only the last chunk is short
+        const int64_t last_len = C.nnz - (nch - 1) * W;
+        int64_t mx = -1, mn = -1;
+        for (int64_t w = 0; w < std::min<int64_t>(P, nch + 1); ++w) {
+            const int64_t cnt = w < nch ? (nch - 1 - w) / P + 1 : 0;
+            int64_t z = cnt * W;
+            if (cnt > 0 && (nch - 1 - w) % P == 0) z -= W - last_len;    // holds the last chunk
+            mx = mx < 0 ? z : std::max(mx, z);
+            mn = mn < 0 ? z : std::min(mn, z);
+        }
+        if (P > nch) mn = 0;
+        C.worker_max_nnz = mx;
+        C.worker_min_nnz = mn;
+        return SPW_OK;
+    }
+    const int64_t cols = C.cols, q = cols / P, big = cols % P;
+    std::vector<int32_t> first((size_t)P + 1, (int32_t)nch);
+    int64_t mx = -1, mn = -1, j0 = 0, c = 0;
+    for (int64_t w = 0; w < P; ++w) {
+        const int64_t j1 = j0 + (w < big ? q + 1 : q);
+        const int64_t z = ptr[j1] - ptr[j0];
+        mx = mx < 0 ? z : std::max(mx, z);
+        mn = mn < 0 ? z : std::min(mn, z);
+        // chunks whose first position's column lies in [j0, j1)
+        first[(size_t)w] = (int32_t)c;
+        while (c < nch && C.zp.jlo[(size_t)c] < j1) ++c;
+        j0 = j1;
+    }
+    first[(size_t)P] = (int32_t)nch;
+    C.worker_max_nnz = mx;
+    C.worker_min_nnz = mn;
+    spw_status st;
+    if ((st = dev_alloc(A, &C.d_wchunks, P + 1, "worker chunk runs"))) return st;
+    if ((st = h2d(C.d_wchunks, first.data(), first.size() * 4, "worker chunk runs"))) return st;
+    return SPW_OK;
+}
+
 // Row panels, wave row sets and blocks of the scatter product (see
 // spw_internal.h and the scatter kernel).  rowi holds the internal
 // (renumbered) rows.
@@ -457,8 +506,20 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
         pd.wg0 = (int32_t)wr.size();
         if (qb > qa) {
             const int64_t nw = std::max<int64_t>(1, (int64_t)((double)target * (double)(qb - qa) / (double)nnz + 0.5));
+            const int64_t *pq = pptr.data() + q * (cols + 1);
+            int64_t j0 = 0;
             for (int64_t w = 0; w < nw; ++w) {
-                const int64_t a = qa + (qb - qa) * w / nw, b = qa + (qb - qa) * (w + 1) / nw;
+                int64_t a, b;
+                if (A.partition == SPW_PART_COLUMN) {
+                    // equal numbers of columns, the first cols mod nw one more
+                    const int64_t j1 = j0 + cols / nw + (w < cols % nw ? 1 : 0);
+                    a = pq[j0];
+                    b = pq[j1];
+                    j0 = j1;
+                } else {
+                    a = qa + (qb - qa) * w / nw;
+                    b = qa + (qb - qa) * (w + 1) / nw;
+                }
                 if (b > a) wr.push_back(WgRange{(int32_t)q, a, b});
             }
         }
@@ -652,6 +713,8 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     }
     if (opts.value_storage != SPW_F64 && opts.value_storage != SPW_F32 && opts.value_storage != SPW_BF16)
         return fail(SPW_ERR_INVALID_ARG, "spw_create: bad value_storage");
+    if (opts.partition != SPW_PART_NONZERO && opts.partition != SPW_PART_COLUMN)
+        return fail(SPW_ERR_INVALID_ARG, "spw_create: bad partition");
     const int64_t chunk = opts.chunk_nnz > 0 ? opts.chunk_nnz : vtm_chunk_default();
     if (chunk != vtm_chunk_default())
         return fail(SPW_ERR_UNSUPPORTED, "spw_create: chunk_nnz must be " + std::to_string(vtm_chunk_default()));
@@ -684,6 +747,7 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     std::unique_ptr<spw_matrix_s> A(new spw_matrix_s());
     A->format = fmt;
     A->value_storage = opts.value_storage;
+    A->partition = opts.partition;
     A->m = m;
     A->n = n;
     A->nnz = nnz;
@@ -727,6 +791,7 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
         });
     }
     if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val, A->value_storage))) return st;
+    if ((st = plan_workers(*A, A->cd, ptr, A->partition))) return st;
 
     // The transpose (caller's numbering), used by the multi-RHS scatter
     // products: its column dots are the rows of B.
@@ -795,6 +860,10 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *o)
     o->mv_workgroups = A->mv_wgs;
     o->index_bytes = A->cd.idx_kind == IdxKind::U16 ? 2 : 4;
     o->has_transpose = A->cdt.built ? 1 : 0;
+    o->partition = A->partition;
+    o->workers = A->cd.n_workers;
+    o->worker_max_nnz = A->cd.worker_max_nnz;
+    o->worker_min_nnz = A->cd.worker_min_nnz;
     o->relabeled = A->relabeled;
     o->device = A->device;
     o->device_bytes = A->device_bytes;

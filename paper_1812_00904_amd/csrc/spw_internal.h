@@ -66,6 +66,9 @@ struct ColDot {
     int64_t n_empty = 0;
     int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
     int64_t n_zones = 0;
+    int32_t *d_wchunks = nullptr;       // column partitioning: first chunk of each worker (n_workers+1)
+    int64_t n_workers = 0;              // workers (waves) of the single-vector column dots
+    int64_t worker_max_nnz = 0, worker_min_nnz = 0;
     uint16_t *d_heads = nullptr;        // per chunk and lane: column-start bits of the lane's positions
     int32_t *d_cinfo = nullptr;         // per chunk: first column, first segment, segments, flags
     int32_t *d_segcol = nullptr;        // per chunk segment: its column
@@ -84,6 +87,7 @@ struct Scratch {
 struct spw_matrix_s {
     spw_format format = SPW_CSC;
     spw_dtype value_storage = SPW_F64;
+    spw_partition partition = SPW_PART_NONZERO;
     int64_t m = 0, n = 0, nnz = 0;      // caller's shape
     int64_t rows = 0, cols = 0;         // B = short x long
     int device = 0;
@@ -146,6 +150,8 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
 int64_t mv_block_nnz();
 int64_t mv_waves();
 int64_t vtm_chunk_default();
+// Waves the single-vector column-dot kernel runs for nchunks chunks on device.
+int64_t vtm_workers(int device, int64_t nchunks);
 int64_t vtm_hot_rows_limit(spw_dtype vdt);
 int64_t vtm_slice_window();
 int device_cu_count(int device);

@@ -392,11 +392,15 @@ template <typename IdxT, typename ValT, int ITEMS> struct VtmChunk {
 // once and reduced once per column with exactly the single-vector arithmetic,
 // so every column equals the single-vector result bit for bit.  The hot rows
 // are staged in LDS as vh[r*k + col].
+// wchunks: NULL, or per worker (wave) the first chunk of its run, P+1 entries
+// (column partitioning: worker w reduces chunks wchunks[w] .. wchunks[w+1]-1
+// in order instead of every P-th chunk).
 template <int BLOCK, int ITEMS, typename IdxT, typename ValT, typename VecT, bool MULTI>
 __global__ __launch_bounds__(BLOCK) void vtm_wave(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks,
-    const VecT *__restrict__ v, int k, int vhot, ColOut<VecT> out, double *__restrict__ carry)
+    const int32_t *__restrict__ wchunks, const VecT *__restrict__ v, int k, int vhot, ColOut<VecT> out,
+    double *__restrict__ carry)
 {
     if (!MULTI) k = 1;
     const int64_t ldv = k;
@@ -417,9 +421,15 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
     }
     __syncthreads();
 
-    const int64_t stride = (int64_t)gridDim.x * NW;
+    int64_t stride = (int64_t)gridDim.x * NW;
     int64_t c = (int64_t)blockIdx.x * NW + wave;
-    if (c >= nchunks) return;
+    int64_t cend = nchunks;
+    if (wchunks) {
+        cend = wchunks[c + 1];
+        c = wchunks[c];
+        stride = 1;
+    }
+    if (c >= cend) return;
 
     // Two chunk buffers used alternately (no register copies, so no wait for
     // data still in flight): while one chunk is reduced, the next one's
@@ -455,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
                 // issued: the load counter is in order, so waiting for them
                 // later would also wait for the prefetch.
                 __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
-                if (cn < nchunks) load_chunk(N, cn);
+                if (cn < cend) load_chunk(N, cn);
             }
             VecT *uc = MULTI ? out.u[col] : out.u[0];
             const int64_t ldu = MULTI ? out.ld[col] : 1;
@@ -469,13 +479,13 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
     for (;;) {
         const int64_t c1 = c + stride;
         int4 ci1 = make_int4(0, 0, 0, 0);
-        if (c1 < nchunks) ci1 = cinfo[c1];
+        if (c1 < cend) ci1 = cinfo[c1];
         step(A, B, c, ci0, c1);
-        if (c1 >= nchunks) break;
+        if (c1 >= cend) break;
         const int64_t c2 = c1 + stride;
-        if (c2 < nchunks) ci0 = cinfo[c2];
+        if (c2 < cend) ci0 = cinfo[c2];
         step(B, A, c1, ci1, c2);
-        if (c2 >= nchunks) break;
+        if (c2 >= cend) break;
         c = c2;
     }
 }
@@ -1095,9 +1105,12 @@ int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
     static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
     (void)attr;
-    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>), dim3(grid), dim3(VTM_BLOCK), lds,
+    // column partitioning: one wave per worker of the plan (single-vector calls)
+    const int32_t *wch = (!MULTI && C.d_wchunks) ? C.d_wchunks : nullptr;
+    const unsigned g = wch ? (unsigned)(C.n_workers / (VTM_BLOCK / WAVE)) : grid;
+    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>), dim3(g), dim3(VTM_BLOCK), lds,
                        stream, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,
-                       C.d_segcol, C.nnz, C.zp.n_chunks, vin, k, vhot, out, A.scratch.carry);
+                       C.d_segcol, C.nnz, C.zp.n_chunks, wch, vin, k, vhot, out, A.scratch.carry);
     return (int)hipGetLastError();
 }
 
@@ -1234,6 +1247,13 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k)
 int64_t mv_block_nnz() { return MV_BLK; }
 int64_t mv_waves() { return MV_BLOCK / WAVE; }
 int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
+int64_t vtm_workers(int device, int64_t nchunks)
+{
+    const int64_t nw = VTM_BLOCK / WAVE;
+    const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cu_count(device) * VTM_WG_PER_CU,
+                                                               (nchunks + nw - 1) / nw));
+    return wgs * nw;
+}
 int64_t vtm_slice_window() { return VTM_SLICE_W; }
 int64_t vtm_hot_rows_limit(spw_dtype vdt) { return hot_rows_limit(vdt == SPW_F64 ? 8 : 4); }
 

@@ -22,6 +22,7 @@ STATUS_NAMES = ["SPW_OK", "SPW_ERR_INVALID_ARG", "SPW_ERR_BAD_MATRIX", "SPW_ERR_
                 "SPW_ERR_TIMEOUT", "SPW_ERR_SHUTDOWN"]
 SPW_CSC, SPW_CSR = 0, 1
 SPW_F64, SPW_F32, SPW_BF16 = 0, 1, 2
+SPW_PART_NONZERO, SPW_PART_COLUMN = 0, 1
 DTYPES = {SPW_F64: torch.float64, SPW_F32: torch.float32}
 
 
@@ -36,7 +37,8 @@ class CreateOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("value_storage", ctypes.c_int),
                 ("chunk_nnz", ctypes.c_int32), ("relabel", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("transpose", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("device", ctypes.c_int32), ("transpose", ctypes.c_int32), ("partition", ctypes.c_int),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -47,7 +49,8 @@ class MatrixInfo(ctypes.Structure):
                 ("n_panels", ctypes.c_int64), ("panel_rows", ctypes.c_int64),
                 ("mv_workgroups", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
                 ("relabeled", ctypes.c_int32), ("device", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
-                ("has_transpose", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("has_transpose", ctypes.c_int32), ("partition", ctypes.c_int), ("workers", ctypes.c_int64),
+                ("worker_max_nnz", ctypes.c_int64), ("worker_min_nnz", ctypes.c_int64)]
 
 
 SPW_OP_MV, SPW_OP_VTM = 0, 1

@@ -250,3 +250,32 @@ def serving_requests(count: int, n_matrices: int, seed: int | None = None) -> di
     return {"matrix": rng.integers(0, n_matrices, count), "op": rng.integers(0, 2, count),
             "k": rng.integers(1, 9, count), "f32": rng.random(count) < 0.5,
             "gap": rng.exponential(1.0, count)}
+
+
+# --------------------------------------------------------------------------
+# Column-partitioning comparison (the paper's Section V experiments)
+# --------------------------------------------------------------------------
+def sort_columns_by_length(A: Sparse) -> Sparse:
+    """The same matrix with its columns in descending order of length (ties by
+    index): the worst case for column partitioning."""
+    lengths = np.diff(A.ptr)
+    order = np.lexsort((np.arange(A.n), -lengths))
+    ptr = np.zeros(A.n + 1, dtype=np.int64)
+    np.cumsum(lengths[order], out=ptr[1:])
+    idx = np.empty_like(A.idx)
+    val = np.empty_like(A.val)
+    for new, old in enumerate(order):
+        s, e = A.ptr[old], A.ptr[old + 1]
+        idx[ptr[new]:ptr[new + 1]] = A.idx[s:e]
+        val[ptr[new]:ptr[new + 1]] = A.val[s:e]
+    return Sparse(A.m, A.n, ptr, idx, val)
+
+
+def uniform_lengths(m: int, n: int, rho: float, iota_minus: int, iota_plus: int, seed: int) -> Sparse:
+    """Column lengths uniform on [floor(rho m) - iota_minus, ceil(rho m) + iota_plus], rows uniform
+    without repeats, values uniform [-1, 1): the balanced random matrix of the comparison."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 3])))
+    lo = max(int(np.floor(rho * m)) - iota_minus, 0)
+    hi = min(int(np.ceil(rho * m)) + iota_plus, m)
+    lengths = rng.integers(lo, hi + 1, n).astype(np.int64)
+    return from_lengths(m, lengths, seed)
