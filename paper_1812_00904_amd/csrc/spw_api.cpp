@@ -444,7 +444,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
         std::vector<int32_t> cnt((size_t)(P * cols), 0);
         parallel_for(cols, [&](int64_t a, int64_t b) {
             for (int64_t j = a; j < b; ++j)
-                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) cnt[(size_t)(row_of(p) / R * cols + j)]++;
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) cnt[(size_t)(row_of(p) % P * cols + j)]++;
         });
         int64_t run = 0;
         for (int64_t q = 0; q < P; ++q) {
@@ -462,7 +462,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
             std::vector<int64_t> cur((size_t)P);
             for (int64_t j = a; j < b; ++j) {
                 for (int64_t q = 0; q < P; ++q) cur[(size_t)q] = pptr[(size_t)(q * (cols + 1) + j)];
-                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) order[(size_t)cur[(size_t)(row_of(p) / R)]++] = p;
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) order[(size_t)cur[(size_t)(row_of(p) % P)]++] = p;
             }
         });
     }
@@ -474,9 +474,8 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
         std::vector<int64_t> rc((size_t)rows, 0);
         for (int64_t p = 0; p < nnz; ++p) rc[(size_t)row_of(p)]++;
         for (int64_t q = 0; q < P; ++q) {
-            const int64_t r0 = q * R, r1 = std::min(rows, r0 + R);
-            std::vector<int32_t> rs((size_t)(r1 - r0));
-            std::iota(rs.begin(), rs.end(), (int32_t)r0);
+            std::vector<int32_t> rs;
+            for (int64_t r = q; r < rows; r += P) rs.push_back((int32_t)r);
             std::stable_sort(rs.begin(), rs.end(), [&](int32_t a, int32_t b) { return rc[(size_t)a] > rc[(size_t)b]; });
             std::vector<int64_t> load((size_t)NB, 0);
             for (int32_t r : rs) {
@@ -498,14 +497,32 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
     };
     std::vector<WgRange> wr;
     A.panels.clear();
+    // workgroups per panel in proportion to its nonzeros, largest remainders
+    // first, at least one per non-empty panel, no more than target in total
+    // when the panels allow it (one more would run as a second wave)
+    std::vector<int64_t> pnw((size_t)P, 0);
+    {
+        std::vector<std::pair<double, int64_t>> rem;
+        int64_t used = 0;
+        for (int64_t q = 0; q < P; ++q) {
+            const int64_t qn = pptr[(size_t)(q * (cols + 1) + cols)] - pptr[(size_t)(q * (cols + 1))];
+            if (qn == 0) continue;
+            const double share = (double)target * (double)qn / (double)std::max<int64_t>(nnz, 1);
+            pnw[(size_t)q] = std::max<int64_t>(1, (int64_t)share);
+            used += pnw[(size_t)q];
+            rem.push_back({share - (double)(int64_t)share, q});
+        }
+        std::stable_sort(rem.begin(), rem.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        for (size_t i = 0; i < rem.size() && used < target; ++i, ++used) pnw[(size_t)rem[i].second]++;
+    }
     for (int64_t q = 0; q < P; ++q) {
         const int64_t qa = pptr[(size_t)(q * (cols + 1))], qb = pptr[(size_t)(q * (cols + 1) + cols)];
         PanelDesc pd;
-        pd.row0 = (int32_t)(q * R);
-        pd.rows = (int32_t)std::min(R, rows - q * R);
+        pd.row0 = (int32_t)q;
+        pd.rows = (int32_t)((rows - q + P - 1) / P);
         pd.wg0 = (int32_t)wr.size();
         if (qb > qa) {
-            const int64_t nw = std::max<int64_t>(1, (int64_t)((double)target * (double)(qb - qa) / (double)nnz + 0.5));
+            const int64_t nw = pnw[(size_t)q];
             const int64_t *pq = pptr.data() + q * (cols + 1);
             int64_t j0 = 0;
             for (int64_t w = 0; w < nw; ++w) {
@@ -562,7 +579,7 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
                 const int32_t l = cb.count++;
                 const int32_t jj = l / 64, ln = l % 64;
                 cb.packed[((jj / 4) * 64 + ln) * 4 + jj % 4] =
-                    ((uint32_t)(r - (int64_t)g.panel * R) << 16) | (uint32_t)(j - cb.col_base);
+                    ((uint32_t)(r / P) << 16) | (uint32_t)(j - cb.col_base);
                 cb.val[((jj / GV) * 64 + ln) * GV + jj % GV] = val[sp];
             }
         }

@@ -39,8 +39,9 @@ struct ZonePlan {
 // Builds the zone plan; ptr has cols+1 entries.  Pure host code.
 void build_zone_plan(int64_t cols, const int64_t *ptr, int64_t chunk, ZonePlan &out);
 
-// Panel of the scatter product: internal rows [row0, row0+rows), workgroups
-// [wg0, wg0+nwg) hold its partial vectors.
+// Panel of the scatter product: the internal rows row0, row0 + P, row0 + 2P, ...
+// (rows of them; P panels, row0 = panel index), at panel-local rows 0, 1, 2, ...;
+// workgroups [wg0, wg0+nwg) hold its partial vectors.
 struct PanelDesc {
     int32_t row0, rows, wg0, nwg;
 };

@@ -523,7 +523,11 @@ __global__ void gather_vec(const int32_t *__restrict__ inv, int64_t len, const V
 }
 
 // ------------------------------------------------------------------------
-// Scatter product over one row panel.
+// Scatter product over one row panel.  Panel q holds the internal rows
+// r = q (mod P) for P panels, so every panel sees about the same share of each
+// column, and the workgroups of different panels that cover the same column
+// range gather the same x entries at about the same time (the second and
+// later reads hit in cache instead of HBM).
 // Storage: blocks of 64*MV_ITEMS nonzeros.  A block holds nonzeros of one
 // wave's rows, in column order, from one workgroup's column range.  Logical
 // nonzero j*64 + lane sits at word slot ((j/4)*64 + lane)*4 + j%4 and at value
@@ -632,22 +636,25 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
     for (int i = tid; i < panel_rows; i += BLOCK) out[i] = ypan[i];
 }
 
-// y[caller row] = sum over the panel's workgroups of their partials.  Eight
+// y[caller row] = sum over the panel's workgroups of their partials.  Internal
+// row r belongs to panel r mod npanels, at panel-local row r / npanels; threads
+// walk the panels one after another so each reads consecutive partials.  Eight
 // lanes share a row: lane t adds workgroups t, t+8, t+16, ... in ascending
 // order, then the eight sums are combined by a fixed butterfly, so the order
 // of every addition is fixed.
 template <typename VecT>
 __global__ void mv_reduce(const double *__restrict__ partial, int panel_rows, const PanelDesc *__restrict__ panels,
-                          int64_t rows, const int32_t *__restrict__ inv, VecT *__restrict__ y, int64_t ldy)
+                          int npanels, int64_t rows, const int32_t *__restrict__ inv, VecT *__restrict__ y, int64_t ldy)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t r = g >> 3;
+    const int64_t slot = g >> 3;              // panel * panel_rows + panel-local row
     const int t = (int)(g & 7);
-    const bool live = r < rows;
+    const int p = (int)(slot / panel_rows);
+    const int local = (int)(slot - (int64_t)p * panel_rows);
+    const int64_t r = (int64_t)local * npanels + p;
+    const bool live = p < npanels && r < rows;
     double s = 0.0;
     if (live) {
-        const int p = (int)(r / panel_rows);
-        const int local = (int)(r - (int64_t)p * panel_rows);
         const PanelDesc pd = panels[p];
         const double *src = partial + (int64_t)pd.wg0 * panel_rows + local;
         int w = t;
@@ -1228,8 +1235,8 @@ int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT 
         }
         {
             ProfScope ps(stream, "mv_reduce");
-            hipLaunchKernelGGL(mv_reduce<VecT>, dim3(blocks_for(A.rows * 8, 256)), dim3(256), 0, stream,
-                               A.scratch.partial, (int)A.panel_rows, A.d_panels, A.rows,
+            hipLaunchKernelGGL(mv_reduce<VecT>, dim3(blocks_for(A.n_panels * A.panel_rows * 8, 256)), dim3(256), 0, stream,
+                               A.scratch.partial, (int)A.panel_rows, A.d_panels, (int)A.n_panels, A.rows,
                                A.relabeled ? A.d_inv : nullptr, y + c, ldy);
             if ((e = (int)hipGetLastError())) return e;
         }
