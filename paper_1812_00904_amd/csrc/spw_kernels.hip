@@ -288,6 +288,100 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 //           CHUNK_DENSE       no empty column inside: segment q is column jlo+q
 constexpr int CHUNK_START_HEAD = 1, CHUNK_END_CONT = 2, CHUNK_DENSE = 4;
 
+// Joins the lanes' runs of one chunk and writes what they complete.  Lane
+// inputs: `run` is the sum of the lane's last run (segment k), `head_sum` the
+// sum of its first run (segment hk) when the lane holds a column start after
+// its first position (multi).  A segmented scan adds the runs of each segment
+// across lanes; the lane where a segment ends writes it (the chunk's first
+// segment to carry [2c] when it started in an earlier chunk, the last to
+// [2c+1] when it continues into the next, every other to u).
+template <typename VecT>
+__device__ __forceinline__ void vtm_chunk_tail(double run, int k, int hk, double head_sum, bool multi, bool active,
+                                               int4 ci, const int32_t *__restrict__ segcol, int64_t c, int lane,
+                                               VecT *__restrict__ u, int64_t ldu, double *__restrict__ carry, int kk,
+                                               int col)
+{
+    const int jlo = ci.x, seg0 = ci.y, last_seg = ci.z - 1, flags = ci.w;
+    const bool dense = (flags & CHUNK_DENSE) != 0;
+    auto column = [&](int q) -> int64_t { return dense ? (int64_t)jlo + q : (int64_t)segcol[seg0 + q]; };
+    const SegPair o = wave_seg_scan(SegPair{run, k});
+    const double prev_s = __shfl_up(o.s, 1, WAVE);
+    const int prev_k = __shfl_up(o.k, 1, WAVE);
+    const int next_hk = __shfl_down(hk, 1, WAVE);
+    if (active) {
+        auto emit = [&](int q, double value) {
+            const bool before = q == 0 && !(flags & CHUNK_START_HEAD);
+            const bool after = q == last_seg && (flags & CHUNK_END_CONT);
+            if (before) carry[(2 * c) * kk + col] = value;
+            else if (after) carry[(2 * c + 1) * kk + col] = value;
+            else u[column(q) * ldu] = (VecT)value;
+        };
+        if (multi) {
+            // the lane's first column ends inside it: add what earlier lanes hold
+            double tot = head_sum;
+            if (lane > 0 && prev_k == hk) tot = prev_s + head_sum;
+            emit(hk, tot);
+        }
+        if (lane == WAVE - 1 || next_hk != k) emit(k, o.s);
+    }
+}
+
+// Buffer stores of one value; an offset at or past the view's size writes
+// nothing (the hardware range check drops it), which predicates a store per
+// lane without changing the exec mask.
+typedef unsigned int spw_u32x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t BUF_DROP = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_view(void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_store(double x, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(spw_u32x2, x), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, 0);
+}
+
+// Reduces one full chunk (all 64*ITEMS positions are nonzeros) whose columns
+// have no empty column between them, so segment q is column jlo + q.  Same
+// additions in the same order as vtm_reduce_chunk, with the per-position
+// branches replaced by selects: a column wholly inside a lane is written by a
+// buffer store whose offset is out of range for every other position.  The
+// caller guarantees nseg * ldu * sizeof(VecT) < 2^31.
+template <int ITEMS, typename VecT>
+__device__ __forceinline__ void vtm_reduce_dense(const double *prod, uint32_t mask, int4 ci,
+                                                 const int32_t *__restrict__ segcol, int64_t c, int lane,
+                                                 VecT *__restrict__ u, int64_t ldu, double *__restrict__ carry,
+                                                 int kk, int col)
+{
+    const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
+    const int cnt = __popc(after_s);
+    const int incl = wave_prefix_sum(cnt);
+    const int k0 = incl - cnt + (lane > 0 ? (int)(mask & 1u) : 0);   // segment of the lane's first position
+    const uint32_t hb = mask & ((1u << ITEMS) - 1u) & ~1u;             // column starts after the first position
+    const __amdgpu_buffer_rsrc_t ub =
+        buf_view(u + (int64_t)ci.x * ldu, (uint32_t)((int64_t)ci.z * ldu * (int64_t)sizeof(VecT)));
+    const uint32_t step_bytes = (uint32_t)(ldu * (int64_t)sizeof(VecT));
+    double run = 0.0, head_sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (i > 0) {
+            const uint32_t below = hb & ((1u << i) - 1u);
+            const bool hd = (hb >> i) & 1u;
+            // the run ending at position i-1 is segment k0 + popc(below)
+            const uint32_t off = (uint32_t)(k0 + __popc(below)) * step_bytes;
+            buf_store((VecT)run, ub, (hd && below != 0u) ? off : BUF_DROP);
+            head_sum = (hd && below == 0u) ? run : head_sum;
+            run = hd ? 0.0 : run;
+        }
+        run += prod[i];
+    }
+    vtm_chunk_tail<VecT>(run, k0 + __popc(hb), k0, head_sum, hb != 0u, true, ci, segcol, c, lane, u, ldu, carry,
+                         kk, col);
+}
+
 // Reduces one chunk whose products are in `prod` (lane-owned positions
 // p0 .. p0+ITEMS-1).  `mask` bit i is set when position p0+i is the first
 // nonzero of its column, so column boundaries are register bit tests.  Runs
@@ -303,7 +397,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const double *prod, uint32_t ma
 {
     const int p0 = s + lane * ITEMS;
     const int my_n = max(0, min(ITEMS, e - p0));
-    const int jlo = ci.x, seg0 = ci.y, last_seg = ci.z - 1, flags = ci.w;
+    const int jlo = ci.x, seg0 = ci.y, flags = ci.w;
     const bool dense = (flags & CHUNK_DENSE) != 0;
     auto column = [&](int q) -> int64_t { return dense ? (int64_t)jlo + q : (int64_t)segcol[seg0 + q]; };
     // column starts after position s in this lane, and in all earlier lanes
@@ -338,26 +432,7 @@ __device__ __forceinline__ void vtm_reduce_chunk(const double *prod, uint32_t ma
         hk = -2 - lane;
     }
 
-    const SegPair o = wave_seg_scan(SegPair{run, k});
-    const double prev_s = __shfl_up(o.s, 1, WAVE);
-    const int prev_k = __shfl_up(o.k, 1, WAVE);
-    const int next_hk = __shfl_down(hk, 1, WAVE);
-    if (my_n > 0) {
-        auto emit = [&](int q, double value) {
-            const bool before = q == 0 && !(flags & CHUNK_START_HEAD);
-            const bool after = q == last_seg && (flags & CHUNK_END_CONT);
-            if (before) carry[(2 * c) * kk + col] = value;
-            else if (after) carry[(2 * c + 1) * kk + col] = value;
-            else u[column(q) * ldu] = (VecT)value;
-        };
-        if (multi) {
-            // the lane's first column ends inside it: add what earlier lanes hold
-            double tot = head_sum;
-            if (lane > 0 && prev_k == hk) tot = prev_s + head_sum;
-            emit(hk, tot);
-        }
-        if (lane == WAVE - 1 || next_hk != k) emit(k, o.s);
-    }
+    vtm_chunk_tail<VecT>(run, k, hk, head_sum, multi, my_n > 0, ci, segcol, c, lane, u, ldu, carry, kk, col);
 }
 
 // dst[i] = src(i) for i < n, by the BLOCK threads of a workgroup, with U loads
@@ -420,6 +495,8 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
         stage_rows<BLOCK, 16, VecT>(vh, vhot, [&](int i) { return v[i]; });
     }
     __syncthreads();
+    const __attribute__((address_space(3))) VecT *vh3 = (const __attribute__((address_space(3))) VecT *)vh;
+    const __attribute__((address_space(1))) VecT *vg1 = (const __attribute__((address_space(1))) VecT *)v;
 
     int64_t stride = (int64_t)gridDim.x * NW;
     int64_t c = (int64_t)blockIdx.x * NW + wave;
@@ -443,47 +520,63 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
         C.mask = heads[cc * WAVE + lane];
     };
     // Reduces chunk cc held in C (description ci), after issuing the loads of
-    // chunk cn into N (when cn < nchunks).
+    // chunk cn into N (when cn < cend).
     auto step = [&](Chunk &C, Chunk &N, int64_t cc, int4 ci, int64_t cn) {
         const int s = (int)(cc * WCH);
         const int e = (int)min((int64_t)s + WCH, nnz);
         for (int col = 0; col < k; ++col) {
             double prod[ITEMS];
+            // The LDS reads and the global reads are typed with their address
+            // spaces, so they stay ds_reads and global loads (a select between
+            // two generic pointers would become one flat load, which every
+            // later wait on either counter has to cover), and all LDS reads are
+            // issued before the first global read, so none waits for another.
+            VecT lv[ITEMS], gv[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) lv[i] = vh3[min(C.r.get(i), vhot - 1) * k + col];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                // the LDS read and the global read stay separate instructions (a
-                // selected pointer would become a flat load, which waits for
-                // every outstanding load)
                 const int ri = C.r.get(i);
-                const VecT lv = vh[min(ri, vhot - 1) * k + col];
-                VecT gv = 0;
-                if (ri >= vhot) gv = v[(int64_t)ri * ldv + col];
-                prod[i] = C.a.get(i) * (double)(ri < vhot ? lv : gv);
+                gv[i] = 0;
+                if (ri >= vhot) gv[i] = vg1[(int64_t)ri * ldv + col];
             }
             if (col == 0) {
-                // The gathers must land before the next chunk's loads are
-                // issued: the load counter is in order, so waiting for them
-                // later would also wait for the prefetch.
-                __builtin_amdgcn_s_waitcnt(0x0F70);      // vmcnt(0); lgkmcnt and expcnt left open
-                if (cn < cend) load_chunk(N, cn);
+                // The next chunk's loads go out after the gathers (the
+                // scheduling barriers keep that order): the load counter
+                // retires in order, so the wait for the gathers then leaves
+                // the prefetch in flight.  The loads are issued on every path
+                // (after the wave's last chunk they fetch the current one
+                // again, unused) so that the wait can count them.
+                __builtin_amdgcn_sched_barrier(0);
+                load_chunk(N, cn < cend ? cn : cc);
+                __builtin_amdgcn_sched_barrier(0);
             }
+            // a select of the two loaded values, not of two addresses: the
+            // gathers stay ahead of the prefetch
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                prod[i] = C.a.get(i) * (double)(C.r.get(i) < vhot ? lv[i] : gv[i]);
             VecT *uc = MULTI ? out.u[col] : out.u[0];
             const int64_t ldu = MULTI ? out.ld[col] : 1;
-            vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+            // full chunk, no empty column inside, output view within 2^31 bytes
+            if (e - s == WCH && (ci.w & CHUNK_DENSE) && ldu <= (int64_t)(1 << 28) / (WCH * (int64_t)sizeof(VecT)))
+                vtm_reduce_dense<ITEMS, VecT>(prod, C.mask, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+            else
+                vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
         }
     };
 
     // chunk sequence c, c + stride, ...; chunk descriptions are loaded one step ahead
+    auto ci_at = [&](int64_t cc) { return cc < cend ? cinfo[cc] : make_int4(0, 0, 0, 0); };
     int4 ci0 = cinfo[c];
     load_chunk(A, c);
     for (;;) {
         const int64_t c1 = c + stride;
-        int4 ci1 = make_int4(0, 0, 0, 0);
-        if (c1 < cend) ci1 = cinfo[c1];
+        const int4 ci1 = ci_at(c1);
         step(A, B, c, ci0, c1);
         if (c1 >= cend) break;
         const int64_t c2 = c1 + stride;
-        if (c2 < cend) ci0 = cinfo[c2];
+        ci0 = ci_at(c2);
         step(B, A, c1, ci1, c2);
         if (c2 >= cend) break;
         c = c2;
