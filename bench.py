@@ -20,7 +20,9 @@ error against binary64 products), multi-RHS blocks on the 5e7-nonzero
 batching matrix, and the CPU oracle timed on the host.
 
 `--pmc-summary DIR` turns rocprofv3 counter output (FETCH_SIZE / WRITE_SIZE
-runs of `--profile-run`) into the traffic summary under profiles/.
+runs of `--profile-run`) into the traffic summary under profiles/, and
+`--stats-summary DIR` a `rocprofv3 --kernel-trace --stats` run of the main
+benchmark into the kernel statistics summary there.
 """
 from __future__ import annotations
 
@@ -40,6 +42,9 @@ METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 l
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
+STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
+STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
+                 "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition")
 
 
 def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, si: int = 4, sp: int = 4) -> int:
@@ -144,10 +149,14 @@ def main():
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
     ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
                     help="FETCH_SIZE and WRITE_SIZE rocprofv3 output directories -> traffic summary")
+    ap.add_argument("--stats-summary", metavar="DIR",
+                    help="rocprofv3 --kernel-trace --stats output directory -> kernel statistics summary")
     args = ap.parse_args()
 
     if args.pmc_summary:
         return summarize_pmc(*args.pmc_summary)
+    if args.stats_summary:
+        return summarize_stats(args.stats_summary)
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the multi-GPU "
               "sharding is described in DESIGN.md but not built)" % args.gpus, file=sys.stderr)
@@ -693,6 +702,32 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
             out.append("%s_bytes_per_launch=%.0f" % (name, d["FETCH_SIZE"] + d["WRITE_SIZE"]))
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def summarize_stats(stats_dir: str):
+    """Fold the kernel_stats.csv of a `rocprofv3 --kernel-trace --stats` run of
+    the main benchmark (STATS_COMMAND) into the kernel statistics summary."""
+    files = glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_stats.csv under %s" % stats_dir)
+    rows = []
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                         float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda t: -t[5])
+    out = ["# rocprofv3 kernel statistics for one benchmark run on the wide CSC matrix m=50000 n=2e7",
+           "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs.",
+           "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND,
+           "kernel_source_sha256_16=%s" % kernel_hash(),
+           "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
+    for name, calls, avg, mn, mx, pct in rows:
+        short = name.replace("spw::(anonymous namespace)::", "").replace("void ", "")
+        short = short.split("(")[0][:56]
+        out.append("%-56s %5d %10.2f %10.2f %10.2f %7.2f%%" % (short, calls, avg, mn, mx, pct))
+    with open(STATS_FILE, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 
