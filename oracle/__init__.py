@@ -83,6 +83,8 @@ def _load():
     lib.orc_nzp_vtm.restype = ctypes.c_int
     lib.orc_colp_imbalance.argtypes = [_i64, _I64P, _i64]
     lib.orc_colp_imbalance.restype = ctypes.c_double
+    lib.orc_cgls.argtypes = [ctypes.c_int, _i64, _i64, _I64P, _I32P, _F64P, _F64P, _F64P, _i64, _F64P, _F64P]
+    lib.orc_cgls.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -260,3 +262,19 @@ def nzp_vtm(m, n, ptr, idx, val, off, v):
 
 def colp_imbalance(n, ptr, P) -> float:
     return _load().orc_colp_imbalance(n, np.ascontiguousarray(ptr, dtype=np.int64), P)
+
+
+def cgls(fmt, m, n, ptr, idx, val, b, x0, iters):
+    """CGLS on min ||b - A x||_2 from x0 (Section VI's first-order use of the
+    products; the variant is Hestenes-Stiefel / Bjorck, see oracle.c).  A is m x n,
+    fmt "csc" (wide) or "csr" (tall).  Returns (x, gamma, rho) with gamma[k] =
+    ||A^T r_k||^2 and rho[k] = ||r_k||^2 for k = 0 .. iters."""
+    lib = _load()
+    ptr, idx, val = _arrs(ptr, idx, val)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    gamma = np.empty(iters + 1, dtype=np.float64)
+    rho = np.empty(iters + 1, dtype=np.float64)
+    if lib.orc_cgls(1 if fmt == "csr" else 0, m, n, ptr, idx, val,
+                    np.ascontiguousarray(b, dtype=np.float64), x, iters, gamma, rho) != 0:
+        raise MemoryError("orc_cgls")
+    return x, gamma, rho

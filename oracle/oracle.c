@@ -32,6 +32,13 @@
  *   - orc_nzp_mv / orc_nzp_vtm: a serial simulation of the nonzero-partitioned
  *     algorithms of Section III (local products, then y = sum of y_(i)) and
  *     Section IV-A (local products, then zone sums over S_k).
+ *   - orc_cgls: a first-order solver that alternates the two products with
+ *     vector updates and inner products, as Section VI describes such methods.
+ *     The paper names conjugate gradients without fixing a variant; this is
+ *     conjugate gradients on the least-squares problem min ||b - A x||_2
+ *     (CGLS, Hestenes and Stiefel 1952, in the arrangement of Bjorck,
+ *     "Numerical Methods for Least Squares Problems", 1996, Section 7.4),
+ *     one A p and one A^T r per iteration, inner products summed in index order.
  *
  * Parity status: every function here is pinned by tests/test_oracle_pins.py
  * (dense brute force, exact integer arithmetic, closed forms, the worked
@@ -390,4 +397,57 @@ double orc_colp_imbalance(int64_t n, const int64_t *ptr, int64_t P)
         j0 = j1;
     }
     return (double)P * (double)(mx - mn) / (double)Z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CGLS (Section VI's first-order use of the two products).  A is m x n, wide  */
+/* CSC (csr = 0) or tall CSR (csr = 1).  x holds x_0 on entry and x_iters on  */
+/* exit.  hist_gamma[k] = ||A^T r_k||^2 and hist_rho[k] = ||r_k||^2 for        */
+/* k = 0 .. iters (either may be NULL).  An exact zero in a denominator (the  */
+/* iterate already solves the normal equations) makes that step size zero.    */
+/* Returns 0, or -1 when out of memory.                                       */
+/* ------------------------------------------------------------------------ */
+static double dot_seq(const double *a, const double *b, int64_t len)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < len; ++i) s = s + a[i] * b[i];
+    return s;
+}
+
+int orc_cgls(int csr, int64_t m, int64_t n, const int64_t *ptr, const int32_t *idx, const double *val,
+             const double *b, double *x, int64_t iters, double *hist_gamma, double *hist_rho)
+{
+    double *r = malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    double *q = malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    double *s = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    double *p = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (!r || !q || !s || !p) { free(r); free(q); free(s); free(p); return -1; }
+#define ORC_MV(in, out) (csr ? orc_mv_csr(m, n, ptr, idx, val, in, out, NULL) : orc_mv_csc(m, n, ptr, idx, val, in, out, NULL))
+#define ORC_VTM(in, out) (csr ? orc_vtm_csr(m, n, ptr, idx, val, in, out, NULL) : orc_vtm_csc(m, n, ptr, idx, val, in, out, NULL))
+    /* r_0 = b - A x_0,  s_0 = A^T r_0,  p_0 = s_0,  gamma_0 = ||s_0||^2 */
+    ORC_MV(x, q);
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - q[i];
+    ORC_VTM(r, s);
+    for (int64_t j = 0; j < n; ++j) p[j] = s[j];
+    double gamma = dot_seq(s, s, n);
+    if (hist_gamma) hist_gamma[0] = gamma;
+    if (hist_rho) hist_rho[0] = dot_seq(r, r, m);
+    for (int64_t k = 0; k < iters; ++k) {
+        ORC_MV(p, q);                                   /* q_k = A p_k */
+        const double delta = dot_seq(q, q, m);
+        const double alpha = (gamma > 0.0 && delta > 0.0) ? gamma / delta : 0.0;
+        for (int64_t j = 0; j < n; ++j) x[j] = x[j] + alpha * p[j];
+        for (int64_t i = 0; i < m; ++i) r[i] = r[i] - alpha * q[i];
+        ORC_VTM(r, s);                                  /* s_{k+1} = A^T r_{k+1} */
+        const double gamma_new = dot_seq(s, s, n);
+        const double beta = gamma > 0.0 ? gamma_new / gamma : 0.0;
+        for (int64_t j = 0; j < n; ++j) p[j] = s[j] + beta * p[j];
+        gamma = gamma_new;
+        if (hist_gamma) hist_gamma[k + 1] = gamma;
+        if (hist_rho) hist_rho[k + 1] = dot_seq(r, r, m);
+    }
+#undef ORC_MV
+#undef ORC_VTM
+    free(r); free(q); free(s); free(p);
+    return 0;
 }

@@ -35,6 +35,12 @@ MUTANTS = {
     "nzp_vtm_overwrites_zone": ("if (g > 0 && off[g] > ptr[j]) u[j] = u[j] + part;", "if (0) u[j] = u[j] + part;"),
     "nzp_mv_skips_first_group": ("for (int64_t r = 0; r < m; ++r) y[r] = y[r] + yi[r];",
                                  "for (int64_t r = 0; r < m; ++r) y[r] = g ? y[r] + yi[r] : y[r];"),
+    "cgls_residual_sign": ("r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
+    "cgls_steepest_descent": ("const double beta = gamma > 0.0 ? gamma_new / gamma : 0.0;",
+                              "const double beta = 0.0 * gamma_new;"),
+    "cgls_step_from_direction_norm": ("const double delta = dot_seq(q, q, m);",
+                                      "const double delta = dot_seq(p, p, n);"),
+    "cgls_iterate_moves_along_gradient": ("x[j] = x[j] + alpha * p[j];", "x[j] = x[j] + alpha * s[j];"),
 }
 
 

@@ -379,3 +379,70 @@ def test_colp_imbalance_closed_form():
     assert oracle.colp_imbalance(8, ptr, 1) == 0.0
     # eight single-column spans: max 5, min 1
     assert oracle.colp_imbalance(8, ptr, 8) == pytest.approx(8 * (5 - 1) / 21)
+
+
+# ---------------------------------------------------------------------------
+# CGLS (Section VI: first-order methods alternating the two products)
+# ---------------------------------------------------------------------------
+def _cgls_case(fmt, seed, m_w=12, n_w=40):
+    """A small random matrix in the requested layout with its dense copy: wide
+    CSC (m_w x n_w), or the same arrays read as tall CSR (n_w x m_w)."""
+    B = synth.random_csc(m_w, n_w, 3.0, seed)
+    D = synth.to_dense(B)
+    if fmt == "csr":
+        return B, D.T.copy(), n_w, m_w
+    return B, D, m_w, n_w
+
+
+@pytest.mark.parametrize("fmt", ["csc", "csr"])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_cgls_converges_to_min_norm_least_squares(fmt, seed):
+    # From x0 = 0, CGLS iterates stay in range(A^T) and converge to the
+    # minimum-norm least-squares solution, which numpy's SVD-based lstsq returns.
+    B, D, m, n = _cgls_case(fmt, seed)
+    rng = np.random.default_rng(seed)
+    b = rng.uniform(-1, 1, m)
+    x, gamma, rho = oracle.cgls(fmt, m, n, B.ptr, B.idx, B.val, b, np.zeros(n), 4 * min(m, n))
+    x_ref = np.linalg.lstsq(D, b, rcond=None)[0]
+    assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    assert gamma[-1] <= 1e-18 * gamma[0]
+
+
+@pytest.mark.parametrize("fmt", ["csc", "csr"])
+def test_cgls_residual_history_matches_direct_residual(fmt):
+    # rho_k is carried by recursion (r <- r - alpha q); it must equal ||b - A x||^2
+    # recomputed densely from the returned iterate, and ||r_k|| never grows.
+    B, D, m, n = _cgls_case(fmt, 5)
+    b = np.random.default_rng(5).uniform(-1, 1, m)
+    x0 = np.random.default_rng(6).uniform(-1, 1, n)
+    for iters in (0, 1, 3, 7):
+        x, gamma, rho = oracle.cgls(fmt, m, n, B.ptr, B.idx, B.val, b, x0, iters)
+        r = b - D @ x
+        assert abs(rho[-1] - r @ r) <= 1e-12 * (1.0 + r @ r)
+        g = D.T @ r
+        assert abs(gamma[-1] - g @ g) <= 1e-10 * (1.0 + g @ g)
+        assert np.all(np.diff(rho) <= 1e-14 * rho[0])
+    assert np.array_equal(oracle.cgls(fmt, m, n, B.ptr, B.idx, B.val, b, x0, 0)[0], x0)
+
+
+def test_cgls_finite_termination_two_singular_values():
+    # A = [diag(1, 1, 2, 2) | 0] has two distinct singular values: exact CG
+    # finishes in two steps, so x_2 is the minimum-norm solution up to rounding.
+    cols = [[1], [2], [3], [4], [], []]
+    ptr, idx = _csc_from_cols(cols, 4)
+    val = np.array([1.0, 1.0, 2.0, 2.0])
+    b = np.array([1.0, -2.0, 3.0, 0.5])
+    x, gamma, _ = oracle.cgls("csc", 4, 6, ptr, idx, val, b, np.zeros(6), 2)
+    assert np.allclose(x, [1.0, -2.0, 1.5, 0.25, 0.0, 0.0], rtol=0, atol=1e-15)
+    assert gamma[2] <= 1e-28
+    # one step is not enough: the first step is a steepest-descent step
+    x1, _, _ = oracle.cgls("csc", 4, 6, ptr, idx, val, b, np.zeros(6), 1)
+    s0 = np.array([1.0, -2.0, 6.0, 1.0, 0, 0])
+    Ds = np.array([1.0, -2.0, 12.0, 2.0])
+    assert np.allclose(x1, (s0 @ s0) / (Ds @ Ds) * s0, rtol=1e-15, atol=0)
+
+
+def test_cgls_zero_right_hand_side_stays_zero():
+    B, D, m, n = _cgls_case("csc", 3)
+    x, gamma, rho = oracle.cgls("csc", m, n, B.ptr, B.idx, B.val, np.zeros(m), np.zeros(n), 5)
+    assert not np.any(x) and not np.any(gamma) and not np.any(rho)
