@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the reduced-precision storage section")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-partition", action="store_true", help="skip the column-partitioning comparison")
+    ap.add_argument("--no-solver", action="store_true", help="skip the CGLS loop")
+    ap.add_argument("--solver-iters", type=int, default=20)
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.7",
                     help="comma-separated offered loads, as fractions of the plain path's capacity")
@@ -264,6 +266,9 @@ def main():
 
     if not args.no_precision:
         extra["precision"] = bench_precision(args, A, M, xd, vd)
+
+    if not args.no_solver:
+        extra["solver"] = bench_solver(args, A, M, vd, ms_per_step)
 
     if not args.no_batch:
         M.close()
@@ -390,6 +395,49 @@ def bench_precision(args, A, M, xd, vd):
         torch.cuda.empty_cache()
         res["rows"].append(row)
         print("[bench] precision %s" % row, file=sys.stderr, flush=True)
+    return res
+
+
+def bench_solver(args, A, M, bd, pair_ms):
+    """CGLS on the same matrix (spw_cgls, binary64): time per iteration from a
+    K-iteration and a 0-iteration call (the difference removes the start-up
+    product pair), against the plain product pair.  Byte model per iteration:
+    the two products plus the vector passes (||q||^2 and r -= alpha q on the
+    m-vectors: 32 m bytes; ||s||^2, then x += alpha p and p = s + beta p on the
+    n-vectors: 48 n bytes)."""
+    import numpy as np
+    import torch
+    K = max(args.solver_iters, 1)
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    M.cgls(bd, x, 2, hist=False)
+    torch.cuda.synchronize()
+
+    def timed(iters):
+        ts = []
+        for _ in range(3):
+            x.zero_()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            M.cgls(bd, x, iters, hist=False)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return sorted(ts)[1]
+
+    t0, tk = timed(0), timed(K)
+    it_ms = (tk - t0) / K
+    x.zero_()
+    gamma, rho = M.cgls(bd, x, K)
+    by = 2 * model_bytes(A.m, A.n, A.nnz) + 32 * A.m + 48 * A.n
+    res = {"workload": "CGLS, min ||b - A x||_2 on the same matrix, x0 = 0, binary64",
+           "iterations": K, "ms_per_iteration": round(it_ms, 4), "pair_ms": round(pair_ms, 4),
+           "vector_overhead_pct": round(100.0 * (it_ms - pair_ms) / pair_ms, 1),
+           "model_bytes_per_iteration": by, "GBps": round(by / (it_ms * 1e-3) / 1e9, 1),
+           "iterations_per_s": round(1e3 / it_ms, 1), "startup_ms": round(t0, 4),
+           "residual_reduction": float(np.sqrt(rho[-1] / rho[0])) if rho[0] > 0 else 0.0,
+           "normal_residual_reduction": float(np.sqrt(gamma[-1] / gamma[0])) if gamma[0] > 0 else 0.0}
+    del x
+    print("[bench] solver %s" % res, file=sys.stderr, flush=True)
     return res
 
 

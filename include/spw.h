@@ -182,6 +182,35 @@ spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, i
 spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv,
                          void *U, int64_t ldu, void *stream);
 
+/* ------------------------------------------------------------- a solver */
+
+/* Conjugate gradients on the least-squares problem min ||b - A x||_2 (CGLS):
+ * the first-order use of the two products that Section VI describes, where
+ * each iteration alternates one y := A p with one u^T := r^T A and a few
+ * vector updates and inner products.  The paper names conjugate gradients
+ * without fixing a variant; this is the Hestenes-Stiefel form as arranged by
+ * Bjorck (1996, Section 7.4): r_0 = b - A x_0, s_0 = p_0 = A^T r_0,
+ * gamma_0 = ||s_0||^2, then for k = 0 .. iters-1: q = A p_k,
+ * alpha = gamma_k / ||q||^2, x += alpha p_k, r -= alpha q, s = A^T r,
+ * gamma_{k+1} = ||s||^2, p_{k+1} = s + (gamma_{k+1} / gamma_k) p_k.  A step
+ * whose denominator is exactly zero (the iterate already solves the normal
+ * equations) has size zero.  Inner products are summed in a fixed order, so a
+ * call is bit-identical from run to run.
+ *   vdt   : SPW_F64 (SPW_ERR_UNSUPPORTED otherwise)
+ *   b     : device, m binary64 entries (not written)
+ *   x     : device, n binary64 entries: x_0 on entry, x_iters when the stream
+ *           reaches the end of the call's work
+ *   iters : >= 0
+ *   hist  : NULL, or host array of 2*(iters+1) doubles that receives
+ *           hist[k] = ||A^T r_k||^2 and hist[iters+1+k] = ||r_k||^2 for
+ *           k = 0 .. iters; the call then waits for the stream before returning.
+ *           Without hist the call only enqueues work on the stream.
+ * Workspace (2m + 2n doubles and the history) is kept with the matrix until
+ * spw_destroy and counted in device_bytes.  Calls on one matrix must not
+ * overlap (they share that workspace and the products' scratch). */
+spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist,
+                    void *stream);
+
 /* ----------------------------------------------------------------- serving */
 
 /* A server keeps many created matrices resident and serves product requests

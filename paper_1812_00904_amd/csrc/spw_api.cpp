@@ -672,6 +672,43 @@ spw_status grow_scratch(spw_matrix_s &A, int32_t k)
     return SPW_OK;
 }
 
+// The CGLS workspace: r, q (m), s, p (n), partial sums, scalars, and a history
+// of at least hist_len entries (a longer history replaces the old one once the
+// device is idle).
+spw_status grow_cgls(spw_matrix_s &A, int64_t hist_len)
+{
+    CglsScratch &W = A.cgls;
+    spw_status st;
+    if (!W.r) {
+        if ((st = dev_alloc(A, &W.r, std::max<int64_t>(A.m, 1), "CGLS r"))) return st;
+        if ((st = dev_alloc(A, &W.q, std::max<int64_t>(A.m, 1), "CGLS q"))) return st;
+        if ((st = dev_alloc(A, &W.s, std::max<int64_t>(A.n, 1), "CGLS s"))) return st;
+        if ((st = dev_alloc(A, &W.p, std::max<int64_t>(A.n, 1), "CGLS p"))) return st;
+        if ((st = dev_alloc(A, &W.partial, cgls_dot_parts(), "CGLS partial sums"))) return st;
+        if ((st = dev_alloc(A, &W.scal, 4, "CGLS scalars"))) return st;
+    }
+    if (W.hist_cap >= hist_len) return SPW_OK;
+    if (W.hist) {
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, "hipDeviceSynchronize failed while growing the CGLS history");
+        }
+        for (size_t i = 0; i < A.allocations.size(); ++i)
+            if (A.allocations[i].first == W.hist) {
+                A.device_bytes -= A.allocations[i].second;
+                A.allocations.erase(A.allocations.begin() + (long)i);
+                break;
+            }
+        (void)hipFree(W.hist);
+        W.hist = nullptr;
+        W.hist_cap = 0;
+    }
+    const int64_t cap = std::max<int64_t>(hist_len, 64);
+    if ((st = dev_alloc(A, &W.hist, cap, "CGLS history"))) return st;
+    W.hist_cap = cap;
+    return SPW_OK;
+}
+
 }  // namespace spw
 
 using namespace spw;
@@ -951,6 +988,60 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
                          void *stream)
 {
     return run_product(A, false, vdt, k, V, ldv, U, ldu, stream, "spw_vtm_batch");
+}
+
+spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist, void *stream)
+{
+    if (!A) return fail(SPW_ERR_INVALID_ARG, "spw_cgls: NULL matrix");
+    if (vdt != SPW_F64) return fail(SPW_ERR_UNSUPPORTED, "spw_cgls: binary64 vectors only");
+    if (iters < 0) return fail(SPW_ERR_INVALID_ARG, "spw_cgls: iters must be >= 0");
+    if ((A->m > 0 && !b) || (A->n > 0 && !x)) return fail(SPW_ERR_INVALID_ARG, "spw_cgls: NULL vector");
+    DeviceGuard dg(A->device);
+    if (dg.st) return dg.st;
+    spw_status st = grow_scratch(*A, 1);
+    if (st) return st;
+    const int64_t hl = 2 * ((int64_t)iters + 1);
+    if ((st = grow_cgls(*A, hl))) return st;
+    CglsScratch &W = A->cgls;
+    CglsWork w;
+    w.m = A->m;
+    w.n = A->n;
+    w.b = (const double *)b;
+    w.x = (double *)x;
+    w.r = W.r;
+    w.q = W.q;
+    w.s = W.s;
+    w.p = W.p;
+    w.partial = W.partial;
+    w.scal = W.scal;
+    w.hist_gamma = W.hist;
+    w.hist_rho = W.hist + iters + 1;
+    auto vec = [&](CglsVecOp op, int64_t k) -> spw_status {
+        const int e = launch_cgls_vec(op, w, k, stream);
+        if (e) return fail(SPW_ERR_DEVICE, std::string("spw_cgls: kernel launch failed: ") +
+                                               hipGetErrorString((hipError_t)e));
+        return SPW_OK;
+    };
+    // r_0 = b - A x_0, s_0 = A^T r_0, gamma_0 = ||s_0||^2, p_0 = s_0
+    if ((st = run_product(A, true, SPW_F64, 1, x, 1, w.q, 1, stream, "spw_cgls"))) return st;
+    if ((st = vec(CglsVecOp::R_INIT, 0))) return st;
+    if ((st = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return st;
+    if ((st = vec(CglsVecOp::GAMMA0, 0))) return st;
+    for (int64_t k = 1; k <= iters; ++k) {
+        if ((st = run_product(A, true, SPW_F64, 1, w.p, 1, w.q, 1, stream, "spw_cgls"))) return st;   // q = A p
+        if ((st = vec(CglsVecOp::ALPHA_R, k))) return st;
+        if ((st = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return st;  // s = A^T r
+        if ((st = vec(CglsVecOp::BETA_XP, k))) return st;
+    }
+    if (hist) {
+        if (hipMemcpyAsync(hist, W.hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
+                hipSuccess ||
+            hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, "spw_cgls: copying the history failed");
+        }
+    }
+    return SPW_OK;
 }
 
 spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, double *out)

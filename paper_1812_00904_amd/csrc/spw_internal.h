@@ -76,6 +76,16 @@ struct ColDot {
     bool built = false;
 };
 
+// Workspace of the CGLS loop (allocated on its first call, kept until destroy).
+struct CglsScratch {
+    double *r = nullptr, *q = nullptr;        // m entries each
+    double *s = nullptr, *p = nullptr;        // n entries each
+    double *partial = nullptr;                // partial sums of one inner product
+    double *scal = nullptr;                   // gamma, alpha, beta
+    double *hist = nullptr;                   // hist_cap entries: gamma history, then rho history
+    int64_t hist_cap = 0;
+};
+
 struct Scratch {
     double *partial = nullptr;    // mv_wgs * panel_rows  (binary64 partial sums of one column)
     double *carry = nullptr;      // 2 * max chunks * kcap
@@ -112,6 +122,7 @@ struct spw_matrix_s {
     int64_t mv_wgs = 0;
 
     spw::Scratch scratch;
+    spw::CglsScratch cgls;
     int64_t device_bytes = 0;
     std::vector<std::pair<void *, int64_t>> allocations;   // device buffers and their sizes
 };
@@ -156,6 +167,23 @@ int64_t vtm_workers(int device, int64_t nchunks);
 int64_t vtm_hot_rows_limit(spw_dtype vdt);
 int64_t vtm_slice_window();
 int device_cu_count(int device);
+
+// CGLS vector steps (spw_solve.hip).  x and p have n entries, b, r and q
+// have m; hist_gamma / hist_rho receive the inner products at index k.
+struct CglsWork {
+    int64_t m = 0, n = 0;
+    const double *b = nullptr;
+    double *x = nullptr, *r = nullptr, *q = nullptr, *s = nullptr, *p = nullptr;
+    double *partial = nullptr, *scal = nullptr, *hist_gamma = nullptr, *hist_rho = nullptr;
+};
+enum class CglsVecOp : int {
+    R_INIT,    // r = b - q (q = A x_0); rho_k = ||r||^2
+    GAMMA0,    // gamma_0 = ||s||^2 (s = A^T r_0); p = s
+    ALPHA_R,   // alpha = gamma / ||q||^2 (q = A p); r = r - alpha q; rho_k = ||r||^2
+    BETA_XP    // gamma_k = ||s||^2 (s = A^T r); beta = gamma_k / gamma_{k-1}; x = x + alpha p; p = s + beta p
+};
+int launch_cgls_vec(CglsVecOp op, const CglsWork &w, int64_t k, void *stream);
+int64_t cgls_dot_parts();
 
 // Profiling hooks (spw_profile.cpp).
 bool profile_on();

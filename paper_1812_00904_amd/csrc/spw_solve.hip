@@ -1,0 +1,185 @@
+// Vector kernels of the CGLS loop (conjugate gradients on min ||b - A x||_2),
+// the first-order use of the two products that the paper's closing section
+// describes: each iteration is one A p, one A^T r, and a few passes of vector
+// updates and inner products, which this file fuses.
+//
+// Every inner product is formed in a fixed order, so a solve is bit-identical
+// from run to run: DOT_PARTS workgroups each sum a fixed contiguous range
+// (thread t adds elements t, t + BLOCK, ... of the range in order, then a
+// fixed butterfly inside each wave and the waves in ascending order), and one
+// workgroup adds the DOT_PARTS partial sums the same way.  The step sizes stay
+// on the device: the scalar kernel that finishes an inner product also forms
+// alpha or beta, so the loop never waits for the host.
+//
+// Scalars slot layout (binary64): [0] gamma = ||A^T r||^2 of the current
+// iterate, [1] alpha, [2] beta.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "spw_internal.h"
+
+namespace spw {
+namespace {
+
+constexpr int SV_BLOCK = 256;
+constexpr int SV_WAVE = 64;
+constexpr int DOT_PARTS = 1024;          // partial sums per inner product (one per workgroup)
+constexpr int S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2;
+
+// Sum of one value per thread over a workgroup of SV_BLOCK threads, in a fixed
+// order: butterfly inside each wave, then the waves in ascending order.  The
+// result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    for (int off = SV_WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, SV_WAVE);
+    const int wave = threadIdx.x / SV_WAVE, lane = threadIdx.x % SV_WAVE;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < SV_BLOCK / SV_WAVE; ++w) s += lds[w];
+    return s;
+}
+
+// Range of workgroup g out of DOT_PARTS over len elements.
+__device__ __forceinline__ void part_range(int64_t len, int64_t &a, int64_t &e)
+{
+    a = len * (int64_t)blockIdx.x / DOT_PARTS;
+    e = len * ((int64_t)blockIdx.x + 1) / DOT_PARTS;
+}
+
+// partial[g] = sum over workgroup g's range of a_i * a_i.
+__global__ __launch_bounds__(SV_BLOCK) void sq_part(const double *__restrict__ a, int64_t len,
+                                                    double *__restrict__ partial)
+{
+    __shared__ double lds[SV_BLOCK / SV_WAVE];
+    int64_t s, e;
+    part_range(len, s, e);
+    double acc = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += SV_BLOCK) acc += a[i] * a[i];
+    const double t = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// INIT: r = b - q.  UPDATE: r = r - alpha q.  Either way partial[g] = sum of
+// r_i * r_i of the new r over workgroup g's range.
+template <bool INIT>
+__global__ __launch_bounds__(SV_BLOCK) void r_step(double *__restrict__ r, const double *__restrict__ b,
+                                                   const double *__restrict__ q, int64_t len,
+                                                   const double *__restrict__ scal, double *__restrict__ partial)
+{
+    __shared__ double lds[SV_BLOCK / SV_WAVE];
+    const double alpha = INIT ? 0.0 : scal[S_ALPHA];
+    int64_t s, e;
+    part_range(len, s, e);
+    double acc = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += SV_BLOCK) {
+        const double ri = INIT ? b[i] - q[i] : r[i] - alpha * q[i];
+        r[i] = ri;
+        acc += ri * ri;
+    }
+    const double t = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// What the scalar kernel does with the finished inner product.
+enum ScalarOp : int {
+    OP_GAMMA0 = 0,   // gamma = sum, hist_gamma[k] = sum
+    OP_ALPHA = 1,    // delta = sum, alpha = gamma / delta (0 when either is 0)
+    OP_GAMMA = 2,    // gamma_new = sum, beta = gamma_new / gamma (0 when gamma is 0), gamma = gamma_new
+    OP_RHO = 3       // hist_rho[k] = sum
+};
+
+// One workgroup: adds the DOT_PARTS partial sums in a fixed order and applies op.
+__global__ __launch_bounds__(SV_BLOCK) void scalar_step(const double *__restrict__ partial, int op,
+                                                        double *__restrict__ scal, double *__restrict__ hist_gamma,
+                                                        double *__restrict__ hist_rho, int64_t k)
+{
+    __shared__ double lds[SV_BLOCK / SV_WAVE];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < DOT_PARTS; i += SV_BLOCK) acc += partial[i];
+    const double sum = block_sum(acc, lds);
+    if (threadIdx.x != 0) return;
+    if (op == OP_GAMMA0) {
+        scal[S_GAMMA] = sum;
+        hist_gamma[k] = sum;
+    } else if (op == OP_ALPHA) {
+        const double gamma = scal[S_GAMMA];
+        scal[S_ALPHA] = (gamma > 0.0 && sum > 0.0) ? gamma / sum : 0.0;
+    } else if (op == OP_GAMMA) {
+        const double gamma = scal[S_GAMMA];
+        scal[S_BETA] = gamma > 0.0 ? sum / gamma : 0.0;
+        scal[S_GAMMA] = sum;
+        hist_gamma[k] = sum;
+    } else {
+        hist_rho[k] = sum;
+    }
+}
+
+// x = x + alpha p, then p = s + beta p (with the p the x update used): one
+// pass over the three long vectors.
+__global__ __launch_bounds__(SV_BLOCK) void xp_step(double *__restrict__ x, double *__restrict__ p,
+                                                    const double *__restrict__ s, int64_t len,
+                                                    const double *__restrict__ scal)
+{
+    const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
+    const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
+    for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) {
+        const double pi = p[i];
+        x[i] = x[i] + alpha * pi;
+        p[i] = s[i] + beta * pi;
+    }
+}
+
+__global__ __launch_bounds__(SV_BLOCK) void copy_vec(const double *__restrict__ a, double *__restrict__ b,
+                                                     int64_t len)
+{
+    const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
+    for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) b[i] = a[i];
+}
+
+unsigned stream_grid(int64_t len)
+{
+    const int64_t g = (len + SV_BLOCK - 1) / SV_BLOCK;
+    return (unsigned)(g < 1 ? 1 : (g > 16384 ? 16384 : g));
+}
+
+}  // namespace
+
+int64_t cgls_dot_parts() { return DOT_PARTS; }
+
+int launch_cgls_vec(CglsVecOp op, const CglsWork &w, int64_t k, void *stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    switch (op) {
+    case CglsVecOp::R_INIT:   // r = b - q, rho_k
+        hipLaunchKernelGGL(r_step<true>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO, w.scal, w.hist_gamma,
+                           w.hist_rho, k);
+        break;
+    case CglsVecOp::GAMMA0:   // gamma_0 = ||s||^2, p = s
+        hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA0, w.scal, w.hist_gamma,
+                           w.hist_rho, k);
+        hipLaunchKernelGGL(copy_vec, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.s, w.p, w.n);
+        break;
+    case CglsVecOp::ALPHA_R:  // alpha = gamma / ||q||^2, r = r - alpha q, rho_k
+        hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.q, w.m, w.partial);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_ALPHA, w.scal, w.hist_gamma,
+                           w.hist_rho, k);
+        hipLaunchKernelGGL(r_step<false>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO, w.scal, w.hist_gamma,
+                           w.hist_rho, k);
+        break;
+    case CglsVecOp::BETA_XP:  // gamma_k = ||s||^2, beta, x += alpha p, p = s + beta p
+        hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA, w.scal, w.hist_gamma,
+                           w.hist_rho, k);
+        hipLaunchKernelGGL(xp_step, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
+        break;
+    }
+    return (int)hipGetLastError();
+}
+
+}  // namespace spw

@@ -96,6 +96,7 @@ SIGNATURES = {
     "spw_mv_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_vtm_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_round_values": (ctypes.c_int, [ctypes.c_int, _I64, _VP, _VP]),
+    "spw_cgls": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, ctypes.c_int32, _VP, _VP]),
     "spw_serve_opts_default": (ctypes.c_int, [ctypes.POINTER(ServeOpts)]),
     "spw_serve_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServeOpts)]),
     "spw_serve_register": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(_I32)]),
@@ -213,6 +214,22 @@ def spw_vtm_batch(h: int, V: torch.Tensor, U: torch.Tensor, stream=None):
                                 _stream_ptr(stream)))
 
 
+def spw_cgls(h: int, b: torch.Tensor, x: torch.Tensor, iters: int, hist: bool = True, stream=None):
+    """CGLS on min ||b - A x||_2 in place on x (float64 device tensors).  With
+    hist, returns (gamma, rho): ||A^T r_k||^2 and ||r_k||^2 for k = 0 .. iters."""
+    _dev(b, "b"), _dev(x, "x")
+    if b.dtype != torch.float64 or x.dtype != torch.float64:
+        raise ValueError("spw_cgls takes float64 vectors")
+    if not (b.is_contiguous() and x.is_contiguous()):
+        raise ValueError("spw_cgls takes contiguous vectors")
+    out = np.empty(2 * (iters + 1), dtype=np.float64) if hist else None
+    _check(load().spw_cgls(h, SPW_F64, b.data_ptr(), x.data_ptr(), int(iters),
+                           out.ctypes.data if hist else None, _stream_ptr(stream)))
+    if not hist:
+        return None
+    return out[:iters + 1].copy(), out[iters + 1:].copy()
+
+
 def spw_round_values(storage: int, val) -> np.ndarray:
     """Host-only: the values spw_create stores for `storage`, promoted to float64."""
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -290,6 +307,10 @@ class SpwMatrix:
             U = torch.empty((self.n, V.shape[1]), dtype=V.dtype, device=V.device)
         spw_vtm_batch(self.handle, V, U, stream)
         return U
+
+    def cgls(self, b: torch.Tensor, x: torch.Tensor, iters: int, hist: bool = True, stream=None):
+        """CGLS iterations on min ||b - A x||_2, in place on x; see spw_cgls."""
+        return spw_cgls(self.handle, b, x, iters, hist, stream)
 
     def close(self):
         if self.handle:
