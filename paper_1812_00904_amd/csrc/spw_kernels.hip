@@ -276,7 +276,7 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 // Each wave handles the chunks c, c + stride, ...; the values, indices and
 // column-start window of the next chunk, and the column range of the one
 // after, are loaded while the current chunk is reduced.
-// Dynamic LDS: vhot doubles, then SLICE_W column starts per wave.  Columns
+// Dynamic LDS: each wave's segment stage, then the vhot hot rows.  Columns
 // without nonzeros are written by zero_cols, not here.
 // ------------------------------------------------------------------------
 // Per-chunk description used by the column dots (built on the host):
@@ -344,14 +344,81 @@ __device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, uin
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, 0);
 }
 
+// Segments of one chunk a wave stages in LDS before writing them out; chunks
+// with more segments take the general path.
+constexpr int STAGE_CAP = 256;
+constexpr int STAGE_STRIDE = STAGE_CAP + 64;     // plus one spare slot per lane
+
 // Reduces one full chunk (all 64*ITEMS positions are nonzeros) whose columns
-// have no empty column between them, so segment q is column jlo + q.  Same
+// have no empty column between them, so segment q is column jlo + q, with at
+// most STAGE_CAP segments.  Same additions in the same order as
+// vtm_reduce_chunk, with the per-position branches replaced by selects.  Every
+// segment's sum goes to this wave's LDS stage at its segment index (writes
+// that carry nothing go to the lane's spare slot), then the wave copies the
+// chunk's segments out: a contiguous run of columns in one or two coalesced
+// buffer stores, and the two chunk-cut segments to their carry slots.  LDS
+// instructions of one wave execute in order, so the copy sees every write.
+// The caller guarantees nseg * ldu * sizeof(VecT) < 2^31.
+template <int ITEMS, typename VecT>
+__device__ __forceinline__ void vtm_reduce_dense(const double *prod, uint32_t mask, int4 ci, int64_t c, int lane,
+                                                 VecT *__restrict__ u, int64_t ldu, double *__restrict__ carry,
+                                                 int kk, int col, __attribute__((address_space(3))) double *stage)
+{
+    const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
+    const int cnt = __popc(after_s);
+    const int incl = wave_prefix_sum(cnt);
+    const int k0 = incl - cnt + (lane > 0 ? (int)(mask & 1u) : 0);   // segment of the lane's first position
+    const uint32_t hb = mask & ((1u << ITEMS) - 1u) & ~1u;             // column starts after the first position
+    const int spare = STAGE_CAP + lane;
+    double run = 0.0, head_sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (i > 0) {
+            const uint32_t below = hb & ((1u << i) - 1u);
+            const bool hd = (hb >> i) & 1u;
+            // the run ending at position i-1 is segment k0 + popc(below)
+            stage[(hd && below != 0u) ? k0 + __popc(below) : spare] = run;
+            head_sum = (hd && below == 0u) ? run : head_sum;
+            run = hd ? 0.0 : run;
+        }
+        run += prod[i];
+    }
+    // join the lanes' first and last runs (segmented scan, as in vtm_chunk_tail)
+    const int k = k0 + __popc(hb);
+    const SegPair o = wave_seg_scan(SegPair{run, k});
+    const double prev_s = __shfl_up(o.s, 1, WAVE);
+    const int prev_k = __shfl_up(o.k, 1, WAVE);
+    const int next_hk = __shfl_down(k0, 1, WAVE);
+    const double tot = (lane > 0 && prev_k == k0) ? prev_s + head_sum : head_sum;
+    stage[hb != 0u ? k0 : spare] = tot;
+    stage[(lane == WAVE - 1 || next_hk != k) ? k : spare] = o.s;
+    // copy out: segment t is column jlo + t, except a first segment that began
+    // in an earlier chunk and a last one that continues into the next
+    const int nseg = ci.z, flags = ci.w;
+    const bool first_carry = !(flags & CHUNK_START_HEAD), last_carry = (flags & CHUNK_END_CONT) != 0;
+    const __amdgpu_buffer_rsrc_t ub =
+        buf_view(u + (int64_t)ci.x * ldu, (uint32_t)((int64_t)nseg * ldu * (int64_t)sizeof(VecT)));
+    const uint32_t step_bytes = (uint32_t)(ldu * (int64_t)sizeof(VecT));
+    for (int t = lane; t < nseg; t += WAVE) {
+        const double val = stage[t];
+        const bool to_carry = (t == 0 && first_carry) || (t == nseg - 1 && last_carry);
+        buf_store((VecT)val, ub, to_carry ? BUF_DROP : (uint32_t)t * step_bytes);
+    }
+    if (lane == 0) {
+        if (first_carry) carry[(2 * c) * kk + col] = stage[0];
+        if (last_carry) carry[(2 * c + 1) * kk + col] = stage[nseg - 1];
+    }
+}
+
+// As vtm_reduce_dense, without the LDS stage (binary32 outputs, whose LDS is
+// worth more as hot rows of v): the same additions in the same order, with a
+// column wholly inside a lane written by a buffer store of its own.  Same
 // additions in the same order as vtm_reduce_chunk, with the per-position
 // branches replaced by selects: a column wholly inside a lane is written by a
 // buffer store whose offset is out of range for every other position.  The
 // caller guarantees nseg * ldu * sizeof(VecT) < 2^31.
 template <int ITEMS, typename VecT>
-__device__ __forceinline__ void vtm_reduce_dense(const double *prod, uint32_t mask, int4 ci,
+__device__ __forceinline__ void vtm_reduce_dense_direct(const double *prod, uint32_t mask, int4 ci,
                                                  const int32_t *__restrict__ segcol, int64_t c, int lane,
                                                  VecT *__restrict__ u, int64_t ldu, double *__restrict__ carry,
                                                  int kk, int col)
@@ -482,8 +549,13 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
     constexpr int NW = BLOCK / WAVE;
     constexpr int WCH = WAVE * ITEMS;
     extern __shared__ double lds[];
-    VecT *vh = reinterpret_cast<VecT *>(lds);
+    // LDS: each wave's segment stage (STAGE_STRIDE doubles; binary64 vectors
+    // only), then the hot rows of v
+    constexpr int STAGED = sizeof(VecT) == 8 ? STAGE_STRIDE : 0;
+    VecT *vh = reinterpret_cast<VecT *>(lds + NW * STAGED);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    __attribute__((address_space(3))) double *stage =
+        (__attribute__((address_space(3))) double *)(lds + wave * STAGED);
     const int lane = threadIdx.x & (WAVE - 1);
 
     if (MULTI) {
@@ -558,11 +630,21 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
                 prod[i] = C.a.get(i) * (double)(C.r.get(i) < vhot ? lv[i] : gv[i]);
             VecT *uc = MULTI ? out.u[col] : out.u[0];
             const int64_t ldu = MULTI ? out.ld[col] : 1;
-            // full chunk, no empty column inside, output view within 2^31 bytes
-            if (e - s == WCH && (ci.w & CHUNK_DENSE) && ldu <= (int64_t)(1 << 28) / (WCH * (int64_t)sizeof(VecT)))
-                vtm_reduce_dense<ITEMS, VecT>(prod, C.mask, ci, segcol, cc, lane, uc, ldu, carry, k, col);
-            else
-                vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+            // full chunk, no empty column inside, segments fit the stage, output
+            // view within 2^31 bytes
+            const bool dense_full = e - s == WCH && (ci.w & CHUNK_DENSE) &&
+                                    ldu <= (int64_t)(1 << 28) / (WCH * (int64_t)sizeof(VecT));
+            if constexpr (sizeof(VecT) == 8) {
+                if (dense_full && ci.z <= STAGE_CAP)
+                    vtm_reduce_dense<ITEMS, VecT>(prod, C.mask, ci, cc, lane, uc, ldu, carry, k, col, stage);
+                else
+                    vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+            } else {
+                if (dense_full)
+                    vtm_reduce_dense_direct<ITEMS, VecT>(prod, C.mask, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+                else
+                    vtm_reduce_chunk<ITEMS, VecT>(prod, C.mask, s, e, ci, segcol, cc, lane, uc, ldu, carry, k, col);
+            }
         }
     };
 
@@ -1191,15 +1273,25 @@ int with_types(spw_dtype storage, spw_dtype vdt, Fn &&fn)
     return (int)hipErrorNotSupported;
 }
 
-int64_t hot_rows_limit(size_t vec_bytes) { return (LDS_BYTES / VTM_WG_PER_CU - 256) / (int64_t)vec_bytes; }
+// LDS of one column-dot workgroup outside the hot rows: the waves' segment
+// stages, for binary64 vectors.
+int64_t vtm_stage_bytes(size_t elem_bytes)
+{
+    return elem_bytes == 8 ? (int64_t)(VTM_BLOCK / WAVE) * STAGE_STRIDE * (int64_t)sizeof(double) : 0;
+}
+// Hot rows of v that fit beside the stages, for k columns of elem_bytes each.
+int64_t hot_rows_limit(size_t elem_bytes, int64_t k)
+{
+    return (LDS_BYTES / VTM_WG_PER_CU - 256 - vtm_stage_bytes(elem_bytes)) / ((int64_t)elem_bytes * k);
+}
 
 template <typename IdxT, typename ValT, typename VecT, bool MULTI>
 int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
 {
     const ColDot &C = A.cd;
     if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
-    const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT) * (size_t)k));
-    const size_t lds = std::max<size_t>((size_t)vhot * k * sizeof(VecT), 16);
+    const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT), k));
+    const size_t lds = (size_t)vtm_stage_bytes(sizeof(VecT)) + (size_t)vhot * k * sizeof(VecT);
     const int cus = device_cu_count(A.device);
     const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
@@ -1355,7 +1447,7 @@ int64_t vtm_workers(int device, int64_t nchunks)
     return wgs * nw;
 }
 int64_t vtm_slice_window() { return VTM_SLICE_W; }
-int64_t vtm_hot_rows_limit(spw_dtype vdt) { return hot_rows_limit(vdt == SPW_F64 ? 8 : 4); }
+int64_t vtm_hot_rows_limit(spw_dtype vdt) { return hot_rows_limit(vdt == SPW_F64 ? 8 : 4, 1); }
 
 int device_cu_count(int device)
 {
