@@ -1232,6 +1232,7 @@ __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k
 #define SPW_MV_BLOCK 256
 #endif
 constexpr int VTM_BLOCK = SPW_VTM_BLOCK;
+constexpr int VTM_BLOCK_F32 = 1024;                // single-vector column dots, 4-byte values and vectors or less
 constexpr int VTM_WG_PER_CU = SPW_VTM_WG_PER_CU;   // resident workgroups per CU (they share the LDS)
 constexpr int VTM_ITEMS = 16;
 constexpr int VTM_SLICE_W = 256;
@@ -1293,17 +1294,32 @@ int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<
     const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT), k));
     const size_t lds = (size_t)vtm_stage_bytes(sizeof(VecT)) + (size_t)vhot * k * sizeof(VecT);
     const int cus = device_cu_count(A.device);
-    const int64_t wgs_needed = (C.zp.n_chunks + VTM_BLOCK / WAVE - 1) / (VTM_BLOCK / WAVE);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
-    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
-    (void)attr;
     // column partitioning: one wave per worker of the plan (single-vector calls)
     const int32_t *wch = (!MULTI && C.d_wchunks) ? C.d_wchunks : nullptr;
-    const unsigned g = wch ? (unsigned)(C.n_workers / (VTM_BLOCK / WAVE)) : grid;
-    hipLaunchKernelGGL((vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>), dim3(g), dim3(VTM_BLOCK), lds,
-                       stream, (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,
-                       C.d_segcol, C.nnz, C.zp.n_chunks, wch, vin, k, vhot, out, A.scratch.carry);
-    return (int)hipGetLastError();
+    auto run = [&](auto kernel, int block) -> int {
+        const int nw = block / WAVE;
+        const int64_t wgs_needed = (C.zp.n_chunks + nw - 1) / nw;
+        const unsigned grid =
+            wch ? (unsigned)(C.n_workers / nw)
+                : (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, (const IdxT *)C.d_idx, (const ValT *)C.d_val,
+                           C.d_heads, (const int4 *)C.d_cinfo, C.d_segcol, C.nnz, C.zp.n_chunks, wch, vin, k, vhot,
+                           out, A.scratch.carry);
+        return (int)hipGetLastError();
+    };
+    if constexpr (!MULTI && sizeof(VecT) == 4 && sizeof(ValT) <= 4) {
+        // binary32 or bfloat16 values with binary32 vectors, one column: few
+        // enough registers for 16 waves per workgroup, which hide more latency
+        // (the plan's worker table of a column partition assumes VTM_BLOCK)
+        if (!wch) {
+            static const bool attr_w = allow_full_lds(vtm_wave<VTM_BLOCK_F32, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
+            (void)attr_w;
+            return run(vtm_wave<VTM_BLOCK_F32, VTM_ITEMS, IdxT, ValT, VecT, MULTI>, VTM_BLOCK_F32);
+        }
+    }
+    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
+    (void)attr;
+    return run(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>, VTM_BLOCK);
 }
 
 template <typename ValT, typename VecT>
