@@ -44,7 +44,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
-                 "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition")
+                 "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver")
 
 
 def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, si: int = 4, sp: int = 4) -> int:

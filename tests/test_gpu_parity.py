@@ -122,6 +122,25 @@ def test_structures(spw, fmt, case):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("case", ["256_aligned", "257_aligned", "257_cut", "1024_singletons"])
+def test_chunk_segment_counts(spw, fmt, case):
+    # Full chunks of 1,024 positions with no empty column inside take the
+    # staged reduction when they hold at most 256 column segments and the
+    # general one otherwise; cover both sides of that limit, with chunk
+    # boundaries on and off column starts.
+    if case == "256_aligned":
+        L = np.full(256 * 20, 4)                                   # 256 segments per chunk
+    elif case == "257_aligned":
+        L = np.tile(np.r_[3, np.full(255, 4), 1], 20)              # 257 segments per chunk
+    elif case == "257_cut":
+        L = np.r_[2, np.full(256 * 20, 4), 3]                      # every chunk cuts two columns
+    else:
+        L = np.ones(1024 * 20 + 17, dtype=np.int64)                # 1,024 segments, ragged tail
+    A = synth.from_lengths(3000, L, 21, row_alpha=0.8, values="lognormal")
+    parity(spw, A, fmt, seed=4, reps=2, name=case)
+
+
+@pytest.mark.parametrize("fmt", FMTS)
 def test_integer_data_bit_exact(spw, fmt):
     A = synth.random_csc(500, 30000, 6.0, 9, values="int", empty_frac=0.2)
     A = synth.from_lengths(500, np.r_[np.diff(A.ptr), [500] * 4], 9, values="int")
