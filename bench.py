@@ -503,6 +503,11 @@ def bench_partition(args):
     the batching matrix in generated order, the same with columns in
     descending length (the worst case for column partitioning), and a
     2,000 x 100,000 matrix with uniform column lengths (the best case).
+    Then the same comparison on a stand-in for the paper's document-term data
+    set (19,996 x 1,355,191, 9,097,916 nonzeros, its published heavy-column
+    statistics), ingested from coordinate triples as the paper's driver reads
+    it, in random column order and in descending column length (the order of
+    the paper's first experiment).
     Reports median kernel times of single-vector products and the column
     partition's imbalance Delta = P (max - min) / nnz over its P workers."""
     import numpy as np
@@ -514,6 +519,9 @@ def bench_partition(args):
             ("batching matrix, columns by descending length", synth.sort_columns_by_length(base)),
             ("uniform lengths 2000 x 100000", synth.uniform_lengths(2000, max(int(100000 * args.scale), 1), 0.274,
                                                                     100, 100, synth.SEED_BASE + 5))]
+    news = synth.news20_shaped(scale=min(args.scale, 1.0))
+    mats += [("document-term stand-in 19996 x 1355191, random column order", news),
+             ("document-term stand-in, columns by descending length", synth.sort_columns_by_length(news))]
     reps = max(args.steps // 2, 10)
     out = []
     for name, A in mats:
@@ -522,8 +530,17 @@ def bench_partition(args):
         y = torch.empty(A.m, dtype=torch.float64, device="cuda")
         u = torch.empty(A.n, dtype=torch.float64, device="cuda")
         row = {"matrix": name, "m": A.m, "n": A.n, "nnz": A.nnz}
+        coo = name.startswith("document-term")
+        if coo:
+            rows_t = A.idx.astype(np.int32)
+            cols_t = np.repeat(np.arange(A.n, dtype=np.int32), np.diff(A.ptr))
         for label, opts in (("nonzero", {}), ("column", {"partition": SPW_PART_COLUMN})):
-            M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, transpose=0, **opts)
+            t_create = time.perf_counter()
+            if coo:
+                M = SpwMatrix.from_coo(SPW_CSC, A.m, A.n, rows_t, cols_t, A.val, transpose=0, **opts)
+            else:
+                M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, transpose=0, **opts)
+            t_create = time.perf_counter() - t_create
             info = M.info()
             mv50, _ = _time_each(lambda: M.mv(x, y), reps)
             vt50, _ = _time_each(lambda: M.vtm(v, u), reps)
@@ -532,7 +549,9 @@ def bench_partition(args):
                           "worker_max_nnz": info["worker_max_nnz"], "worker_min_nnz": info["worker_min_nnz"],
                           "imbalance_pct": round(100.0 * P * (info["worker_max_nnz"] - info["worker_min_nnz"])
                                                  / max(A.nnz, 1), 2),
-                          "zones": info["n_zones"]}
+                          "zones": info["n_zones"], "pair_GBps": round(2 * model_bytes(A.m, A.n, A.nnz) /
+                                                                      ((mv50 + vt50) * 1e-3) / 1e9, 1),
+                          "create_s": round(t_create, 2), "created_from": "triples" if coo else "CSC"}
             M.close()
         row["vtm_column_over_nonzero"] = round(row["column"]["vtm_ms"] / row["nonzero"]["vtm_ms"], 2)
         row["mv_column_over_nonzero"] = round(row["column"]["mv_ms"] / row["nonzero"]["mv_ms"], 2)

@@ -152,6 +152,20 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
                       const int64_t *ptr, const int32_t *idx, const double *val,
                       const spw_create_opts *opts);
 
+/* Create a matrix from coordinate triples, the input form of the paper's
+ * nonzero-partitioned driver (Section V: a stream of (row, column, value)
+ * triples in column-major order).  Any order is accepted: the triples are
+ * sorted on the host into the compressed arrays of fmt (SPW_CSC: by column,
+ * then row; SPW_CSR: by row, then column), which then go through spw_create
+ * with opts.
+ *   rows, cols : nnz int32 entries each, 0 <= rows[p] < m, 0 <= cols[p] < n
+ *   val        : nnz binary64 entries
+ * Errors: as spw_create, plus SPW_ERR_BAD_MATRIX for an index out of range or
+ * a (row, column) pair given twice (duplicates are not summed). */
+spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz,
+                          const int32_t *rows, const int32_t *cols, const double *val,
+                          const spw_create_opts *opts);
+
 /* Release the matrix and its device memory (waits for the device first).  NULL is a no-op. */
 spw_status spw_destroy(spw_matrix A);
 

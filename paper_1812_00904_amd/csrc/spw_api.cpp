@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -880,6 +881,63 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     cleanup.armed = false;
     *out = A.release();
     return SPW_OK;
+}
+
+spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int32_t *rows,
+                          const int32_t *cols, const double *val, const spw_create_opts *opts)
+{
+    if (!out) return fail(SPW_ERR_INVALID_ARG, "spw_create_coo: NULL out");
+    *out = nullptr;
+    if (fmt != SPW_CSC && fmt != SPW_CSR) return fail(SPW_ERR_INVALID_ARG, "spw_create_coo: bad format");
+    if (m < 0 || n < 0 || nnz < 0) return fail(SPW_ERR_INVALID_ARG, "spw_create_coo: negative size");
+    if (nnz > 0 && (!rows || !cols || !val)) return fail(SPW_ERR_INVALID_ARG, "spw_create_coo: NULL triples");
+    if (nnz >= ((int64_t)1 << 31)) return fail(SPW_ERR_UNSUPPORTED, "spw_create_coo: nnz must be < 2^31");
+    // compressed dimension (outer) and the one stored per entry (inner)
+    const bool csc = fmt == SPW_CSC;
+    const int32_t *outer = csc ? cols : rows, *inner = csc ? rows : cols;
+    const int64_t n_outer = csc ? n : m, n_inner = csc ? m : n;
+    for (int64_t p = 0; p < nnz; ++p)
+        if (rows[p] < 0 || rows[p] >= m || cols[p] < 0 || cols[p] >= n)
+            return fail(SPW_ERR_BAD_MATRIX, "spw_create_coo: triple " + std::to_string(p) + " (" +
+                                                std::to_string(rows[p]) + ", " + std::to_string(cols[p]) +
+                                                ") lies outside the " + std::to_string(m) + " x " +
+                                                std::to_string(n) + " matrix");
+    (void)n_inner;
+    // counting sort by the outer index (stable), then each outer line by inner index
+    std::vector<int64_t> ptr((size_t)n_outer + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) ptr[(size_t)outer[p] + 1]++;
+    for (int64_t j = 0; j < n_outer; ++j) ptr[(size_t)j + 1] += ptr[(size_t)j];
+    std::vector<int64_t> order((size_t)nnz);
+    {
+        std::vector<int64_t> cur(ptr.begin(), ptr.end() - 1);
+        for (int64_t p = 0; p < nnz; ++p) order[(size_t)cur[(size_t)outer[p]]++] = p;
+    }
+    std::vector<int32_t> idx((size_t)nnz);
+    std::vector<double> v((size_t)nnz);
+    std::atomic<int64_t> dup{-1};
+    parallel_for(n_outer, [&](int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j) {
+            int64_t *o0 = order.data() + ptr[(size_t)j], *o1 = order.data() + ptr[(size_t)j + 1];
+            std::sort(o0, o1, [&](int64_t x, int64_t y) { return inner[x] < inner[y] || (inner[x] == inner[y] && x < y); });
+            for (int64_t *q = o0; q < o1; ++q) {
+                const int64_t pos = q - order.data();
+                idx[(size_t)pos] = inner[*q];
+                v[(size_t)pos] = val[*q];
+                if (q > o0 && inner[*q] == inner[*(q - 1)]) {
+                    int64_t none = -1;
+                    dup.compare_exchange_strong(none, *q);
+                }
+            }
+        }
+    });
+    if (dup.load() >= 0) {
+        const int64_t p = dup.load();
+        return fail(SPW_ERR_BAD_MATRIX, "spw_create_coo: (" + std::to_string(rows[p]) + ", " +
+                                            std::to_string(cols[p]) + ") is given more than once");
+    }
+    order.clear();
+    order.shrink_to_fit();
+    return spw_create(out, fmt, m, n, nnz, ptr.data(), idx.data(), v.data(), opts);
 }
 
 spw_status spw_destroy(spw_matrix A)

@@ -89,6 +89,8 @@ SIGNATURES = {
     "spw_create_opts_default": (ctypes.c_int, [ctypes.POINTER(CreateOpts)]),
     "spw_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
                                   ctypes.POINTER(CreateOpts)]),
+    "spw_create_coo": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, _I64, _I64, _I64, _VP, _VP, _VP,
+                                      ctypes.POINTER(CreateOpts)]),
     "spw_destroy": (ctypes.c_int, [_VP]),
     "spw_info": (ctypes.c_int, [_VP, ctypes.POINTER(MatrixInfo)]),
     "spw_mv": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, _VP]),
@@ -163,6 +165,19 @@ def spw_create(fmt: int, m: int, n: int, ptr, idx, val, opts: CreateOpts | None 
     h = _VP()
     _check(load().spw_create(ctypes.byref(h), fmt, m, n, nnz, ptr.ctypes.data, idx.ctypes.data,
                              val.ctypes.data, ctypes.byref(opts) if opts is not None else None))
+    return h.value
+
+
+def spw_create_coo(fmt: int, m: int, n: int, rows, cols, val, opts: CreateOpts | None = None) -> int:
+    """Create a matrix from coordinate triples (numpy, any order); returns the handle."""
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    if not (rows.size == cols.size == val.size):
+        raise ValueError("rows, cols and val must have the same length")
+    h = _VP()
+    _check(load().spw_create_coo(ctypes.byref(h), fmt, m, n, int(val.size), rows.ctypes.data, cols.ctypes.data,
+                                 val.ctypes.data, ctypes.byref(opts) if opts is not None else None))
     return h.value
 
 
@@ -280,6 +295,15 @@ class SpwMatrix:
         self.fmt, self.m, self.n = fmt, m, n
         self.handle = None
         self.handle = spw_create(fmt, m, n, ptr, idx, val, create_opts(**opts) if opts else None)
+
+    @classmethod
+    def from_coo(cls, fmt: int, m: int, n: int, rows, cols, val, **opts) -> "SpwMatrix":
+        """A matrix from (row, column, value) triples in any order; see spw_create_coo."""
+        self = cls.__new__(cls)
+        self.fmt, self.m, self.n = fmt, m, n
+        self.handle = None
+        self.handle = spw_create_coo(fmt, m, n, rows, cols, val, create_opts(**opts) if opts else None)
+        return self
 
     def info(self) -> dict:
         return spw_info(self.handle)

@@ -279,3 +279,54 @@ def uniform_lengths(m: int, n: int, rho: float, iota_minus: int, iota_plus: int,
     hi = min(int(np.ceil(rho * m)) + iota_plus, m)
     lengths = rng.integers(lo, hi + 1, n).astype(np.int64)
     return from_lengths(m, lengths, seed)
+
+
+# --------------------------------------------------------------------------
+# A stand-in for the paper's document-term matrix (its Section VI data set,
+# which is not available here): the published shape and column statistics,
+# the rest chosen.
+# --------------------------------------------------------------------------
+NEWS20_M, NEWS20_N, NEWS20_NNZ = 19996, 1355191, 9097916
+
+
+def news20_shaped(seed: int | None = None, scale: float = 1.0) -> Sparse:
+    """m = 19,996 documents, n = 1,355,191 terms, exactly 9,097,916 nonzeros;
+    25 columns hold at least 9,998 nonzeros, the 10 densest 18,531 down to
+    11,872 (geometric steps), the next 15 from 11,700 down to 9,998; every other
+    column has a length drawn from a Zipf law on {1, ..., 9,997} whose exponent
+    is fitted to the remaining nonzeros (term document-frequencies are heavy
+    tailed), then a few lengths move by one to hit the total exactly.  Columns
+    are in random order, rows follow Zipf(0.5) weights over permuted documents
+    (document lengths differ), values are lognormal (tf-idf weights are
+    positive).  `scale` < 1 shrinks n and nnz together (tests only)."""
+    seed = SEED_BASE + 20 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11])))
+    m = NEWS20_M
+    n = max(int(round(NEWS20_N * scale)), 30)
+    total = max(int(round(NEWS20_NNZ * scale)), n + 400000)
+    heavy = np.r_[np.round(np.geomspace(18531, 11872, 10)), np.round(np.linspace(11700, 9998, 15))].astype(np.int64)
+    rest_n, rest_nnz = n - heavy.size, total - int(heavy.sum())
+    kmax = 9997
+    ks = np.arange(1, kmax + 1, dtype=np.float64)
+
+    def mean_for(a):
+        w = ks ** -a
+        return float((ks * w).sum() / w.sum())
+
+    lo, hi = 1.01, 4.0            # mean_for decreases in a
+    target = rest_nnz / rest_n
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if mean_for(mid) > target else (lo, mid)
+    w = ks ** -(0.5 * (lo + hi))
+    lengths = rng.choice(kmax, size=rest_n, p=w / w.sum()).astype(np.int64) + 1
+    diff = rest_nnz - int(lengths.sum())
+    while diff != 0:
+        step = 1 if diff > 0 else -1
+        ok = np.nonzero((lengths < kmax) if step > 0 else (lengths > 1))[0]
+        pick = rng.choice(ok, size=min(abs(diff), ok.size), replace=False)
+        lengths[pick] += step
+        diff -= step * pick.size
+    lengths = np.r_[heavy, lengths]
+    lengths = lengths[rng.permutation(n)]
+    return from_lengths(m, lengths, seed, row_alpha=0.5, values="lognormal")

@@ -198,3 +198,40 @@ def test_create_rejects_value_overflow_before_device_use(spw):
     assert "position 1" in msg
     _expect(spw, "SPW_ERR_INVALID_ARG", spw.spw_create, spw.SPW_CSC, 2, 2, ptr, idx, val,
             spw.create_opts(value_storage=5))
+
+
+def test_create_coo_rejects_bad_triples_before_device_use(spw):
+    rows = np.array([0, 1, 1], dtype=np.int32)
+    cols = np.array([1, 0, 2], dtype=np.int32)
+    val = np.ones(3)
+    # a column index outside the matrix, named by its triple
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create_coo, spw.SPW_CSC, 2, 2, rows, cols, val)
+    assert "triple 2" in msg
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create_coo, spw.SPW_CSR, 1, 3, rows, cols, val)
+    # a (row, column) pair given twice, in either layout
+    dup_r = np.array([1, 0, 1], dtype=np.int32)
+    dup_c = np.array([2, 1, 2], dtype=np.int32)
+    for fmt in (spw.SPW_CSC, spw.SPW_CSR):
+        msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create_coo, fmt, 2, 3, dup_r, dup_c, val)
+        assert "(1, 2)" in msg
+    _expect(spw, "SPW_ERR_INVALID_ARG", spw.spw_create_coo, 7, 2, 3, rows, cols, val)
+    lib = spw.load()
+    h = ctypes.c_void_p()
+    assert lib.spw_create_coo(ctypes.byref(h), 0, 2, 3, 3, None, None, None, None) == 1   # NULL triples
+    assert lib.spw_create_coo(None, 0, 2, 3, 0, None, None, None, None) == 1               # NULL out
+
+
+def test_news20_shaped_statistics():
+    # the published shape of the paper's data set (Section VI): 19,996 x
+    # 1,355,191, 9,097,916 nonzeros, 25 columns with at least 9,998 nonzeros,
+    # the 10 densest between 11,872 and 18,531
+    A = synth.news20_shaped()
+    assert (A.m, A.n, A.nnz) == (19996, 1355191, 9097916)
+    L = np.diff(A.ptr)
+    top = np.sort(L)[::-1]
+    assert int((L >= 9998).sum()) == 25
+    assert top[0] == 18531 and top[9] == 11872 and top[10] < 11872
+    assert 6.5 < L.mean() < 7.0
+    assert np.all(np.diff(A.idx[A.ptr[0]:A.ptr[1]]) > 0)
+    B = synth.news20_shaped()
+    assert np.array_equal(A.ptr, B.ptr) and np.array_equal(A.idx, B.idx) and np.array_equal(A.val, B.val)

@@ -1,0 +1,112 @@
+"""Coordinate-triple ingest (spw_create_coo) and the document-term stand-in.
+
+A matrix created from its (row, column, value) triples in any order must hold
+exactly the arrays spw_create gets from the compressed form, so every product
+is bit-identical to the compressed create; both are checked against the oracle
+at the usual bar (per component |gpu - oracle| <= 1e-13 * sum|a||x|).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-13
+
+
+@pytest.fixture(scope="module")
+def spw():
+    from paper_1812_00904_amd import spw as mod
+    mod.load()
+    assert torch.cuda.is_available()
+    return mod
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def triples(A):
+    """(rows, cols) of the CSC arrays of A, in storage order."""
+    cols = np.repeat(np.arange(A.n, dtype=np.int32), np.diff(A.ptr))
+    return A.idx.astype(np.int32), cols
+
+
+def products(M, m, n, x, v):
+    y = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    u = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    M.mv(dev(x), y)
+    M.vtm(dev(v), u)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), u.cpu().numpy()
+
+
+def check(got, ref, d, what):
+    assert not np.isnan(got).any(), what
+    bad = np.abs(got - ref) > TOL64 * d
+    assert not bad.any(), "%s: %d components off" % (what, int(bad.sum()))
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_coo_matches_compressed_create_bit_for_bit(spw, fmt):
+    A = synth.random_csc(700, 30000, 6.0, 31, row_alpha=0.8, values="lognormal", empty_frac=0.1)
+    r, c = triples(A)
+    perm = np.random.default_rng(1).permutation(A.nnz)
+    if fmt == 0:      # wide CSC, m x n
+        m, n = A.m, A.n
+        Mc = spw.SpwMatrix(spw.SPW_CSC, m, n, A.ptr, A.idx, A.val)
+        Mo = spw.SpwMatrix.from_coo(spw.SPW_CSC, m, n, r[perm], c[perm], A.val[perm])
+    else:             # the same arrays read as tall CSR (n x m): triple (row j, column i)
+        m, n = A.n, A.m
+        Mc = spw.SpwMatrix(spw.SPW_CSR, m, n, A.ptr, A.idx, A.val)
+        Mo = spw.SpwMatrix.from_coo(spw.SPW_CSR, m, n, c[perm], r[perm], A.val[perm])
+    x, v = synth.vector(n, 2, 1), synth.vector(m, 2, 2)
+    yc, uc = products(Mc, m, n, x, v)
+    yo, uo = products(Mo, m, n, x, v)
+    assert np.array_equal(yc, yo) and np.array_equal(uc, uo)
+    assert Mc.info()["n_zones"] == Mo.info()["n_zones"]
+    if fmt == 0:
+        y, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x, with_d=True)
+        u, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v, with_d=True)
+    else:
+        y, dy = oracle.mv_csr(m, n, A.ptr, A.idx, A.val, x, with_d=True)
+        u, du = oracle.vtm_csr(m, n, A.ptr, A.idx, A.val, v, with_d=True)
+    check(yo, y, dy, "coo mv")
+    check(uo, u, du, "coo vtm")
+    Mc.close()
+    Mo.close()
+
+
+def test_coo_empty_and_duplicates(spw):
+    M = spw.SpwMatrix.from_coo(spw.SPW_CSC, 5, 7, np.zeros(0), np.zeros(0), np.zeros(0))
+    y, u = products(M, 5, 7, np.ones(7), np.ones(5))
+    assert not y.any() and not u.any()
+    M.close()
+    with pytest.raises(spw.SpwError):
+        spw.SpwMatrix.from_coo(spw.SPW_CSC, 5, 7, [1, 1], [2, 2], [1.0, 2.0])
+
+
+@pytest.mark.parametrize("order", ["random", "descending"])
+@pytest.mark.parametrize("partition", ["nonzero", "column"])
+def test_news20_shaped_parity(spw, order, partition):
+    A = synth.news20_shaped()
+    if order == "descending":
+        A = synth.sort_columns_by_length(A)
+    opts = {} if partition == "nonzero" else {"partition": spw.SPW_PART_COLUMN}
+    r, c = triples(A)
+    M = spw.SpwMatrix.from_coo(spw.SPW_CSC, A.m, A.n, r, c, A.val, transpose=0, **opts)
+    x, v = synth.vector(A.n, 3, 1), synth.vector(A.m, 3, 2)
+    yg, ug = products(M, A.m, A.n, x, v)
+    info = M.info()
+    M.close()
+    y, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x, with_d=True)
+    u, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v, with_d=True)
+    check(yg, y, dy, "news20 mv")
+    check(ug, u, du, "news20 vtm")
+    if partition == "column":
+        P = info["workers"]
+        delta = P * (info["worker_max_nnz"] - info["worker_min_nnz"]) / A.nnz
+        assert delta == pytest.approx(oracle.colp_imbalance(A.n, A.ptr, P), rel=1e-12, abs=1e-15)
