@@ -673,6 +673,31 @@ spw_status grow_scratch(spw_matrix_s &A, int32_t k)
     return SPW_OK;
 }
 
+spw_status grow_partial_cols(spw_matrix_s &A, int32_t cols)
+{
+    if (A.scratch.pcols >= cols || A.mv_wgs == 0) return SPW_OK;
+    if (A.scratch.partial_cols) {
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, "hipDeviceSynchronize failed while growing scratch");
+        }
+        for (size_t i = 0; i < A.allocations.size(); ++i)
+            if (A.allocations[i].first == A.scratch.partial_cols) {
+                A.device_bytes -= A.allocations[i].second;
+                A.allocations.erase(A.allocations.begin() + (long)i);
+                break;
+            }
+        (void)hipFree(A.scratch.partial_cols);
+        A.scratch.partial_cols = nullptr;
+        A.scratch.pcols = 0;
+    }
+    spw_status st;
+    if ((st = dev_alloc(A, &A.scratch.partial_cols, (int64_t)cols * A.mv_wgs * A.panel_rows, "multi-column partial sums")))
+        return st;
+    A.scratch.pcols = cols;
+    return SPW_OK;
+}
+
 // The CGLS workspace: r, q (m), s, p (n), partial sums, scalars, and a history
 // of at least hist_len entries (a longer history replaces the old one once the
 // device is idle).
@@ -1003,8 +1028,9 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     if (k == 1 && ldi == 1 && ldo == 1) {
         e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
     } else if (scatter && (k <= 8 || !A->cdt.built)) {
-        // few right-hand sides (or no transpose kept): one scatter pass per
-        // column, which reads A k times but gathers x once per nonzero
+        // few right-hand sides (or no transpose kept): scatter launches of up
+        // to 8 columns whose workgroups read A together
+        if ((st = grow_partial_cols(*A, std::min<int32_t>(k, 8)))) return st;
         e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
     } else if (scatter) {
         // k right-hand sides in one pass: column dots over the kept transpose

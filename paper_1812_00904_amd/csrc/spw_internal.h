@@ -88,6 +88,8 @@ struct CglsScratch {
 
 struct Scratch {
     double *partial = nullptr;    // mv_wgs * panel_rows  (binary64 partial sums of one column)
+    double *partial_cols = nullptr;   // pcols * mv_wgs * panel_rows (multi-column scatter launches)
+    int32_t pcols = 0;
     double *carry = nullptr;      // 2 * max chunks * kcap
     double *vperm = nullptr;      // rows * kcap elements of 8 bytes (renumbered input of the column dots)
     int32_t kcap = 0;
@@ -196,5 +198,7 @@ void set_error(const std::string &msg);
 // Makes the handle's scratch hold k-wide carries and renumbered inputs (and
 // the one-column partial sums); growing waits for the device (spw_api.cpp).
 spw_status grow_scratch(spw_matrix_s &A, int32_t k);
+// Partial sums for scatter launches of up to cols columns (spw_api.cpp).
+spw_status grow_partial_cols(spw_matrix_s &A, int32_t cols);
 
 }  // namespace spw

@@ -70,18 +70,28 @@ __device__ __forceinline__ double val_at(const double *v, int64_t s) { return v[
 __device__ __forceinline__ double val_at(const float *v, int64_t s) { return (double)v[s]; }
 __device__ __forceinline__ double val_at(const Bf16 *v, int64_t s) { return bf16_bits_to_f64(v[s].bits); }
 
+// A load of streamed matrix data: non-temporal (NT, the default: read once,
+// so it should not push reused vectors out of the caches) or ordinary (data
+// that other workgroups read again soon).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // N stored values of one lane from an interleaved run: 16-byte group g of
 // lane l sits at byte (g*64 + l)*16.  get() promotes exactly to binary64; all
 // accumulation is binary64.
 template <typename ValT, int N> struct ValRaw;
 template <int N> struct ValRaw<double, N> {
     double a[N];
+    template <bool NT = true>
     __device__ __forceinline__ void load(const double *base, int lane)
     {
 #pragma unroll
         for (int g = 0; g < N / 2; ++g) {
-            const f64x2_t w =
-                __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(base + (int64_t)(g * 64 + lane) * 2));
+            const f64x2_t w = ld_stream<NT>(reinterpret_cast<const f64x2_t *>(base + (int64_t)(g * 64 + lane) * 2));
             a[2 * g] = w.x;
             a[2 * g + 1] = w.y;
         }
@@ -90,12 +100,12 @@ template <int N> struct ValRaw<double, N> {
 };
 template <int N> struct ValRaw<float, N> {
     float a[N];
+    template <bool NT = true>
     __device__ __forceinline__ void load(const float *base, int lane)
     {
 #pragma unroll
         for (int g = 0; g < N / 4; ++g) {
-            const f32x4_t w =
-                __builtin_nontemporal_load(reinterpret_cast<const f32x4_t *>(base + (int64_t)(g * 64 + lane) * 4));
+            const f32x4_t w = ld_stream<NT>(reinterpret_cast<const f32x4_t *>(base + (int64_t)(g * 64 + lane) * 4));
             a[4 * g] = w.x;
             a[4 * g + 1] = w.y;
             a[4 * g + 2] = w.z;
@@ -106,13 +116,13 @@ template <int N> struct ValRaw<float, N> {
 };
 template <int N> struct ValRaw<Bf16, N> {
     uint32_t w[N / 2];
+    template <bool NT = true>
     __device__ __forceinline__ void load(const Bf16 *base, int lane)
     {
         const uint16_t *b = reinterpret_cast<const uint16_t *>(base);
 #pragma unroll
         for (int g = 0; g < N / 8; ++g) {
-            const u32x4_t q =
-                __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(b + (int64_t)(g * 64 + lane) * 8));
+            const u32x4_t q = ld_stream<NT>(reinterpret_cast<const u32x4_t *>(b + (int64_t)(g * 64 + lane) * 8));
             w[4 * g] = q.x;
             w[4 * g + 1] = q.y;
             w[4 * g + 2] = q.z;
@@ -727,7 +737,7 @@ template <typename ValT> struct MvBlk {
     int2 bd;
 };
 
-template <typename ValT>
+template <bool NT, typename ValT>
 __device__ __forceinline__ void mv_load(MvBlk<ValT> &B, const uint32_t *__restrict__ packed,
                                         const ValT *__restrict__ val, const int2 *__restrict__ blocks, int b, int lane)
 {
@@ -735,29 +745,30 @@ __device__ __forceinline__ void mv_load(MvBlk<ValT> &B, const uint32_t *__restri
     const int64_t base = (int64_t)b * MV_BLK;
 #pragma unroll
     for (int g = 0; g < MV_ITEMS / 4; ++g) {
-        const u32x4_t q =
-            __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(packed + base + (int64_t)(g * 64 + lane) * 4));
+        const u32x4_t q = ld_stream<NT>(reinterpret_cast<const u32x4_t *>(packed + base + (int64_t)(g * 64 + lane) * 4));
         B.w[4 * g] = q.x;
         B.w[4 * g + 1] = q.y;
         B.w[4 * g + 2] = q.z;
         B.w[4 * g + 3] = q.w;
     }
-    B.a.load(val + base, lane);
+    B.a.template load<NT>(val + base, lane);
 }
 
-template <int BLOCK, typename ValT, typename VecT>
-__global__ __launch_bounds__(BLOCK) void mv_bucket(
-    const uint32_t *__restrict__ packed, const ValT *__restrict__ val, const int2 *__restrict__ blocks,
-    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, double *__restrict__ partial,
-    int panel_rows)
+// One workgroup range of the scatter product into the LDS panel ypan, written
+// to out (panel_rows doubles).  Ends with a workgroup barrier, so the panel
+// can be reused at once.
+template <int BLOCK, typename ValT, typename VecT, bool NT>
+__device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, const ValT *__restrict__ val,
+                                         const int2 *__restrict__ blocks, const int32_t *__restrict__ wg_blk,
+                                         int range, const VecT *__restrict__ x, int64_t ldx,
+                                         double *__restrict__ out, int panel_rows, double *ypan)
 {
     constexpr int NW = BLOCK / WAVE;
-    extern __shared__ double ypan[];
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
     for (int i = tid; i < panel_rows; i += BLOCK) ypan[i] = 0.0;
     __syncthreads();
 
-    const int32_t *wb = wg_blk + (int64_t)blockIdx.x * (NW + 1);
+    const int32_t *wb = wg_blk + (int64_t)range * (NW + 1);
     const int b0 = wb[wave], b1 = wb[wave + 1];
     // Two block buffers used alternately (no register copies, so no wait for
     // data still in flight): while block b is added, the x entries of block
@@ -783,9 +794,9 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
             if (j * WAVE < lim) __hip_atomic_fetch_add(&ypan[row[j]], p[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     if (b0 < b1) {
-        mv_load(B0, packed, val, blocks, b0, lane);
+        mv_load<NT>(B0, packed, val, blocks, b0, lane);
         gather(B0, x0);
-        if (b0 + 1 < b1) mv_load(B1, packed, val, blocks, b0 + 1, lane);
+        if (b0 + 1 < b1) mv_load<NT>(B1, packed, val, blocks, b0 + 1, lane);
     }
     for (int b = b0; b < b1; b += 2) {
         double p[MV_ITEMS];
@@ -794,7 +805,7 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
         int cnt = B0.bd.y;
         if (b + 1 < b1) {
             gather(B1, x1);
-            if (b + 2 < b1) mv_load(B0, packed, val, blocks, b + 2, lane);
+            if (b + 2 < b1) mv_load<NT>(B0, packed, val, blocks, b + 2, lane);
         }
         commit(cnt, p, row);
         if (b + 1 >= b1) break;
@@ -802,13 +813,48 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
         cnt = B1.bd.y;
         if (b + 2 < b1) {
             gather(B0, x0);
-            if (b + 3 < b1) mv_load(B1, packed, val, blocks, b + 3, lane);
+            if (b + 3 < b1) mv_load<NT>(B1, packed, val, blocks, b + 3, lane);
         }
         commit(cnt, p, row);
     }
     __syncthreads();
-    double *out = partial + (int64_t)blockIdx.x * panel_rows;
     for (int i = tid; i < panel_rows; i += BLOCK) out[i] = ypan[i];
+    __syncthreads();
+}
+
+template <int BLOCK, typename ValT, typename VecT>
+__global__ __launch_bounds__(BLOCK) void mv_bucket(
+    const uint32_t *__restrict__ packed, const ValT *__restrict__ val, const int2 *__restrict__ blocks,
+    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, double *__restrict__ partial,
+    int panel_rows)
+{
+    extern __shared__ double ypan[];
+    mv_range<BLOCK, ValT, VecT, true>(packed, val, blocks, wg_blk, blockIdx.x, x, ldx,
+                                partial + (int64_t)blockIdx.x * panel_rows, panel_rows, ypan);
+}
+
+// k columns of X in one launch.  Workgroup (column c, group g) runs the
+// ranges g*S .. g*S+S-1 of the single-column product for column c, each into
+// its own partial slot (c * W + range), so every column is summed exactly as
+// the single-column call sums it.  The k workgroups of a group are dispatched
+// to the same XCD (workgroup ids are dealt to the 8 XCDs round-robin: id b
+// goes to XCD b mod 8), so they read the same blocks, and the same lines of a
+// row-major X, through one L2 at about the same time (ordinary loads, so the
+// lines stay for the others): A streams from HBM about once for the k columns.
+template <int BLOCK, typename ValT, typename VecT>
+__global__ __launch_bounds__(BLOCK) void mv_bucket_cols(
+    const uint32_t *__restrict__ packed, const ValT *__restrict__ val, const int2 *__restrict__ blocks,
+    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, double *__restrict__ partial,
+    int panel_rows, int k, int W, int S)
+{
+    extern __shared__ double ypan[];
+    const int b = blockIdx.x;
+    const int c = (b % (8 * k)) / 8;
+    const int g = (b / (8 * k)) * 8 + b % 8;
+    const int w0 = g * S, w1 = min(W, w0 + S);
+    for (int w = w0; w < w1; ++w)
+        mv_range<BLOCK, ValT, VecT, false>(packed, val, blocks, wg_blk, w, x + c, ldx,
+                                    partial + ((int64_t)c * W + w) * panel_rows, panel_rows, ypan);
 }
 
 // y[caller row] = sum over the panel's workgroups of their partials.  Internal
@@ -819,8 +865,12 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
 // of every addition is fixed.
 template <typename VecT>
 __global__ void mv_reduce(const double *__restrict__ partial, int panel_rows, const PanelDesc *__restrict__ panels,
-                          int npanels, int64_t rows, const int32_t *__restrict__ inv, VecT *__restrict__ y, int64_t ldy)
+                          int npanels, int64_t rows, const int32_t *__restrict__ inv, VecT *__restrict__ y, int64_t ldy,
+                          int64_t col_stride)
 {
+    // column blockIdx.y: its partials start col_stride doubles further, its output one entry further
+    partial += blockIdx.y * col_stride;
+    y += blockIdx.y;
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t slot = g >> 3;              // panel * panel_rows + panel-local row
     const int t = (int)(g & 7);
@@ -1421,9 +1471,39 @@ template <typename ValT, typename VecT>
 int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT *y, int64_t ldy, hipStream_t stream)
 {
     if (A.rows == 0) return 0;
+    int e;
+    const unsigned red_blocks = blocks_for(A.n_panels * A.panel_rows * 8, 256);
+    if (k > 1 && A.mv_wgs > 0 && A.scratch.partial_cols && A.scratch.pcols > 0) {
+        // columns in batches of up to pcols, one launch per batch
+        static const bool attr_c = allow_full_lds(mv_bucket_cols<MV_BLOCK, ValT, VecT>);
+        (void)attr_c;
+        const int W = (int)A.mv_wgs, cus = device_cu_count(A.device);
+        for (int32_t c0 = 0; c0 < k; c0 += A.scratch.pcols) {
+            const int kb = (int)std::min<int64_t>(A.scratch.pcols, k - c0);
+            // S ranges per workgroup so that kb * ceil(W / S) workgroups fit the CUs
+            const int S = (int)std::max<int64_t>(1, ((int64_t)W * kb + cus - 1) / cus);
+            const int G = (W + S - 1) / S;
+            const unsigned grid = (unsigned)(kb * 8 * ((G + 7) / 8));
+            {
+                ProfScope ps(stream, "mv_bucket");
+                hipLaunchKernelGGL((mv_bucket_cols<MV_BLOCK, ValT, VecT>), dim3(grid), dim3(MV_BLOCK),
+                                   (size_t)A.panel_rows * 8, stream, (const uint32_t *)A.d_mpacked,
+                                   (const ValT *)A.d_mval, (const int2 *)A.d_mblocks, A.d_wg_blk, x + c0, ldx,
+                                   A.scratch.partial_cols, (int)A.panel_rows, kb, W, S);
+                if ((e = (int)hipGetLastError())) return e;
+            }
+            {
+                ProfScope ps(stream, "mv_reduce");
+                hipLaunchKernelGGL(mv_reduce<VecT>, dim3(red_blocks, (unsigned)kb), dim3(256), 0, stream,
+                                   A.scratch.partial_cols, (int)A.panel_rows, A.d_panels, (int)A.n_panels, A.rows,
+                                   A.relabeled ? A.d_inv : nullptr, y + c0, ldy, (int64_t)W * A.panel_rows);
+                if ((e = (int)hipGetLastError())) return e;
+            }
+        }
+        return 0;
+    }
     static const bool attr = allow_full_lds(mv_bucket<MV_BLOCK, ValT, VecT>);
     (void)attr;
-    int e;
     for (int32_t c = 0; c < k; ++c) {
         if (A.mv_wgs > 0) {
             ProfScope ps(stream, "mv_bucket");
@@ -1436,9 +1516,9 @@ int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT 
         }
         {
             ProfScope ps(stream, "mv_reduce");
-            hipLaunchKernelGGL(mv_reduce<VecT>, dim3(blocks_for(A.n_panels * A.panel_rows * 8, 256)), dim3(256), 0, stream,
-                               A.scratch.partial, (int)A.panel_rows, A.d_panels, (int)A.n_panels, A.rows,
-                               A.relabeled ? A.d_inv : nullptr, y + c, ldy);
+            hipLaunchKernelGGL(mv_reduce<VecT>, dim3(red_blocks), dim3(256), 0, stream, A.scratch.partial,
+                               (int)A.panel_rows, A.d_panels, (int)A.n_panels, A.rows, A.relabeled ? A.d_inv : nullptr,
+                               y + c, ldy, (int64_t)0);
             if ((e = (int)hipGetLastError())) return e;
         }
     }
