@@ -249,15 +249,6 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
     spw_status st;
     const int64_t WCH = vtm_chunk_default(), ITEMS = WCH / 64;
     const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), 4096);
-    {
-        // column starts, then a padding window so that the column-dot kernel
-        // can always read a fixed number of entries after any column
-        const int64_t win = vtm_slice_window();
-        std::vector<int32_t> p32((size_t)(cols + 1 + win), (int32_t)nnz);
-        for (int64_t j = 0; j <= cols; ++j) p32[(size_t)j] = (int32_t)ptr[j];
-        if ((st = dev_alloc(A, &C.d_ptr, cols + 1 + win, "column starts"))) return st;
-        if ((st = h2d(C.d_ptr, p32.data(), p32.size() * 4, "column starts"))) return st;
-    }
     // Chunk-interleaved copies: inside each chunk of W = 64*I positions, item i
     // of lane l (position l*I + i) is stored at ((i/G)*64 + l)*G + i%G, G being
     // the number of elements in 16 bytes.
@@ -339,10 +330,6 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
             return st;
         if ((st = h2d(C.d_segcol, segcol.data(), segcol.size() * 4, "segment columns"))) return st;
     }
-    if ((st = dev_alloc(A, &C.d_cjlo, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;
-    if ((st = h2d(C.d_cjlo, C.zp.jlo.data(), C.zp.jlo.size() * 4, "chunk table"))) return st;
-    if ((st = dev_alloc(A, &C.d_cjhi, std::max<int64_t>(C.zp.n_chunks, 1), "chunk table"))) return st;
-    if ((st = h2d(C.d_cjhi, C.zp.jhi.data(), C.zp.jhi.size() * 4, "chunk table"))) return st;
     {
         std::vector<int32_t> empty;
         for (int64_t j = 0; j < cols; ++j)

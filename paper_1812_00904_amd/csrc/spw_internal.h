@@ -58,11 +58,9 @@ enum class IdxKind : int32_t { U16 = 0, I32 = 1 };
 struct ColDot {
     int64_t rows = 0, cols = 0, nnz = 0;
     IdxKind idx_kind = IdxKind::U16;
-    int32_t *d_ptr = nullptr;
     void *d_idx = nullptr;
     void *d_val = nullptr;
     ZonePlan zp;
-    int32_t *d_cjlo = nullptr, *d_cjhi = nullptr;
     int32_t *d_empty = nullptr;
     int64_t n_empty = 0;
     int32_t *d_zone_col = nullptr, *d_zone_first = nullptr, *d_zone_last = nullptr;
@@ -167,7 +165,6 @@ int64_t vtm_chunk_default();
 // Waves the single-vector column-dot kernel runs for nchunks chunks on device.
 int64_t vtm_workers(int device, int64_t nchunks);
 int64_t vtm_hot_rows_limit(spw_dtype vdt);
-int64_t vtm_slice_window();
 int device_cu_count(int device);
 
 // CGLS vector steps (spw_solve.hip).  x and p have n entries, b, r and q

@@ -19,7 +19,7 @@
 // carry that the zone kernel adds in ascending chunk order.
 //
 // Scatter product (y = B x; the paper's A x, Section III): a row panel of y
-// lives in LDS per workgroup.  The panel's rows are dealt to the 16 waves of
+// lives in LDS per workgroup.  The panel's rows are dealt to the 4 waves of
 // the workgroup (balanced by count), and each wave streams, in column order,
 // only the nonzeros of its own rows, adding them into LDS.  No two waves touch
 // the same LDS entry, and a wave adds in program order, so every sum is formed
@@ -271,21 +271,22 @@ __device__ __forceinline__ SegPair wave_seg_scan(SegPair x)
 
 // ------------------------------------------------------------------------
 // Column dots, one wave per chunk of 64*ITEMS positions.
-//   ptr      : cols+1 column starts (absolute positions), followed by SLICE_W
-//              padding entries so a fixed-size window can always be read
 //   idx, val : row (renumbered when relabeled) and value of every position,
 //              interleaved inside each chunk: item i of lane l sits at value
 //              slot ((i/2)*64 + l)*2 + i%2 and at index slot ((i/G)*64 + l)*G
 //              + i%G (G indices per 16 bytes); tails are zero-padded
-//   cjlo/cjhi: column holding the chunk's first / last position
+//   heads    : per chunk and lane, the column-start bits of its positions
+//   cinfo    : per chunk, (first column, first segment, segments, flags)
+//   segcol   : per segment of a chunk with empty columns inside, its column
 //   v        : short input vector (renumbered); rows < vhot are read from LDS
 //   u        : long output; a column wholly inside the chunk is final here
 //   carry    : [2c] = part of the column entering chunk c from the left,
 //              [2c+1] = part of the column leaving chunk c to the right
 //              (a column crossing the whole chunk leaves its part in [2c])
-// Each wave handles the chunks c, c + stride, ...; the values, indices and
-// column-start window of the next chunk, and the column range of the one
-// after, are loaded while the current chunk is reduced.
+// Each wave handles the chunks c, c + stride, ... (or its run of a column
+// partition); the values, indices and column-start bits of the next chunk,
+// and the description of the one after, are loaded while the current chunk
+// is reduced.
 // Dynamic LDS: each wave's segment stage, then the vhot hot rows.  Columns
 // without nonzeros are written by zero_cols, not here.
 // ------------------------------------------------------------------------
@@ -1285,7 +1286,6 @@ constexpr int VTM_BLOCK = SPW_VTM_BLOCK;
 constexpr int VTM_BLOCK_F32 = 1024;                // single-vector column dots, 4-byte values and vectors or less
 constexpr int VTM_WG_PER_CU = SPW_VTM_WG_PER_CU;   // resident workgroups per CU (they share the LDS)
 constexpr int VTM_ITEMS = 16;
-constexpr int VTM_SLICE_W = 256;
 constexpr int MV_BLOCK = SPW_MV_BLOCK;
 constexpr int LDS_BYTES = 160 * 1024;
 
@@ -1542,7 +1542,6 @@ int64_t vtm_workers(int device, int64_t nchunks)
                                                                (nchunks + nw - 1) / nw));
     return wgs * nw;
 }
-int64_t vtm_slice_window() { return VTM_SLICE_W; }
 int64_t vtm_hot_rows_limit(spw_dtype vdt) { return hot_rows_limit(vdt == SPW_F64 ? 8 : 4, 1); }
 
 int device_cu_count(int device)
