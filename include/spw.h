@@ -220,7 +220,9 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
  *   hist  : NULL, or host array of 2*(iters+1) doubles that receives
  *           hist[k] = ||A^T r_k||^2 and hist[iters+1+k] = ||r_k||^2 for
  *           k = 0 .. iters; the call then waits for the stream before returning.
- *           Without hist the call only enqueues work on the stream.
+ *           Without hist the call only enqueues work on the stream, the same
+ *           launches on every call with the same arguments, so a caller can
+ *           capture it in a graph (after one call has grown the workspace).
  * Workspace (2m + 2n doubles and the history) is kept with the matrix until
  * spw_destroy and counted in device_bytes.  Calls on one matrix must not
  * overlap (they share that workspace and the products' scratch). */

@@ -1087,23 +1087,29 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
     w.scal = W.scal;
     w.hist_gamma = W.hist;
     w.hist_rho = W.hist + iters + 1;
-    auto vec = [&](CglsVecOp op, int64_t k) -> spw_status {
-        const int e = launch_cgls_vec(op, w, k, stream);
+    auto vec = [&](CglsVecOp op) -> spw_status {
+        const int e = launch_cgls_vec(op, w, stream);
         if (e) return fail(SPW_ERR_DEVICE, std::string("spw_cgls: kernel launch failed: ") +
                                                hipGetErrorString((hipError_t)e));
         return SPW_OK;
     };
+    auto iteration = [&]() -> spw_status {
+        spw_status s2;
+        if ((s2 = run_product(A, true, SPW_F64, 1, w.p, 1, w.q, 1, stream, "spw_cgls"))) return s2;   // q = A p
+        if ((s2 = vec(CglsVecOp::ALPHA_R))) return s2;
+        if ((s2 = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return s2;  // s = A^T r
+        return vec(CglsVecOp::BETA_XP);
+    };
     // r_0 = b - A x_0, s_0 = A^T r_0, gamma_0 = ||s_0||^2, p_0 = s_0
     if ((st = run_product(A, true, SPW_F64, 1, x, 1, w.q, 1, stream, "spw_cgls"))) return st;
-    if ((st = vec(CglsVecOp::R_INIT, 0))) return st;
+    if ((st = vec(CglsVecOp::R_INIT))) return st;
     if ((st = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return st;
-    if ((st = vec(CglsVecOp::GAMMA0, 0))) return st;
-    for (int64_t k = 1; k <= iters; ++k) {
-        if ((st = run_product(A, true, SPW_F64, 1, w.p, 1, w.q, 1, stream, "spw_cgls"))) return st;   // q = A p
-        if ((st = vec(CglsVecOp::ALPHA_R, k))) return st;
-        if ((st = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return st;  // s = A^T r
-        if ((st = vec(CglsVecOp::BETA_XP, k))) return st;
-    }
+    if ((st = vec(CglsVecOp::GAMMA0))) return st;
+    // Every iteration launches the same kernels with the same arguments (the
+    // history index lives on the device), so a caller may capture a whole
+    // call without a history in a graph and replay it.
+    for (int64_t k = 1; k <= iters; ++k)
+        if ((st = iteration())) return st;
     if (hist) {
         if (hipMemcpyAsync(hist, W.hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
                 hipSuccess ||

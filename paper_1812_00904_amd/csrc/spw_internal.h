@@ -168,7 +168,7 @@ int64_t vtm_hot_rows_limit(spw_dtype vdt);
 int device_cu_count(int device);
 
 // CGLS vector steps (spw_solve.hip).  x and p have n entries, b, r and q
-// have m; hist_gamma / hist_rho receive the inner products at index k.
+// have m; hist_gamma / hist_rho receive the inner products of iteration k.
 struct CglsWork {
     int64_t m = 0, n = 0;
     const double *b = nullptr;
@@ -181,7 +181,9 @@ enum class CglsVecOp : int {
     ALPHA_R,   // alpha = gamma / ||q||^2 (q = A p); r = r - alpha q; rho_k = ||r||^2
     BETA_XP    // gamma_k = ||s||^2 (s = A^T r); beta = gamma_k / gamma_{k-1}; x = x + alpha p; p = s + beta p
 };
-int launch_cgls_vec(CglsVecOp op, const CglsWork &w, int64_t k, void *stream);
+// The history index advances on the device (see spw_solve.hip), so the
+// launches of one iteration are the same every time.
+int launch_cgls_vec(CglsVecOp op, const CglsWork &w, void *stream);
 int64_t cgls_dot_parts();
 
 // Profiling hooks (spw_profile.cpp).

@@ -12,7 +12,8 @@
 // alpha or beta, so the loop never waits for the host.
 //
 // Scalars slot layout (binary64): [0] gamma = ||A^T r||^2 of the current
-// iterate, [1] alpha, [2] beta.
+// iterate, [1] alpha, [2] beta, [3] the iteration the history is at (an
+// integer, so one captured iteration can be replayed unchanged).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -25,7 +26,7 @@ namespace {
 constexpr int SV_BLOCK = 256;
 constexpr int SV_WAVE = 64;
 constexpr int DOT_PARTS = 1024;          // partial sums per inner product (one per workgroup)
-constexpr int S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2;
+constexpr int S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_ITER = 3;
 
 // Sum of one value per thread over a workgroup of SV_BLOCK threads, in a fixed
 // order: butterfly inside each wave, then the waves in ascending order.  The
@@ -83,27 +84,36 @@ __global__ __launch_bounds__(SV_BLOCK) void r_step(double *__restrict__ r, const
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// What the scalar kernel does with the finished inner product.
+// What the scalar kernel does with the finished inner product.  Iteration k
+// (the history index) is scal[S_ITER]: 0 during the start-up, set to 1 by
+// OP_GAMMA0 and advanced by OP_GAMMA, the last scalar step of an iteration.
 enum ScalarOp : int {
-    OP_GAMMA0 = 0,   // gamma = sum, hist_gamma[k] = sum
+    OP_GAMMA0 = 0,   // gamma = sum, hist_gamma[0] = sum, k = 1
     OP_ALPHA = 1,    // delta = sum, alpha = gamma / delta (0 when either is 0)
-    OP_GAMMA = 2,    // gamma_new = sum, beta = gamma_new / gamma (0 when gamma is 0), gamma = gamma_new
-    OP_RHO = 3       // hist_rho[k] = sum
+    OP_GAMMA = 2,    // gamma_new = sum, beta = gamma_new / gamma (0 when gamma is 0), gamma = gamma_new,
+                     // hist_gamma[k] = sum, k = k + 1
+    OP_RHO = 3,      // hist_rho[k] = sum
+    OP_RHO0 = 4      // hist_rho[0] = sum, k = 0
 };
 
 // One workgroup: adds the DOT_PARTS partial sums in a fixed order and applies op.
 __global__ __launch_bounds__(SV_BLOCK) void scalar_step(const double *__restrict__ partial, int op,
                                                         double *__restrict__ scal, double *__restrict__ hist_gamma,
-                                                        double *__restrict__ hist_rho, int64_t k)
+                                                        double *__restrict__ hist_rho)
 {
     __shared__ double lds[SV_BLOCK / SV_WAVE];
     double acc = 0.0;
     for (int i = threadIdx.x; i < DOT_PARTS; i += SV_BLOCK) acc += partial[i];
     const double sum = block_sum(acc, lds);
     if (threadIdx.x != 0) return;
-    if (op == OP_GAMMA0) {
+    const int64_t k = (int64_t)scal[S_ITER];
+    if (op == OP_RHO0) {
+        scal[S_ITER] = 0.0;
+        hist_rho[0] = sum;
+    } else if (op == OP_GAMMA0) {
         scal[S_GAMMA] = sum;
-        hist_gamma[k] = sum;
+        hist_gamma[0] = sum;
+        scal[S_ITER] = 1.0;
     } else if (op == OP_ALPHA) {
         const double gamma = scal[S_GAMMA];
         scal[S_ALPHA] = (gamma > 0.0 && sum > 0.0) ? gamma / sum : 0.0;
@@ -112,6 +122,7 @@ __global__ __launch_bounds__(SV_BLOCK) void scalar_step(const double *__restrict
         scal[S_BETA] = gamma > 0.0 ? sum / gamma : 0.0;
         scal[S_GAMMA] = sum;
         hist_gamma[k] = sum;
+        scal[S_ITER] = (double)(k + 1);
     } else {
         hist_rho[k] = sum;
     }
@@ -149,33 +160,33 @@ unsigned stream_grid(int64_t len)
 
 int64_t cgls_dot_parts() { return DOT_PARTS; }
 
-int launch_cgls_vec(CglsVecOp op, const CglsWork &w, int64_t k, void *stream)
+int launch_cgls_vec(CglsVecOp op, const CglsWork &w, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
     switch (op) {
-    case CglsVecOp::R_INIT:   // r = b - q, rho_k
+    case CglsVecOp::R_INIT:   // r = b - q, rho_0
         hipLaunchKernelGGL(r_step<true>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO, w.scal, w.hist_gamma,
-                           w.hist_rho, k);
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO0, w.scal, w.hist_gamma,
+                           w.hist_rho);
         break;
     case CglsVecOp::GAMMA0:   // gamma_0 = ||s||^2, p = s
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
         hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA0, w.scal, w.hist_gamma,
-                           w.hist_rho, k);
+                           w.hist_rho);
         hipLaunchKernelGGL(copy_vec, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.s, w.p, w.n);
         break;
     case CglsVecOp::ALPHA_R:  // alpha = gamma / ||q||^2, r = r - alpha q, rho_k
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.q, w.m, w.partial);
         hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_ALPHA, w.scal, w.hist_gamma,
-                           w.hist_rho, k);
+                           w.hist_rho);
         hipLaunchKernelGGL(r_step<false>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
         hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO, w.scal, w.hist_gamma,
-                           w.hist_rho, k);
+                           w.hist_rho);
         break;
     case CglsVecOp::BETA_XP:  // gamma_k = ||s||^2, beta, x += alpha p, p = s + beta p
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
         hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA, w.scal, w.hist_gamma,
-                           w.hist_rho, k);
+                           w.hist_rho);
         hipLaunchKernelGGL(xp_step, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
         break;
     }

@@ -154,3 +154,38 @@ def test_cgls_argument_errors(spw):
     torch.cuda.synchronize()
     assert torch.isfinite(x).all()
     M.close()
+
+
+def test_cgls_call_captured_in_a_graph(spw):
+    # A call without a history only enqueues launches that are the same on
+    # every call, so a caller can capture it in a graph: each replay must give
+    # the bits of one more direct call, with other work and synchronizations
+    # between the replays.
+    B = synth.random_csc(400, 30000, 4.0, 16, row_alpha=0.8)
+    rng = np.random.default_rng(9)
+    b, x0 = rng.uniform(-1, 1, 400), rng.uniform(-1, 1, 30000)
+    M = spw.SpwMatrix(spw.SPW_CSC, 400, 30000, B.ptr, B.idx, B.val)
+    bd = dev(b)
+    # direct: three calls of 2 iterations, each from the previous result
+    xe = dev(x0)
+    expected = []
+    for _ in range(3):
+        M.cgls(bd, xe, 2, hist=False)
+        torch.cuda.synchronize()
+        expected.append(xe.cpu().numpy().copy())
+    # captured: the workspace exists already (grown by the calls above)
+    xg = dev(x0)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        M.cgls(bd, xg, 2, hist=False)
+    xg.copy_(dev(x0))           # capture does not run the work
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(xg.cpu().numpy(), expected[rep]), rep
+        M.mv(dev(x0), torch.empty(400, dtype=torch.float64, device="cuda"))   # other work between replays
+        torch.cuda.synchronize()
+    del graph
+    M.close()
