@@ -44,7 +44,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
-                 "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver")
+                 "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver --no-small")
 
 
 def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, si: int = 4, sp: int = 4) -> int:
@@ -143,6 +143,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--no-partition", action="store_true", help="skip the column-partitioning comparison")
     ap.add_argument("--no-solver", action="store_true", help="skip the CGLS loop")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-matrix latency section")
     ap.add_argument("--solver-iters", type=int, default=20)
     ap.add_argument("--serving-requests", type=int, default=10000)
     ap.add_argument("--serving-loads", default="0.7",
@@ -270,6 +271,9 @@ def main():
     if not args.no_solver:
         extra["solver"] = bench_solver(args, A, M, vd, ms_per_step)
 
+    if not args.no_small:
+        extra["small"] = bench_small(args)
+
     if not args.no_batch:
         M.close()
         del xd, vd, yd, ud
@@ -395,6 +399,54 @@ def bench_precision(args, A, M, xd, vd):
         torch.cuda.empty_cache()
         res["rows"].append(row)
         print("[bench] precision %s" % row, file=sys.stderr, flush=True)
+    return res
+
+
+def bench_small(args):
+    """The 1e6-nonzero matrix (1,000 x 100,000; 13 MB of model bytes per
+    product, fits any cache), where a call is bound by latency: event-timed
+    kernel time of single calls warm (back to back) and cold (a 512 MiB write
+    between calls pushes the matrix out of the 256 MB Infinity Cache and the
+    L2s), and the host wall clock from the call to the end of a stream
+    synchronize over 1,000 calls."""
+    import torch
+    import synth
+    from paper_1812_00904_amd import SPW_CSC, SpwMatrix
+    A = synth.config_matrix("c0")
+    x, v = synth.config_vectors("c0", A.m, A.n)
+    M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    xd, vd = torch.from_numpy(x).cuda(), torch.from_numpy(v).cuda()
+    yd = torch.empty(A.m, dtype=torch.float64, device="cuda")
+    ud = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    by = model_bytes(A.m, A.n, A.nnz)
+    res = {"workload": "wide CSC m=%d n=%d nnz=%d (Zipf(1.1) lengths + 5 dense columns)" % (A.m, A.n, A.nnz),
+           "model_bytes": by}
+    for name, fn in (("mv", lambda: M.mv(xd, yd)), ("vtm", lambda: M.vtm(vd, ud))):
+        w50, w99 = _time_each(fn, 200)
+        cold = []
+        for _ in range(50):
+            flush.fill_(1)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            cold.append(a.elapsed_time(b))
+        wall = []
+        for _ in range(1000):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t) * 1e3)
+        res[name] = {"warm_ms_p50": round(w50, 4), "warm_ms_p99": round(w99, 4),
+                     "cold_ms_p50": round(percentile(cold, 50), 4), "cold_ms_p99": round(percentile(cold, 99), 4),
+                     "host_ms_p50": round(percentile(wall, 50), 4), "host_ms_p99": round(percentile(wall, 99), 4),
+                     "warm_GBps": round(by / (w50 * 1e-3) / 1e9, 1)}
+    M.close()
+    del flush
+    torch.cuda.empty_cache()
+    print("[bench] small %s" % res, file=sys.stderr, flush=True)
     return res
 
 
