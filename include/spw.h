@@ -94,7 +94,12 @@ typedef struct spw_matrix_s *spw_matrix;
  *                   multi-RHS products of the long-to-short direction (CSC A x,
  *                   CSR v^T A) use for k > 8 (one pass over A for all k
  *                   columns); 0 saves that memory, and those blocks then run
- *                   one scatter pass per column. */
+ *                   one scatter pass per column.
+ *   canonicalize  : 0 (default) rejects indices that are not strictly increasing
+ *                   inside a column (row) and, in spw_create_coo, repeated
+ *                   (row, column) pairs; 1 sorts each column (row) by index and
+ *                   sums the values of a repeated index in the order they were
+ *                   given.  Indices out of range are rejected either way. */
 typedef struct {
     uint32_t struct_size;
     spw_dtype value_storage;
@@ -105,7 +110,8 @@ typedef struct {
     int32_t device;
     int32_t transpose;
     spw_partition partition;
-    int32_t reserved[6];
+    int32_t canonicalize;
+    int32_t reserved[5];
 } spw_create_opts;
 
 /* Read-only description of a created matrix. */

@@ -722,6 +722,46 @@ spw_status grow_cgls(spw_matrix_s &A, int64_t hist_len)
     return SPW_OK;
 }
 
+// Sorts every line (column of a CSC, row of a CSR) by index and sums the
+// values of a repeated index in the order the positions were given.  ptr must
+// be valid and every index in [0, n_inner).  Fills the compressed output.
+void canonical_lines(int64_t n_outer, const int64_t *ptr, const int32_t *idx, const double *val,
+                     std::vector<int64_t> &optr, std::vector<int32_t> &oidx, std::vector<double> &oval)
+{
+    const int64_t nnz = ptr[n_outer];
+    std::vector<int64_t> cnt((size_t)n_outer, 0), order((size_t)nnz);
+    parallel_for(n_outer, [&](int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j) {
+            int64_t *o0 = order.data() + ptr[j], *o1 = order.data() + ptr[j + 1];
+            std::iota(o0, o1, ptr[j]);
+            std::stable_sort(o0, o1, [&](int64_t x, int64_t y) { return idx[x] < idx[y]; });
+            int64_t distinct = 0;
+            for (int64_t *q = o0; q < o1; ++q)
+                if (q == o0 || idx[*q] != idx[*(q - 1)]) ++distinct;
+            cnt[(size_t)j] = distinct;
+        }
+    });
+    optr.assign((size_t)n_outer + 1, 0);
+    for (int64_t j = 0; j < n_outer; ++j) optr[(size_t)j + 1] = optr[(size_t)j] + cnt[(size_t)j];
+    oidx.resize((size_t)optr[(size_t)n_outer]);
+    oval.resize((size_t)optr[(size_t)n_outer]);
+    parallel_for(n_outer, [&](int64_t a, int64_t b) {
+        for (int64_t j = a; j < b; ++j) {
+            int64_t w = optr[(size_t)j] - 1;
+            for (int64_t q = ptr[j]; q < ptr[j + 1]; ++q) {
+                const int64_t p = order[(size_t)q];
+                if (q == ptr[j] || idx[p] != oidx[(size_t)w]) {
+                    ++w;
+                    oidx[(size_t)w] = idx[p];
+                    oval[(size_t)w] = val[p];
+                } else {
+                    oval[(size_t)w] = oval[(size_t)w] + val[p];
+                }
+            }
+        }
+    });
+}
+
 }  // namespace spw
 
 using namespace spw;
@@ -791,6 +831,25 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     const int64_t pad = 4096;
     if (nnz + pad >= ((int64_t)1 << 31) || cols >= ((int64_t)1 << 31) - 1 || rows >= ((int64_t)1 << 31))
         return fail(SPW_ERR_UNSUPPORTED, "spw_create: nnz and dimensions must stay below 2^31");
+    if (opts.canonicalize) {
+        // checks of the pointer and of the index range (order and repeats are fixed here)
+        if (ptr[0] != 0 || ptr[cols] != nnz)
+            return fail(SPW_ERR_BAD_MATRIX, "ptr must start at 0 and end at nnz");
+        for (int64_t j = 0; j < cols; ++j)
+            if (ptr[j + 1] < ptr[j])
+                return fail(SPW_ERR_BAD_MATRIX, "ptr decreases at " + std::to_string(j));
+        for (int64_t p = 0; p < nnz; ++p)
+            if (idx[p] < 0 || idx[p] >= rows)
+                return fail(SPW_ERR_BAD_MATRIX, "index out of range at position " + std::to_string(p));
+        std::vector<int64_t> cptr;
+        std::vector<int32_t> cidx;
+        std::vector<double> cval;
+        canonical_lines(cols, ptr, idx, val, cptr, cidx, cval);
+        spw_create_opts o2 = opts;
+        o2.canonicalize = 0;
+        o2.validate = 0;
+        return spw_create(out, fmt, m, n, (int64_t)cidx.size(), cptr.data(), cidx.data(), cval.data(), &o2);
+    }
     if (opts.validate) {
         spw_status st = validate(cols, rows, nnz, ptr, idx, fmt == SPW_CSC ? "column" : "row");
         if (st) return st;
@@ -942,6 +1001,17 @@ spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n,
             }
         }
     });
+    const bool canon = opts && opts->struct_size == sizeof(spw_create_opts) && opts->canonicalize;
+    if (dup.load() >= 0 && canon) {
+        // repeats summed in the order given: the lines are sorted by (index, given position)
+        std::vector<int64_t> cptr;
+        std::vector<int32_t> cidx;
+        std::vector<double> cval;
+        canonical_lines(n_outer, ptr.data(), idx.data(), v.data(), cptr, cidx, cval);
+        spw_create_opts o2 = *opts;
+        o2.canonicalize = 0;
+        return spw_create(out, fmt, m, n, (int64_t)cidx.size(), cptr.data(), cidx.data(), cval.data(), &o2);
+    }
     if (dup.load() >= 0) {
         const int64_t p = dup.load();
         return fail(SPW_ERR_BAD_MATRIX, "spw_create_coo: (" + std::to_string(rows[p]) + ", " +

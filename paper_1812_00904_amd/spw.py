@@ -38,7 +38,7 @@ class CreateOpts(ctypes.Structure):
                 ("chunk_nnz", ctypes.c_int32), ("relabel", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("transpose", ctypes.c_int32), ("partition", ctypes.c_int),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("canonicalize", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class MatrixInfo(ctypes.Structure):

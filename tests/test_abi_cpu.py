@@ -235,3 +235,16 @@ def test_news20_shaped_statistics():
     assert np.all(np.diff(A.idx[A.ptr[0]:A.ptr[1]]) > 0)
     B = synth.news20_shaped()
     assert np.array_equal(A.ptr, B.ptr) and np.array_equal(A.idx, B.idx) and np.array_equal(A.val, B.val)
+
+
+def test_canonicalize_still_rejects_out_of_range_before_device_use(spw):
+    ptr = np.array([0, 3, 4], dtype=np.int64)
+    val = np.ones(4)
+    opts = spw.create_opts(canonicalize=1)
+    # unsorted and repeated rows are fine with canonicalize; a row past the end is not
+    msg = _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 3, 2, ptr,
+                  np.array([2, 0, 3, 1], dtype=np.int32), val, opts)
+    assert "position 2" in msg
+    _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 3, 2, np.array([0, 3, 5]),
+            np.array([2, 0, 2, 1], dtype=np.int32), val, opts)
+    assert ctypes.sizeof(spw.CreateOpts) == 60

@@ -110,3 +110,53 @@ def test_news20_shaped_parity(spw, order, partition):
         P = info["workers"]
         delta = P * (info["worker_max_nnz"] - info["worker_min_nnz"]) / A.nnz
         assert delta == pytest.approx(oracle.colp_imbalance(A.n, A.ptr, P), rel=1e-12, abs=1e-15)
+
+
+def _canonical(ptr, idx, val):
+    """Each column sorted by row, repeated rows summed in the order given (plain Python)."""
+    P, I, V = [0], [], []
+    for j in range(len(ptr) - 1):
+        acc = {}
+        for p in range(ptr[j], ptr[j + 1]):
+            acc[int(idx[p])] = acc[int(idx[p])] + val[p] if int(idx[p]) in acc else val[p]
+        for r in sorted(acc):
+            I.append(r)
+            V.append(acc[r])
+        P.append(len(I))
+    return np.array(P, dtype=np.int64), np.array(I, dtype=np.int32), np.array(V)
+
+
+def test_canonicalize_sorts_and_sums_repeats(spw):
+    # columns given out of order and with repeated rows (values in their given
+    # order, sums formed left to right), against the canonical form built here
+    rng = np.random.default_rng(7)
+    m, n = 300, 4000
+    lens = rng.integers(0, 9, n)
+    ptr = np.r_[0, np.cumsum(lens)].astype(np.int64)
+    idx = rng.integers(0, m, int(ptr[-1])).astype(np.int32)
+    val = rng.uniform(-1, 1, int(ptr[-1]))
+    cp, ci, cv = _canonical(ptr, idx, val)
+    x, v = synth.vector(n, 5, 1), synth.vector(m, 5, 2)
+    Mref = spw.SpwMatrix(spw.SPW_CSC, m, n, cp, ci, cv)
+    ref = products(Mref, m, n, x, v)
+    Mref.close()
+    Mc = spw.SpwMatrix(spw.SPW_CSC, m, n, ptr, idx, val, canonicalize=1)
+    got = products(Mc, m, n, x, v)
+    Mc.close()
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    # the same entries as shuffled triples: repeats are rejected, or summed in the order given
+    cols = np.repeat(np.arange(n, dtype=np.int32), lens)
+    perm = rng.permutation(idx.size)
+    with pytest.raises(spw.SpwError):
+        spw.SpwMatrix.from_coo(spw.SPW_CSC, m, n, idx[perm], cols[perm], val[perm])
+    # summing in the given (shuffled) order: build that canonical form from the shuffled stream
+    order = np.argsort(cols[perm], kind="stable")
+    sp = np.r_[0, np.cumsum(np.bincount(cols[perm], minlength=n))].astype(np.int64)
+    qp, qi, qv = _canonical(sp, idx[perm][order], val[perm][order])
+    Mq = spw.SpwMatrix(spw.SPW_CSC, m, n, qp, qi, qv)
+    ref2 = products(Mq, m, n, x, v)
+    Mq.close()
+    Mo = spw.SpwMatrix.from_coo(spw.SPW_CSC, m, n, idx[perm], cols[perm], val[perm], canonicalize=1)
+    got2 = products(Mo, m, n, x, v)
+    Mo.close()
+    assert np.array_equal(got2[0], ref2[0]) and np.array_equal(got2[1], ref2[1])
