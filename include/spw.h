@@ -49,7 +49,7 @@ typedef enum {
     SPW_ERR_BUDGET = 4,        /* serving: registering or admitting would exceed the HBM budget */
     SPW_ERR_DEVICE = 5,        /* a HIP runtime call or kernel launch failed */
     SPW_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement (e.g. nnz >= 2^31) */
-    SPW_ERR_BUSY = 7,          /* serving: queue full */
+    SPW_ERR_BUSY = 7,          /* serving: queue full; products: the matrix has work in flight on another stream */
     SPW_ERR_TIMEOUT = 8,       /* serving: wait timed out (the request stays queued) */
     SPW_ERR_SHUTDOWN = 9       /* serving: server is shutting down */
 } spw_status;
@@ -178,6 +178,14 @@ spw_status spw_destroy(spw_matrix A);
 spw_status spw_info(spw_matrix A, spw_matrix_info *out);
 
 /* --------------------------------------------------------------- products */
+
+/* Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ * stream); results are valid once the stream reaches the end of the call's
+ * work.  A matrix's scratch serves one stream at a time: a product or solver
+ * call on another stream than the previous call's while that call's work is
+ * still pending returns SPW_ERR_BUSY (nothing is enqueued).  Work captured into
+ * a graph, and work the server issues, is ordered by its owner and not checked.
+ */
 
 /* y := A x (Section I; for CSC, Section III's nonzero-split product).
  * x: device, n entries of type vdt; y: device, m entries of type vdt.

@@ -236,6 +236,55 @@ struct DeviceGuard {
     }
 };
 
+// One stream at a time per matrix: a call on another stream than the last
+// call's, while the last call's work is still pending, returns SPW_ERR_BUSY.
+// Work being captured into a graph is ordered by the caller and is not tracked.
+bool capturing(void *stream)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool yes = hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+    (void)hipGetLastError();
+    return yes;
+}
+
+spw_status claim_stream(spw_matrix_s &A, void *stream, const char *fname)
+{
+    if (capturing(stream)) return SPW_OK;
+    std::lock_guard<std::mutex> lk(A.use_mu);
+    if (A.used && stream != A.last_stream && A.last_done) {
+        const hipError_t q = hipEventQuery((hipEvent_t)A.last_done);
+        if (q == hipErrorNotReady)
+            return fail(SPW_ERR_BUSY, std::string(fname) + ": the matrix still has work in flight on another stream");
+        if (q != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, std::string(fname) + ": hipEventQuery failed");
+        }
+    }
+    return SPW_OK;
+}
+
+// Marks the end of a call's work on stream.
+spw_status release_stream(spw_matrix_s &A, void *stream, const char *fname)
+{
+    if (capturing(stream)) return SPW_OK;
+    std::lock_guard<std::mutex> lk(A.use_mu);
+    if (!A.last_done) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, std::string(fname) + ": hipEventCreate failed");
+        }
+        A.last_done = e;
+    }
+    if (hipEventRecord((hipEvent_t)A.last_done, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPW_ERR_DEVICE, std::string(fname) + ": hipEventRecord failed");
+    }
+    A.last_stream = stream;
+    A.used = true;
+    return SPW_OK;
+}
+
 // Column-dot storage of a rows x cols CSC matrix (ptr over columns, rows[]
 // already in the numbering the kernel will use).
 spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, const int64_t *ptr,
@@ -1028,6 +1077,7 @@ spw_status spw_destroy(spw_matrix A)
     {
         DeviceGuard dg(A->device);
         (void)hipDeviceSynchronize();
+        if (A->last_done) (void)hipEventDestroy((hipEvent_t)A->last_done);
         free_all(A);
     }
     delete A;
@@ -1079,8 +1129,9 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         return fail(SPW_ERR_INVALID_ARG, std::string(fname) + ": NULL vector");
     DeviceGuard dg(A->device);
     if (dg.st) return dg.st;
-    spw_status st = grow_scratch(*A, k);
+    spw_status st = claim_stream(*A, stream, fname);
     if (st) return st;
+    if ((st = grow_scratch(*A, k))) return st;
     int e;
     if (k == 1 && ldi == 1 && ldo == 1) {
         e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
@@ -1106,7 +1157,7 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     if (e == (int)hipErrorNotSupported)
         return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");
     if (e) return fail(SPW_ERR_DEVICE, std::string(fname) + ": kernel launch failed: " + hipGetErrorString((hipError_t)e));
-    return SPW_OK;
+    return release_stream(*A, stream, fname);
 }
 
 spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)
@@ -1180,6 +1231,7 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
     // call without a history in a graph and replay it.
     for (int64_t k = 1; k <= iters; ++k)
         if ((st = iteration())) return st;
+    if ((st = release_stream(*A, stream, "spw_cgls"))) return st;
     if (hist) {
         if (hipMemcpyAsync(hist, W.hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
                 hipSuccess ||

@@ -11,6 +11,7 @@
 #pragma once
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -125,6 +126,14 @@ struct spw_matrix_s {
     spw::CglsScratch cgls;
     int64_t device_bytes = 0;
     std::vector<std::pair<void *, int64_t>> allocations;   // device buffers and their sizes
+
+    // The stream of the last product call and an event recorded after it: a
+    // call on another stream while that event is pending would race on the
+    // scratch, and is refused (SPW_ERR_BUSY).
+    std::mutex use_mu;
+    void *last_stream = nullptr;
+    void *last_done = nullptr;          // hipEvent_t, created on first use
+    bool used = false;
 };
 
 namespace spw {

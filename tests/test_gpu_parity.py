@@ -212,3 +212,27 @@ def test_streams_and_determinism(spw):
     assert np.array_equal(y.cpu().numpy(), ref_y)
     assert np.array_equal(u.cpu().numpy(), ref_u)
     M.close()
+
+
+def test_other_stream_while_busy(spw):
+    # a matrix serves one stream at a time: while its last call is pending on
+    # stream a, a call on stream b is refused; once idle, b may use it
+    A = synth.config_matrix("c0")
+    M = spw.SpwMatrix(spw.SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    v = torch.rand(A.m, dtype=torch.float64, device="cuda")
+    u = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    u2 = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sa):
+        torch.cuda._sleep(50_000_000)        # a bounded spin that keeps stream a busy for a while
+        M.vtm(v, u, stream=sa)
+        with pytest.raises(spw.SpwError) as ei:
+            M.vtm(v, u2, stream=sb)
+        assert ei.value.status_name == "SPW_ERR_BUSY"
+        M.vtm(v, u, stream=sa)               # the same stream is always fine
+    torch.cuda.synchronize()
+    M.vtm(v, u2, stream=sb)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u2)
+    M.close()
