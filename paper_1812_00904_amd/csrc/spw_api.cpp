@@ -1190,8 +1190,10 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
     if ((A->m > 0 && !b) || (A->n > 0 && !x)) return fail(SPW_ERR_INVALID_ARG, "spw_cgls: NULL vector");
     DeviceGuard dg(A->device);
     if (dg.st) return dg.st;
-    spw_status st = grow_scratch(*A, 1);
+    // refuse a busy matrix before any workspace is reallocated
+    spw_status st = claim_stream(*A, stream, "spw_cgls");
     if (st) return st;
+    if ((st = grow_scratch(*A, 1))) return st;
     const int64_t hl = 2 * ((int64_t)iters + 1);
     if ((st = grow_cgls(*A, hl))) return st;
     CglsScratch &W = A->cgls;

@@ -230,6 +230,11 @@ def test_other_stream_while_busy(spw):
         with pytest.raises(spw.SpwError) as ei:
             M.vtm(v, u2, stream=sb)
         assert ei.value.status_name == "SPW_ERR_BUSY"
+        b = torch.ones(A.m, dtype=torch.float64, device="cuda")
+        xs = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        with pytest.raises(spw.SpwError) as ei:  # the solver is refused before it touches x
+            M.cgls(b, xs, 2, hist=False, stream=sb)
+        assert ei.value.status_name == "SPW_ERR_BUSY"
         M.vtm(v, u, stream=sa)               # the same stream is always fine
     torch.cuda.synchronize()
     M.vtm(v, u2, stream=sb)
