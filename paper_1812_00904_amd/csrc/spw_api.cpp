@@ -15,6 +15,10 @@
 
 #include "spw_internal.h"
 
+#ifndef SPW_MULTI_MAX_K
+#define SPW_MULTI_MAX_K 2
+#endif
+
 namespace spw {
 
 static thread_local std::string t_err;
@@ -1131,13 +1135,15 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     if (dg.st) return dg.st;
     spw_status st = claim_stream(*A, stream, fname);
     if (st) return st;
-    if ((st = grow_scratch(*A, k))) return st;
+    if ((st = grow_scratch(*A, coldot_tile_width(k)))) return st;
     int e;
     if (k == 1 && ldi == 1 && ldo == 1) {
         e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
-    } else if (scatter && (k <= 8 || !A->cdt.built)) {
+    } else if (scatter && (k < 16 || !A->cdt.built)) {
         // few right-hand sides (or no transpose kept): scatter launches of up
-        // to 8 columns whose workgroups read A together
+        // to 8 columns whose workgroups read A together.  Below 16 columns
+        // these beat the column dots over the transpose, whose gathers of the
+        // caller's k-wide rows of X cross cache lines unless k is a power of two.
         if ((st = grow_partial_cols(*A, std::min<int32_t>(k, 8)))) return st;
         e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
     } else if (scatter) {
@@ -1147,7 +1153,7 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         } else {
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
-    } else if (k <= 2) {
+    } else if (k <= SPW_MULTI_MAX_K) {
         // two columns: each chunk read once and reduced per column
         e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     } else {

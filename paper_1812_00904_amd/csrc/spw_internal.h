@@ -160,6 +160,15 @@ int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *
 // every column is bit-identical to the k = 1 product on it.
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
               void *y, int64_t ldy, void *stream);
+// Lanes per nonzero of the multi-RHS column dots: the power of two >= k.
+// A renumbered copy of V is stored with this row stride, so the scratch
+// (Scratch::kcap) must be grown to it before the call.
+inline int32_t coldot_tile_width(int32_t k)
+{
+    int32_t L = 1;
+    while (L < k) L <<= 1;
+    return L;
+}
 // Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
 // inv renumbers the rows of V (NULL when C uses the caller's numbering).
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,

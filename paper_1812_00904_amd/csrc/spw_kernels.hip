@@ -1261,16 +1261,16 @@ __global__ void gather_tab(const int32_t *__restrict__ inv, int64_t rows, int k,
     out[g] = in.v[c][src * in.ld[c]];
 }
 
-// Renumber the rows of a k-wide block: out[r*k + c] = in[inv[r]*ldv + c].
+// Renumber the rows of a k-wide block: out[r*ldo + c] = in[inv[r]*ldv + c].
 template <typename VinT>
 __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k, const VinT *__restrict__ in,
-                            int64_t ldv, VinT *__restrict__ out)
+                            int64_t ldv, VinT *__restrict__ out, int64_t ldo)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= rows * k) return;
     const int64_t r = g / k;
     const int cc = (int)(g - r * k);
-    out[g] = in[(int64_t)inv[r] * ldv + cc];
+    out[r * ldo + cc] = in[(int64_t)inv[r] * ldv + cc];
 }
 
 #ifndef SPW_VTM_BLOCK
@@ -1480,8 +1480,11 @@ int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT 
         const int W = (int)A.mv_wgs, cus = device_cu_count(A.device);
         for (int32_t c0 = 0; c0 < k; c0 += A.scratch.pcols) {
             const int kb = (int)std::min<int64_t>(A.scratch.pcols, k - c0);
-            // S ranges per workgroup so that kb * ceil(W / S) workgroups fit the CUs
-            const int S = (int)std::max<int64_t>(1, ((int64_t)W * kb + cus - 1) / cus);
+            // S ranges per workgroup, the fewest for which all kb * ceil(W / S)
+            // workgroups run at once (one per CU): a few workgroups over the CU
+            // count would run as a second round and double the time
+            int S = (int)std::max<int64_t>(1, ((int64_t)W * kb + cus - 1) / cus);
+            while (S < W && (int64_t)kb * ((W + S - 1) / S) > cus) ++S;
             const int G = (W + S - 1) / S;
             const unsigned grid = (unsigned)(kb * 8 * ((G + 7) / 8));
             {
@@ -1672,12 +1675,17 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
         const VecT *Vin = V;
         int64_t ldin = ldv;
         if (inv) {
+            // rows padded to the tile width, so that every gathered row starts
+            // on a multiple of its size (a 12-wide binary64 row would straddle
+            // two 128-byte lines half of the time)
+            const int32_t L = coldot_tile_width(k);
+            if (A.scratch.kcap < L) return (int)hipErrorInvalidValue;
             VecT *vp = reinterpret_cast<VecT *>(A.scratch.vperm);
             hipLaunchKernelGGL(gather_rows<VecT>, dim3(blocks_for(C.rows * k, 256)), dim3(256), 0, stream, inv,
-                               C.rows, k, V, ldv, vp);
+                               C.rows, k, V, ldv, vp, (int64_t)L);
             if ((e = (int)hipGetLastError())) return e;
             Vin = vp;
-            ldin = k;
+            ldin = L;
         }
         e = C.idx_kind == IdxKind::U16 ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream)
                                        : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream);
