@@ -767,14 +767,15 @@ def batch_plan(info, k):
         L *= 2
     tile = ("chunks of 1024 nonzeros, one chunk per wave: %d column lanes x %d position sub-groups of %d "
             "nonzeros, batches of 8, 256-thread workgroups" % (L, 64 // L, 16 * L))
-    if k <= 8:
-        mv = ("%d scatter pass(es): %d row panel(s) of %d rows in LDS, %d workgroups x 4 waves, blocks of 1024 "
-              "nonzeros" % (k, info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
+    if k < 16:
+        mv = ("scatter over %d column(s) in launches of up to 8: %d row panel(s) of %d rows in LDS, %d workgroup "
+              "ranges x 4 waves per column, blocks of 1024 nonzeros"
+              % (k, info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
     else:
         mv = "column dots over the kept transpose: " + tile
     if k == 1:
-        vtm = "column dots: chunks of 1024 nonzeros, one wave per chunk, 512-thread persistent workgroups"
-    elif k == 2:
+        vtm = "column dots: chunks of 1024 nonzeros, one wave per chunk, persistent workgroups"
+    elif k <= 6:
         vtm = "column dots, chunk loaded once and reduced per column: chunks of 1024 nonzeros, one wave per chunk"
     else:
         vtm = "column dots: " + tile

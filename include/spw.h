@@ -203,7 +203,7 @@ spw_status spw_vtm(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *st
  * X: device, row-major n x k with leading dimension ldx >= k (X[j*ldx + c]);
  * Y: device, row-major m x k, ldy >= k.  Column c of Y equals spw_mv on column c
  * of X up to rounding order.  For the scatter direction (CSC A x, CSR v^T A)
- * with 2 <= k <= 8 the first call allocates a partial-sum workspace of
+ * with 2 <= k <= 15 the first call allocates a partial-sum workspace of
  * min(k, 8) * mv_workgroups * panel_rows doubles, kept with the matrix. */
 spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, int64_t ldx,
                         void *Y, int64_t ldy, void *stream);

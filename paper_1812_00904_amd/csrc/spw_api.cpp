@@ -15,10 +15,6 @@
 
 #include "spw_internal.h"
 
-#ifndef SPW_MULTI_MAX_K
-#define SPW_MULTI_MAX_K 2
-#endif
-
 namespace spw {
 
 static thread_local std::string t_err;
@@ -1153,8 +1149,9 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         } else {
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
-    } else if (k <= SPW_MULTI_MAX_K) {
-        // two columns: each chunk read once and reduced per column
+    } else if (k <= 6) {
+        // up to 6 columns: each chunk read once and reduced per column (faster
+        // than the tiled column dots there; the tiles win from about 7 on)
         e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     } else {
         // column dots for k columns in one pass over the matrix
