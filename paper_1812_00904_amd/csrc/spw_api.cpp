@@ -7,9 +7,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <numeric>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -22,6 +24,35 @@ void set_error(const std::string &msg) { t_err = msg; }
 
 namespace {
 
+// Runs part(t) for t = 0 .. nparts-1 on host threads.  A part whose thread
+// cannot be started runs on the calling thread; every thread is joined before
+// the first exception any part threw is rethrown here, so no exception escapes
+// a worker thread.
+template <typename F>
+void run_parts(int64_t nparts, F &&part)
+{
+    std::vector<std::exception_ptr> errs((size_t)std::max<int64_t>(nparts, 0));
+    std::vector<std::thread> th;
+    th.reserve(errs.size());
+    auto body = [&part, &errs](int64_t t) {
+        try {
+            part(t);
+        } catch (...) {
+            errs[(size_t)t] = std::current_exception();
+        }
+    };
+    for (int64_t t = 0; t < nparts; ++t) {
+        try {
+            th.emplace_back(body, t);
+        } catch (const std::system_error &) {
+            body(t);
+        }
+    }
+    for (auto &t : th) t.join();
+    for (auto &e : errs)
+        if (e) std::rethrow_exception(e);
+}
+
 template <typename F>
 void parallel_for(int64_t n, F &&f)
 {
@@ -30,14 +61,11 @@ void parallel_for(int64_t n, F &&f)
         f((int64_t)0, n);
         return;
     }
-    std::vector<std::thread> th;
     const int64_t per = (n + nt - 1) / nt;
-    for (int t = 0; t < nt; ++t) {
+    run_parts(nt, [&](int64_t t) {
         const int64_t a = t * per, b = std::min(n, a + per);
-        if (a >= b) break;
-        th.emplace_back([&f, a, b] { f(a, b); });
-    }
-    for (auto &t : th) t.join();
+        if (a < b) f(a, b);
+    });
 }
 
 spw_status fail(spw_status s, const std::string &msg)
@@ -96,22 +124,18 @@ spw_status validate(int64_t outer, int64_t inner, int64_t nnz, const int64_t *pt
     std::vector<int64_t> bad((size_t)std::min<int64_t>(16, std::max<int64_t>(outer, 1)), -1);
     const int64_t nparts = (int64_t)bad.size();
     const int64_t per = (outer + nparts - 1) / std::max<int64_t>(nparts, 1);
-    std::vector<std::thread> th;
-    for (int64_t t = 0; t < nparts; ++t) {
-        th.emplace_back([&, t] {
-            const int64_t a = t * per, b = std::min(outer, a + per);
-            for (int64_t j = a; j < b; ++j) {
-                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
-                    const int32_t r = idx[p];
-                    if (r < 0 || r >= inner || (p > ptr[j] && idx[p - 1] >= r)) {
-                        bad[(size_t)t] = p;
-                        return;
-                    }
+    run_parts(nparts, [&](int64_t t) {
+        const int64_t a = t * per, b = std::min(outer, a + per);
+        for (int64_t j = a; j < b; ++j) {
+            for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
+                const int32_t r = idx[p];
+                if (r < 0 || r >= inner || (p > ptr[j] && idx[p - 1] >= r)) {
+                    bad[(size_t)t] = p;
+                    return;
                 }
             }
-        });
-    }
-    for (auto &t : th) t.join();
+        }
+    });
     for (int64_t b : bad) {
         if (b >= 0) {
             const int32_t r = idx[b];
@@ -175,21 +199,16 @@ int64_t round_values(spw_dtype storage, int64_t n, const double *in, double *out
 {
     std::vector<int64_t> bad(16, -1);
     const int64_t per = (n + 15) / 16;
-    std::vector<std::thread> th;
-    for (int t = 0; t < 16; ++t) {
+    run_parts(16, [&](int64_t t) {
         const int64_t a = t * per, b = std::min(n, a + per);
-        if (a >= b) break;
-        th.emplace_back([&, t, a, b] {
-            for (int64_t p = a; p < b; ++p) {
-                double r = in[p];
-                const bool ok = storage == SPW_F32 ? round_f32(in[p], &r)
-                                                   : storage == SPW_BF16 ? round_bf16(in[p], &r) : true;
-                out[p] = r;
-                if (!ok && bad[(size_t)t] < 0) bad[(size_t)t] = p;
-            }
-        });
-    }
-    for (auto &t : th) t.join();
+        for (int64_t p = a; p < b; ++p) {
+            double r = in[p];
+            const bool ok = storage == SPW_F32 ? round_f32(in[p], &r)
+                                               : storage == SPW_BF16 ? round_bf16(in[p], &r) : true;
+            out[p] = r;
+            if (!ok && bad[(size_t)t] < 0) bad[(size_t)t] = p;
+        }
+    });
     for (int64_t v : bad)
         if (v >= 0) return v;
     return -1;
@@ -836,7 +855,7 @@ const char *spw_status_string(spw_status s)
     return "SPW_UNKNOWN_STATUS";
 }
 
-spw_status spw_create_opts_default(spw_create_opts *o)
+static spw_status spw_create_opts_default_impl(spw_create_opts *o)
 {
     if (!o) return fail(SPW_ERR_INVALID_ARG, "spw_create_opts_default: NULL opts");
     std::memset(o, 0, sizeof(*o));
@@ -851,8 +870,14 @@ spw_status spw_create_opts_default(spw_create_opts *o)
     return SPW_OK;
 }
 
-spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int64_t *ptr,
-                      const int32_t *idx, const double *val, const spw_create_opts *opts_in)
+spw_status spw_create_opts_default(spw_create_opts *o)
+{
+    return guarded("spw_create_opts_default", [&] { return spw_create_opts_default_impl(o); });
+}
+
+static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz,
+                                  const int64_t *ptr, const int32_t *idx, const double *val,
+                                  const spw_create_opts *opts_in)
 {
     if (!out) return fail(SPW_ERR_INVALID_ARG, "spw_create: NULL out");
     *out = nullptr;
@@ -1003,8 +1028,15 @@ spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int
     return SPW_OK;
 }
 
-spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int32_t *rows,
-                          const int32_t *cols, const double *val, const spw_create_opts *opts)
+spw_status spw_create(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int64_t *ptr,
+                      const int32_t *idx, const double *val, const spw_create_opts *opts_in)
+{
+    return guarded("spw_create", [&] { return spw_create_impl(out, fmt, m, n, nnz, ptr, idx, val, opts_in); });
+}
+
+static spw_status spw_create_coo_impl(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz,
+                                      const int32_t *rows, const int32_t *cols, const double *val,
+                                      const spw_create_opts *opts)
 {
     if (!out) return fail(SPW_ERR_INVALID_ARG, "spw_create_coo: NULL out");
     *out = nullptr;
@@ -1071,7 +1103,13 @@ spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n,
     return spw_create(out, fmt, m, n, nnz, ptr.data(), idx.data(), v.data(), opts);
 }
 
-spw_status spw_destroy(spw_matrix A)
+spw_status spw_create_coo(spw_matrix *out, spw_format fmt, int64_t m, int64_t n, int64_t nnz, const int32_t *rows,
+                          const int32_t *cols, const double *val, const spw_create_opts *opts)
+{
+    return guarded("spw_create_coo", [&] { return spw_create_coo_impl(out, fmt, m, n, nnz, rows, cols, val, opts); });
+}
+
+static spw_status spw_destroy_impl(spw_matrix A)
 {
     if (!A) return SPW_OK;
     {
@@ -1084,7 +1122,12 @@ spw_status spw_destroy(spw_matrix A)
     return SPW_OK;
 }
 
-spw_status spw_info(spw_matrix A, spw_matrix_info *o)
+spw_status spw_destroy(spw_matrix A)
+{
+    return guarded("spw_destroy", [&] { return spw_destroy_impl(A); });
+}
+
+static spw_status spw_info_impl(spw_matrix A, spw_matrix_info *o)
 {
     if (!A || !o) return fail(SPW_ERR_INVALID_ARG, "spw_info: NULL argument");
     if (o->struct_size != sizeof(spw_matrix_info))
@@ -1112,6 +1155,11 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *o)
     o->device = A->device;
     o->device_bytes = A->device_bytes;
     return SPW_OK;
+}
+
+spw_status spw_info(spw_matrix A, spw_matrix_info *o)
+{
+    return guarded("spw_info", [&] { return spw_info_impl(A, o); });
 }
 
 static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
@@ -1163,29 +1211,52 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     return release_stream(*A, stream, fname);
 }
 
-spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)
+static spw_status spw_mv_impl(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)
 {
     return run_product(A, true, vdt, 1, x, 1, y, 1, stream, "spw_mv");
 }
 
-spw_status spw_vtm(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *stream)
+spw_status spw_mv(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)
+{
+    return guarded("spw_mv", [&] { return spw_mv_impl(A, vdt, x, y, stream); });
+}
+
+static spw_status spw_vtm_impl(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *stream)
 {
     return run_product(A, false, vdt, 1, v, 1, u, 1, stream, "spw_vtm");
+}
+
+spw_status spw_vtm(spw_matrix A, spw_dtype vdt, const void *v, void *u, void *stream)
+{
+    return guarded("spw_vtm", [&] { return spw_vtm_impl(A, vdt, v, u, stream); });
+}
+
+static spw_status spw_mv_batch_impl(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, int64_t ldx, void *Y,
+                                    int64_t ldy, void *stream)
+{
+    return run_product(A, true, vdt, k, X, ldx, Y, ldy, stream, "spw_mv_batch");
 }
 
 spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
                         void *stream)
 {
-    return run_product(A, true, vdt, k, X, ldx, Y, ldy, stream, "spw_mv_batch");
+    return guarded("spw_mv_batch", [&] { return spw_mv_batch_impl(A, vdt, k, X, ldx, Y, ldy, stream); });
+}
+
+static spw_status spw_vtm_batch_impl(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv, void *U,
+                                     int64_t ldu, void *stream)
+{
+    return run_product(A, false, vdt, k, V, ldv, U, ldu, stream, "spw_vtm_batch");
 }
 
 spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv, void *U, int64_t ldu,
                          void *stream)
 {
-    return run_product(A, false, vdt, k, V, ldv, U, ldu, stream, "spw_vtm_batch");
+    return guarded("spw_vtm_batch", [&] { return spw_vtm_batch_impl(A, vdt, k, V, ldv, U, ldu, stream); });
 }
 
-spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist, void *stream)
+static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist,
+                                void *stream)
 {
     if (!A) return fail(SPW_ERR_INVALID_ARG, "spw_cgls: NULL matrix");
     if (vdt != SPW_F64) return fail(SPW_ERR_UNSUPPORTED, "spw_cgls: binary64 vectors only");
@@ -1248,7 +1319,12 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
     return SPW_OK;
 }
 
-spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, double *out)
+spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist, void *stream)
+{
+    return guarded("spw_cgls", [&] { return spw_cgls_impl(A, vdt, b, x, iters, hist, stream); });
+}
+
+static spw_status spw_round_values_impl(spw_dtype storage, int64_t n, const double *in, double *out)
 {
     if (storage != SPW_F64 && storage != SPW_F32 && storage != SPW_BF16)
         return fail(SPW_ERR_INVALID_ARG, "spw_round_values: bad storage type");
@@ -1259,8 +1335,14 @@ spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, doub
     return SPW_OK;
 }
 
-spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int64_t *n_chunks, int64_t *n_zones,
-                          int64_t *chunk_owned, int64_t *zone_col, int64_t *zone_first, int64_t *zone_last)
+spw_status spw_round_values(spw_dtype storage, int64_t n, const double *in, double *out)
+{
+    return guarded("spw_round_values", [&] { return spw_round_values_impl(storage, n, in, out); });
+}
+
+static spw_status spw_plan_zones_impl(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int64_t *n_chunks,
+                                      int64_t *n_zones, int64_t *chunk_owned, int64_t *zone_col, int64_t *zone_first,
+                                      int64_t *zone_last)
 {
     if (n < 0 || !ptr || chunk_nnz <= 0 || !n_chunks || !n_zones)
         return fail(SPW_ERR_INVALID_ARG, "spw_plan_zones: bad argument");
@@ -1281,6 +1363,14 @@ spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int6
         if (zone_last) zone_last[k] = zp.zone_last[k];
     }
     return SPW_OK;
+}
+
+spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz, int64_t *n_chunks, int64_t *n_zones,
+                          int64_t *chunk_owned, int64_t *zone_col, int64_t *zone_first, int64_t *zone_last)
+{
+    return guarded("spw_plan_zones", [&] {
+        return spw_plan_zones_impl(n, ptr, chunk_nnz, n_chunks, n_zones, chunk_owned, zone_col, zone_first, zone_last);
+    });
 }
 
 }  // extern "C"

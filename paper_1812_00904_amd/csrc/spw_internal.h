@@ -11,7 +11,9 @@
 #pragma once
 
 #include <cstdint>
+#include <exception>
 #include <mutex>
+#include <new>
 #include <string>
 #include <utility>
 #include <vector>
@@ -211,6 +213,26 @@ void profile_end(void *stream, void *token);
 
 // Error text for the calling thread (spw_api.cpp).
 void set_error(const std::string &msg);
+
+// Runs the body of an exported function and turns a C++ exception into a
+// status (host memory exhausted, a thread that cannot start, ...), so that
+// nothing is thrown across the C ABI.
+template <typename F>
+spw_status guarded(const char *fname, F &&body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        try { set_error(std::string(fname) + ": out of host memory"); } catch (...) {}
+        return SPW_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception &e) {
+        try { set_error(std::string(fname) + ": " + e.what()); } catch (...) {}
+        return SPW_ERR_DEVICE;
+    } catch (...) {
+        try { set_error(std::string(fname) + ": unexpected C++ exception"); } catch (...) {}
+        return SPW_ERR_DEVICE;
+    }
+}
 
 // Makes the handle's scratch hold k-wide carries and renumbered inputs (and
 // the one-column partial sums); growing waits for the device (spw_api.cpp).

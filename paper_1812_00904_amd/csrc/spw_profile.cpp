@@ -83,13 +83,18 @@ void profile_end(void *stream, void *token)
 
 extern "C" {
 
-spw_status spw_profile_enable(int32_t on)
+static spw_status spw_profile_enable_impl(int32_t on)
 {
     spw::g_on.store(on != 0);
     return SPW_OK;
 }
 
-spw_status spw_profile_reset(void)
+spw_status spw_profile_enable(int32_t on)
+{
+    return spw::guarded("spw_profile_enable", [&] { return spw_profile_enable_impl(on); });
+}
+
+static spw_status spw_profile_reset_impl(void)
 {
     std::lock_guard<std::mutex> lk(spw::g_mu);
     spw::fold_pending_locked();
@@ -97,7 +102,12 @@ spw_status spw_profile_reset(void)
     return SPW_OK;
 }
 
-spw_status spw_profile_read(spw_profile_entry *entries, int32_t cap, int32_t *count)
+spw_status spw_profile_reset(void)
+{
+    return spw::guarded("spw_profile_reset", [&] { return spw_profile_reset_impl(); });
+}
+
+static spw_status spw_profile_read_impl(spw_profile_entry *entries, int32_t cap, int32_t *count)
 {
     if (!count || (cap > 0 && !entries)) {
         spw::set_error("spw_profile_read: NULL count, or NULL entries with cap > 0");
@@ -117,6 +127,11 @@ spw_status spw_profile_read(spw_profile_entry *entries, int32_t cap, int32_t *co
     }
     *count = i;
     return SPW_OK;
+}
+
+spw_status spw_profile_read(spw_profile_entry *entries, int32_t cap, int32_t *count)
+{
+    return spw::guarded("spw_profile_read", [&] { return spw_profile_read_impl(entries, cap, count); });
 }
 
 }  // extern "C"

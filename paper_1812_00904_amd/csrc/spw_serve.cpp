@@ -185,7 +185,14 @@ void dispatcher_main(spw_server_s *S)
         // launches happen outside the lock; this stream's completer only looks
         // at groups already in its fifo
         int64_t npass = 0;
-        spw_status st = ev ? issue_group(*Am, reqs, slot.stream, &npass) : SPW_ERR_DEVICE;
+        spw_status st = SPW_ERR_DEVICE;
+        if (ev) {
+            try {
+                st = issue_group(*Am, reqs, slot.stream, &npass);
+            } catch (const std::bad_alloc &) {   // the group fails; the server goes on
+                st = SPW_ERR_OUT_OF_MEMORY;
+            }
+        }
         if (ev && hipEventRecord(ev, slot.stream) != hipSuccess) {
             (void)hipGetLastError();
             st = SPW_ERR_DEVICE;
@@ -252,7 +259,7 @@ using namespace spw;
 
 extern "C" {
 
-spw_status spw_serve_opts_default(spw_serve_opts *o)
+static spw_status spw_serve_opts_default_impl(spw_serve_opts *o)
 {
     if (!o) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_opts_default: NULL opts");
     *o = spw_serve_opts{};
@@ -267,7 +274,12 @@ spw_status spw_serve_opts_default(spw_serve_opts *o)
     return SPW_OK;
 }
 
-spw_status spw_serve_create(spw_server *out, const spw_serve_opts *o_in)
+spw_status spw_serve_opts_default(spw_serve_opts *o)
+{
+    return guarded("spw_serve_opts_default", [&] { return spw_serve_opts_default_impl(o); });
+}
+
+static spw_status spw_serve_create_impl(spw_server *out, const spw_serve_opts *o_in)
 {
     if (!out) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_create: NULL out");
     *out = nullptr;
@@ -315,7 +327,12 @@ spw_status spw_serve_create(spw_server *out, const spw_serve_opts *o_in)
     return SPW_OK;
 }
 
-spw_status spw_serve_register(spw_server S, spw_matrix A, int32_t *handle)
+spw_status spw_serve_create(spw_server *out, const spw_serve_opts *o_in)
+{
+    return guarded("spw_serve_create", [&] { return spw_serve_create_impl(out, o_in); });
+}
+
+static spw_status spw_serve_register_impl(spw_server S, spw_matrix A, int32_t *handle)
 {
     if (!S || !A || !handle) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_register: NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -348,7 +365,12 @@ spw_status spw_serve_register(spw_server S, spw_matrix A, int32_t *handle)
     return SPW_OK;
 }
 
-spw_status spw_serve_submit(spw_server S, const spw_request *r, uint64_t *ticket)
+spw_status spw_serve_register(spw_server S, spw_matrix A, int32_t *handle)
+{
+    return guarded("spw_serve_register", [&] { return spw_serve_register_impl(S, A, handle); });
+}
+
+static spw_status spw_serve_submit_impl(spw_server S, const spw_request *r, uint64_t *ticket)
 {
     if (!S || !r || !ticket) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_submit: NULL argument");
     if (r->struct_size != sizeof(spw_request))
@@ -383,13 +405,23 @@ spw_status spw_serve_submit(spw_server S, const spw_request *r, uint64_t *ticket
     return SPW_OK;
 }
 
-spw_status spw_serve_resume(spw_server S)
+spw_status spw_serve_submit(spw_server S, const spw_request *r, uint64_t *ticket)
+{
+    return guarded("spw_serve_submit", [&] { return spw_serve_submit_impl(S, r, ticket); });
+}
+
+static spw_status spw_serve_resume_impl(spw_server S)
 {
     if (!S) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_resume: NULL server");
     std::lock_guard<std::mutex> lk(S->mu);
     S->paused = false;
     S->cv_work.notify_all();
     return SPW_OK;
+}
+
+spw_status spw_serve_resume(spw_server S)
+{
+    return guarded("spw_serve_resume", [&] { return spw_serve_resume_impl(S); });
 }
 
 static spw_status ticket_state(spw_server S, uint64_t ticket, bool *done)
@@ -403,7 +435,7 @@ static spw_status ticket_state(spw_server S, uint64_t ticket, bool *done)
     return SPW_OK;
 }
 
-spw_status spw_serve_poll(spw_server S, uint64_t ticket, int32_t *done)
+static spw_status spw_serve_poll_impl(spw_server S, uint64_t ticket, int32_t *done)
 {
     if (!S || !done) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_poll: NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
@@ -413,7 +445,12 @@ spw_status spw_serve_poll(spw_server S, uint64_t ticket, int32_t *done)
     return st;
 }
 
-spw_status spw_serve_wait(spw_server S, uint64_t ticket, int64_t timeout_us)
+spw_status spw_serve_poll(spw_server S, uint64_t ticket, int32_t *done)
+{
+    return guarded("spw_serve_poll", [&] { return spw_serve_poll_impl(S, ticket, done); });
+}
+
+static spw_status spw_serve_wait_impl(spw_server S, uint64_t ticket, int64_t timeout_us)
 {
     if (!S) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_wait: NULL server");
     std::unique_lock<std::mutex> lk(S->mu);
@@ -429,7 +466,12 @@ spw_status spw_serve_wait(spw_server S, uint64_t ticket, int64_t timeout_us)
     return ticket_state(S, ticket, &d);
 }
 
-spw_status spw_serve_stats(spw_server S, spw_server_stats *o)
+spw_status spw_serve_wait(spw_server S, uint64_t ticket, int64_t timeout_us)
+{
+    return guarded("spw_serve_wait", [&] { return spw_serve_wait_impl(S, ticket, timeout_us); });
+}
+
+static spw_status spw_serve_stats_impl(spw_server S, spw_server_stats *o)
 {
     if (!S || !o) return sfail(SPW_ERR_INVALID_ARG, "spw_serve_stats: NULL argument");
     if (o->struct_size != sizeof(spw_server_stats))
@@ -456,7 +498,12 @@ spw_status spw_serve_stats(spw_server S, spw_server_stats *o)
     return SPW_OK;
 }
 
-spw_status spw_serve_destroy(spw_server S)
+spw_status spw_serve_stats(spw_server S, spw_server_stats *o)
+{
+    return guarded("spw_serve_stats", [&] { return spw_serve_stats_impl(S, o); });
+}
+
+static spw_status spw_serve_destroy_impl(spw_server S)
 {
     if (!S) return SPW_OK;
     {
@@ -478,6 +525,11 @@ spw_status spw_serve_destroy(spw_server S)
     for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
     delete S;
     return SPW_OK;
+}
+
+spw_status spw_serve_destroy(spw_server S)
+{
+    return guarded("spw_serve_destroy", [&] { return spw_serve_destroy_impl(S); });
 }
 
 }  // extern "C"

@@ -248,3 +248,38 @@ def test_canonicalize_still_rejects_out_of_range_before_device_use(spw):
     _expect(spw, "SPW_ERR_BAD_MATRIX", spw.spw_create, spw.SPW_CSC, 3, 2, np.array([0, 3, 5]),
             np.array([2, 0, 2, 1], dtype=np.int32), val, opts)
     assert ctypes.sizeof(spw.CreateOpts) == 60
+
+
+_OOM_CHILD = r'''
+import resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_1812_00904_amd import spw
+spw.load()
+n, m = 200_000, 1000
+ptr = np.arange(0, 150 * (n + 1), 150, dtype=np.int64)
+nnz = int(ptr[-1])
+idx = (np.arange(nnz) % m).astype(np.int32)
+val = np.ones(nnz)
+with open("/proc/self/status") as f:
+    vm = next(int(l.split()[1]) * 1024 for l in f if l.startswith("VmSize"))
+lim = vm + 150 * 2**20          # far less than the canonical copy of 3e7 entries needs
+resource.setrlimit(resource.RLIMIT_AS, (lim, lim))
+try:
+    spw.SpwMatrix(spw.SPW_CSC, m, n, ptr, idx, val, canonicalize=1)
+    print("created")
+except spw.SpwError as e:
+    print(e.status_name)
+'''
+
+
+def test_host_allocation_failure_is_a_status_not_an_abort():
+    # A C++ exception must not cross the C ABI: with the address space capped,
+    # the host copy made by canonicalize fails and the call returns
+    # SPW_ERR_OUT_OF_MEMORY (before any device use) instead of terminating.
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", _OOM_CHILD, root], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "SPW_ERR_OUT_OF_MEMORY", r.stdout
