@@ -354,6 +354,14 @@ __device__ __forceinline__ void buf_store(float x, __amdgpu_buffer_rsrc_t r, uin
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)off, 0, 0);
 }
+// The same with the non-temporal hint (cache policy bit 1 on gfx950), for
+// stores a wave makes to whole consecutive lines: they then do not push the
+// gathered vector out of L2.  Scattered or strided stores must not use it
+// (partial lines written past the cache cost far more).
+__device__ __forceinline__ void buf_store_nt(double x, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(spw_u32x2, x), r, (int)off, 0, 2);
+}
 
 // Segments of one chunk a wave stages in LDS before writing them out; chunks
 // with more segments take the general path.
@@ -410,10 +418,19 @@ __device__ __forceinline__ void vtm_reduce_dense(const double *prod, uint32_t ma
     const __amdgpu_buffer_rsrc_t ub =
         buf_view(u + (int64_t)ci.x * ldu, (uint32_t)((int64_t)nseg * ldu * (int64_t)sizeof(VecT)));
     const uint32_t step_bytes = (uint32_t)(ldu * (int64_t)sizeof(VecT));
-    for (int t = lane; t < nseg; t += WAVE) {
-        const double val = stage[t];
-        const bool to_carry = (t == 0 && first_carry) || (t == nseg - 1 && last_carry);
-        buf_store((VecT)val, ub, to_carry ? BUF_DROP : (uint32_t)t * step_bytes);
+    if (sizeof(VecT) == 8 && ldu == 1) {
+        // contiguous binary64 outputs: 64 lanes write 512 consecutive bytes
+        for (int t = lane; t < nseg; t += WAVE) {
+            const double val = stage[t];
+            const bool to_carry = (t == 0 && first_carry) || (t == nseg - 1 && last_carry);
+            buf_store_nt(val, ub, to_carry ? BUF_DROP : (uint32_t)t * 8u);
+        }
+    } else {
+        for (int t = lane; t < nseg; t += WAVE) {
+            const double val = stage[t];
+            const bool to_carry = (t == 0 && first_carry) || (t == nseg - 1 && last_carry);
+            buf_store((VecT)val, ub, to_carry ? BUF_DROP : (uint32_t)t * step_bytes);
+        }
     }
     if (lane == 0) {
         if (first_carry) carry[(2 * c) * kk + col] = stage[0];
