@@ -161,8 +161,8 @@ def main():
     if args.stats_summary:
         return summarize_stats(args.stats_summary)
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported (the multi-GPU "
-              "sharding is described in DESIGN.md but not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding a matrix "
+              "over several GPUs is not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

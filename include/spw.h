@@ -48,7 +48,7 @@ typedef enum {
     SPW_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
     SPW_ERR_BUDGET = 4,        /* serving: registering or admitting would exceed the HBM budget */
     SPW_ERR_DEVICE = 5,        /* a HIP runtime call or kernel launch failed */
-    SPW_ERR_UNSUPPORTED = 6,   /* valid request this build does not implement (e.g. nnz >= 2^31) */
+    SPW_ERR_UNSUPPORTED = 6,   /* valid request this library version does not implement (e.g. nnz >= 2^31) */
     SPW_ERR_BUSY = 7,          /* serving: queue full; products: the matrix has work in flight on another stream */
     SPW_ERR_TIMEOUT = 8,       /* serving: wait timed out (the request stays queued) */
     SPW_ERR_SHUTDOWN = 9       /* serving: server is shutting down */
@@ -75,7 +75,7 @@ typedef struct spw_matrix_s *spw_matrix;
  *                   (BF16 directly from binary64, no double rounding); a value
  *                   that overflows the storage type is SPW_ERR_BAD_MATRIX.
  *                   Products promote stored values exactly to binary64.
- *   chunk_nnz     : nonzeros per column-dot chunk (0 = automatic; this build
+ *   chunk_nnz     : nonzeros per column-dot chunk (0 = automatic; this version
  *                   supports only its default, 1024).
  *   relabel       : -1 automatic, 0 off, 1 on.  On: rows are renumbered inside
  *                   the library by descending nonzero count, so the most used
@@ -150,7 +150,7 @@ spw_status spw_create_opts_default(spw_create_opts *opts);
  *                   column (0 <= idx < n), strictly increasing inside a row.
  *   ptr[0] == 0, ptr nondecreasing, ptr[last] == nnz.  val has nnz entries.
  *   nnz == 0 is valid (all products are zero); m or n may be 0.
- * Limits of this build: nnz < 2^31, short dimension < 2^31.
+ * Limits of this version: nnz < 2^31, short dimension < 2^31.
  * Errors: SPW_ERR_INVALID_ARG (NULL out/ptr, NULL idx/val with nnz > 0, negative sizes),
  *         SPW_ERR_BAD_MATRIX (validation), SPW_ERR_OUT_OF_MEMORY, SPW_ERR_DEVICE,
  *         SPW_ERR_UNSUPPORTED. */
