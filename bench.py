@@ -22,7 +22,8 @@ batching matrix, and the CPU oracle timed on the host.
 `--pmc-summary DIR` turns rocprofv3 counter output (FETCH_SIZE / WRITE_SIZE
 runs of `--profile-run`) into the traffic summary under profiles/, and
 `--stats-summary DIR` a `rocprofv3 --kernel-trace --stats` run of the main
-benchmark into the kernel statistics summary there.
+benchmark into the kernel statistics summary there, and `--cache-summary DIR`
+a run with the cache and LDS counters (CACHE_COUNTERS) into the cache summary.
 """
 from __future__ import annotations
 
@@ -43,6 +44,9 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
+CACHE_FILE = os.path.join(ROOT, "profiles", "pmc_cache_lds_wide_2e8.txt")
+CACHE_COUNTERS = ("TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum "
+                  "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_WAIT_INST_LDS")
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
                  "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver --no-small")
 
@@ -152,6 +156,8 @@ def main():
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
     ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
                     help="FETCH_SIZE and WRITE_SIZE rocprofv3 output directories -> traffic summary")
+    ap.add_argument("--cache-summary", metavar="DIR",
+                    help="summarize a rocprofv3 --pmc run with CACHE_COUNTERS of --profile-run and exit")
     ap.add_argument("--stats-summary", metavar="DIR",
                     help="rocprofv3 --kernel-trace --stats output directory -> kernel statistics summary")
     args = ap.parse_args()
@@ -160,6 +166,8 @@ def main():
         return summarize_pmc(*args.pmc_summary)
     if args.stats_summary:
         return summarize_stats(args.stats_summary)
+    if args.cache_summary:
+        return summarize_cache(args.cache_summary)
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding a matrix "
               "over several GPUs is not implemented)" % args.gpus, file=sys.stderr)
@@ -822,6 +830,51 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
             out.append("%s_bytes_per_launch=%.0f" % (name, d["FETCH_SIZE"] + d["WRITE_SIZE"]))
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def summarize_cache(pmc_dir: str):
+    """Fold one rocprofv3 --pmc run with CACHE_COUNTERS of a --profile-run into
+    per-launch cache and LDS figures for the product kernels: L2 hit rate,
+    the share of L1 accesses sent on to L2, and LDS bank-conflict cycles
+    against LDS-active cycles."""
+    vals = {}
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                vals.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no counter_collection.csv under %s" % pmc_dir)
+    out = ["# Cache and LDS counters per launch (median over launches), from one rocprofv3 --pmc run of",
+           "# `bench.py --profile-run` on the wide CSC matrix m=50000 n=2e7 nnz=200201679, binary64, k=1",
+           "# command: rocprofv3 --pmc %s -f csv -d <dir> -- python3 bench.py --profile-run ; "
+           "python3 bench.py --cache-summary <dir>" % CACHE_COUNTERS,
+           "kernel_source_sha256_16=%s" % kernel_hash()]
+    counters = CACHE_COUNTERS.split()
+    for name in ("vtm_wave", "mv_bucket", "mv_reduce", "zone_fixup", "gather_vec"):
+        med = {}
+        for c in counters:
+            xs = sorted(v for (k, cn), vs in vals.items() if name in k and (cn == c or cn == c.replace("_sum", ""))
+                        for v in vs)
+            if xs:
+                med[c] = xs[len(xs) // 2]
+        if not med:
+            continue
+        for c in counters:
+            if c in med:
+                out.append("%s_%s=%.0f" % (name, c, med[c]))
+        hit, miss = med.get("TCC_HIT_sum"), med.get("TCC_MISS_sum")
+        if hit is not None and miss is not None and hit + miss > 0:
+            out.append("%s_L2_hit_pct=%.1f" % (name, 100.0 * hit / (hit + miss)))
+        acc, req = med.get("TCP_TOTAL_CACHE_ACCESSES_sum"), med.get("TCP_TCC_READ_REQ_sum")
+        if acc and req is not None:
+            out.append("%s_L1_reads_sent_to_L2_pct=%.1f" % (name, 100.0 * req / acc))
+        bc, act = med.get("SQ_LDS_BANK_CONFLICT"), med.get("SQ_LDS_IDX_ACTIVE")
+        if act and bc is not None:
+            out.append("%s_LDS_bank_conflict_pct_of_active=%.1f" % (name, 100.0 * bc / act))
+    os.makedirs(os.path.dirname(CACHE_FILE), exist_ok=True)
+    with open(CACHE_FILE, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 
