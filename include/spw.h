@@ -224,8 +224,11 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
  * alpha = gamma_k / ||q||^2, x += alpha p_k, r -= alpha q, s = A^T r,
  * gamma_{k+1} = ||s||^2, p_{k+1} = s + (gamma_{k+1} / gamma_k) p_k.  A step
  * whose denominator is exactly zero (the iterate already solves the normal
- * equations) has size zero.  Inner products are summed in a fixed order, so a
- * call is bit-identical from run to run.
+ * equations) has size zero.  The product with A is taken of s_k and q = A p_k
+ * formed by linearity, q_k = A s_k + beta_k q_{k-1} (equal in exact
+ * arithmetic), so that the update of p and x can run before the product with
+ * A^T.  Inner products are summed in a fixed order, so a call is bit-identical
+ * from run to run.
  *   vdt   : SPW_F64 (SPW_ERR_UNSUPPORTED otherwise)
  *   b     : device, m binary64 entries (not written)
  *   x     : device, n binary64 entries: x_0 on entry, x_iters when the stream

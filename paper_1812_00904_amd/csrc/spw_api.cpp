@@ -763,6 +763,7 @@ spw_status grow_cgls(spw_matrix_s &A, int64_t hist_len)
     if (!W.r) {
         if ((st = dev_alloc(A, &W.r, std::max<int64_t>(A.m, 1), "CGLS r"))) return st;
         if ((st = dev_alloc(A, &W.q, std::max<int64_t>(A.m, 1), "CGLS q"))) return st;
+        if ((st = dev_alloc(A, &W.t, std::max<int64_t>(A.m, 1), "CGLS t"))) return st;
         if ((st = dev_alloc(A, &W.s, std::max<int64_t>(A.n, 1), "CGLS s"))) return st;
         if ((st = dev_alloc(A, &W.p, std::max<int64_t>(A.n, 1), "CGLS p"))) return st;
         if ((st = dev_alloc(A, &W.partial, cgls_dot_parts(), "CGLS partial sums"))) return st;
@@ -1278,6 +1279,7 @@ static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void
     w.x = (double *)x;
     w.r = W.r;
     w.q = W.q;
+    w.t = W.t;
     w.s = W.s;
     w.p = W.p;
     w.partial = W.partial;
@@ -1290,23 +1292,27 @@ static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void
                                                hipGetErrorString((hipError_t)e));
         return SPW_OK;
     };
-    auto iteration = [&]() -> spw_status {
+    // one iteration k: t = A s_k, q_k = t + beta_k q_{k-1} (= A p_k), alpha_k, r_{k+1};
+    // p_k = s_k + beta_k p_{k-1}, x_{k+1} = x_k + alpha_k p_k; s_{k+1} = A^T r_{k+1}, gamma_{k+1},
+    // beta_{k+1}.  The first iteration takes q_0 = t and p_0 = s_0.
+    auto iteration = [&](bool first) -> spw_status {
         spw_status s2;
-        if ((s2 = run_product(A, true, SPW_F64, 1, w.p, 1, w.q, 1, stream, "spw_cgls"))) return s2;   // q = A p
-        if ((s2 = vec(CglsVecOp::ALPHA_R))) return s2;
+        if ((s2 = run_product(A, true, SPW_F64, 1, w.s, 1, w.t, 1, stream, "spw_cgls"))) return s2;   // t = A s
+        if ((s2 = vec(first ? CglsVecOp::ALPHA_R0 : CglsVecOp::ALPHA_R))) return s2;
+        if ((s2 = vec(first ? CglsVecOp::PX0 : CglsVecOp::PX))) return s2;
         if ((s2 = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return s2;  // s = A^T r
-        return vec(CglsVecOp::BETA_XP);
+        return vec(CglsVecOp::GAMMA);
     };
-    // r_0 = b - A x_0, s_0 = A^T r_0, gamma_0 = ||s_0||^2, p_0 = s_0
+    // r_0 = b - A x_0, s_0 = A^T r_0, gamma_0 = ||s_0||^2
     if ((st = run_product(A, true, SPW_F64, 1, x, 1, w.q, 1, stream, "spw_cgls"))) return st;
     if ((st = vec(CglsVecOp::R_INIT))) return st;
     if ((st = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return st;
     if ((st = vec(CglsVecOp::GAMMA0))) return st;
-    // Every iteration launches the same kernels with the same arguments (the
-    // history index lives on the device), so a caller may capture a whole
-    // call without a history in a graph and replay it.
+    // Every iteration after the first launches the same kernels with the same
+    // arguments (the history index lives on the device), so a caller may
+    // capture a whole call without a history in a graph and replay it.
     for (int64_t k = 1; k <= iters; ++k)
-        if ((st = iteration())) return st;
+        if ((st = iteration(k == 1))) return st;
     if ((st = release_stream(*A, stream, "spw_cgls"))) return st;
     if (hist) {
         if (hipMemcpyAsync(hist, W.hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) !=

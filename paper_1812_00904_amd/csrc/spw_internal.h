@@ -79,7 +79,7 @@ struct ColDot {
 
 // Workspace of the CGLS loop (allocated on its first call, kept until destroy).
 struct CglsScratch {
-    double *r = nullptr, *q = nullptr;        // m entries each
+    double *r = nullptr, *q = nullptr, *t = nullptr;   // m entries each
     double *s = nullptr, *p = nullptr;        // n entries each
     double *partial = nullptr;                // partial sums of one inner product
     double *scal = nullptr;                   // gamma, alpha, beta
@@ -192,14 +192,21 @@ int device_cu_count(int device);
 struct CglsWork {
     int64_t m = 0, n = 0;
     const double *b = nullptr;
-    double *x = nullptr, *r = nullptr, *q = nullptr, *s = nullptr, *p = nullptr;
+    double *x = nullptr, *r = nullptr, *q = nullptr, *t = nullptr, *s = nullptr, *p = nullptr;
     double *partial = nullptr, *scal = nullptr, *hist_gamma = nullptr, *hist_rho = nullptr;
 };
+// The steps around the two products of a CGLS iteration.  An iteration takes
+// t = A s (s = A^T r of the previous step) and forms q = A p by linearity,
+// q = t + beta q, so that the long vector update (p, then x) runs just before
+// the A^T r product rather than just before the A p product.
 enum class CglsVecOp : int {
-    R_INIT,    // r = b - q (q = A x_0); rho_k = ||r||^2
-    GAMMA0,    // gamma_0 = ||s||^2 (s = A^T r_0); p = s
-    ALPHA_R,   // alpha = gamma / ||q||^2 (q = A p); r = r - alpha q; rho_k = ||r||^2
-    BETA_XP    // gamma_k = ||s||^2 (s = A^T r); beta = gamma_k / gamma_{k-1}; x = x + alpha p; p = s + beta p
+    R_INIT,      // r = b - q (q = A x_0); rho_0 = ||r||^2
+    GAMMA0,      // gamma_0 = ||s||^2 (s = A^T r_0)
+    ALPHA_R0,    // first iteration: q = t; alpha = gamma / ||q||^2; r = r - alpha q; rho_k = ||r||^2
+    ALPHA_R,     // q = t + beta q; alpha = gamma / ||q||^2; r = r - alpha q; rho_k = ||r||^2
+    PX0,         // first iteration: p = s; x = x + alpha p
+    PX,          // p = s + beta p; x = x + alpha p
+    GAMMA        // gamma_k = ||s||^2 (s = A^T r); beta = gamma_k / gamma_{k-1}
 };
 // The history index advances on the device (see spw_solve.hip), so the
 // launches of one iteration are the same every time.

@@ -1,7 +1,13 @@
 // Vector kernels of the CGLS loop (conjugate gradients on min ||b - A x||_2),
 // the first-order use of the two products that the paper's closing section
-// describes: each iteration is one A p, one A^T r, and a few passes of vector
-// updates and inner products, which this file fuses.
+// describes: each iteration is one product with A, one with A^T, and a few
+// passes of vector updates and inner products, which this file fuses.
+//
+// The product with A is taken of s = A^T r, and q = A p is formed from it by
+// linearity (p = s + beta p, so q = A s + beta q).  This leaves the update of
+// the two long vectors (p, then x) free to run right before the A^T r product,
+// whose scattered gathers leave memory bandwidth to spare for writing them
+// back, instead of right before the A p product, whose streaming they slowed.
 //
 // Every inner product is formed in a fixed order, so a solve is bit-identical
 // from run to run: DOT_PARTS workgroups each sum a fixed contiguous range
@@ -61,6 +67,26 @@ __global__ __launch_bounds__(SV_BLOCK) void sq_part(const double *__restrict__ a
     for (int64_t i = s + threadIdx.x; i < e; i += SV_BLOCK) acc += a[i] * a[i];
     const double t = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+// FIRST: q = t.  Otherwise q = t + beta q.  Either way partial[g] = sum of
+// q_i * q_i of the new q over workgroup g's range.
+template <bool FIRST>
+__global__ __launch_bounds__(SV_BLOCK) void q_step(double *__restrict__ q, const double *__restrict__ t, int64_t len,
+                                                   const double *__restrict__ scal, double *__restrict__ partial)
+{
+    __shared__ double lds[SV_BLOCK / SV_WAVE];
+    const double beta = FIRST ? 0.0 : scal[S_BETA];
+    int64_t s, e;
+    part_range(len, s, e);
+    double acc = 0.0;
+    for (int64_t i = s + threadIdx.x; i < e; i += SV_BLOCK) {
+        const double qi = FIRST ? t[i] : t[i] + beta * q[i];
+        q[i] = qi;
+        acc += qi * qi;
+    }
+    const double sum = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
 }
 
 // INIT: r = b - q.  UPDATE: r = r - alpha q.  Either way partial[g] = sum of
@@ -128,26 +154,20 @@ __global__ __launch_bounds__(SV_BLOCK) void scalar_step(const double *__restrict
     }
 }
 
-// x = x + alpha p, then p = s + beta p (with the p the x update used): one
+// p = s + beta p (FIRST: p = s), then x = x + alpha p with the new p: one
 // pass over the three long vectors.
-__global__ __launch_bounds__(SV_BLOCK) void xp_step(double *__restrict__ x, double *__restrict__ p,
+template <bool FIRST>
+__global__ __launch_bounds__(SV_BLOCK) void px_step(double *__restrict__ x, double *__restrict__ p,
                                                     const double *__restrict__ s, int64_t len,
                                                     const double *__restrict__ scal)
 {
-    const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
+    const double alpha = scal[S_ALPHA], beta = FIRST ? 0.0 : scal[S_BETA];
     const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
     for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) {
-        const double pi = p[i];
+        const double pi = FIRST ? s[i] : s[i] + beta * p[i];
+        p[i] = pi;
         x[i] = x[i] + alpha * pi;
-        p[i] = s[i] + beta * pi;
     }
-}
-
-__global__ __launch_bounds__(SV_BLOCK) void copy_vec(const double *__restrict__ a, double *__restrict__ b,
-                                                     int64_t len)
-{
-    const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
-    for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) b[i] = a[i];
 }
 
 unsigned stream_grid(int64_t len)
@@ -163,31 +183,38 @@ int64_t cgls_dot_parts() { return DOT_PARTS; }
 int launch_cgls_vec(CglsVecOp op, const CglsWork &w, void *stream)
 {
     hipStream_t st = (hipStream_t)stream;
+    auto scalar = [&](ScalarOp sop) {
+        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)sop, w.scal, w.hist_gamma,
+                           w.hist_rho);
+    };
     switch (op) {
-    case CglsVecOp::R_INIT:   // r = b - q, rho_0
+    case CglsVecOp::R_INIT:     // r = b - q, rho_0
         hipLaunchKernelGGL(r_step<true>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO0, w.scal, w.hist_gamma,
-                           w.hist_rho);
+        scalar(OP_RHO0);
         break;
-    case CglsVecOp::GAMMA0:   // gamma_0 = ||s||^2, p = s
+    case CglsVecOp::GAMMA0:     // gamma_0 = ||s||^2
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA0, w.scal, w.hist_gamma,
-                           w.hist_rho);
-        hipLaunchKernelGGL(copy_vec, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.s, w.p, w.n);
+        scalar(OP_GAMMA0);
         break;
-    case CglsVecOp::ALPHA_R:  // alpha = gamma / ||q||^2, r = r - alpha q, rho_k
-        hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.q, w.m, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_ALPHA, w.scal, w.hist_gamma,
-                           w.hist_rho);
+    case CglsVecOp::ALPHA_R0:   // q = t, alpha = gamma / ||q||^2, r = r - alpha q, rho_k
+    case CglsVecOp::ALPHA_R:    // q = t + beta q, the same
+        if (op == CglsVecOp::ALPHA_R0)
+            hipLaunchKernelGGL(q_step<true>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.q, w.t, w.m, w.scal, w.partial);
+        else
+            hipLaunchKernelGGL(q_step<false>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.q, w.t, w.m, w.scal, w.partial);
+        scalar(OP_ALPHA);
         hipLaunchKernelGGL(r_step<false>, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.r, w.b, w.q, w.m, w.scal, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_RHO, w.scal, w.hist_gamma,
-                           w.hist_rho);
+        scalar(OP_RHO);
         break;
-    case CglsVecOp::BETA_XP:  // gamma_k = ||s||^2, beta, x += alpha p, p = s + beta p
+    case CglsVecOp::PX0:        // p = s, x = x + alpha p
+        hipLaunchKernelGGL(px_step<true>, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
+        break;
+    case CglsVecOp::PX:         // p = s + beta p, x = x + alpha p
+        hipLaunchKernelGGL(px_step<false>, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
+        break;
+    case CglsVecOp::GAMMA:      // gamma_k = ||s||^2, beta
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);
-        hipLaunchKernelGGL(scalar_step, dim3(1), dim3(SV_BLOCK), 0, st, w.partial, (int)OP_GAMMA, w.scal, w.hist_gamma,
-                           w.hist_rho);
-        hipLaunchKernelGGL(xp_step, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
+        scalar(OP_GAMMA);
         break;
     }
     return (int)hipGetLastError();
