@@ -12,7 +12,10 @@ bandwidth of that pair under the algorithmic byte model
 (8-byte values, 4-byte indices and pointers), divided by the measured time.
 Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line.  Also reports, outside the timed steps: the tall mirror
+Prints one JSON line.  The timed steps take four different x and v in turn
+(4 x 160 MB of x), so that no input stays in the 256 MB Infinity Cache from
+one step to the next; the rate with one fixed x and v is reported beside it.
+Also reports, outside the timed steps: the tall mirror
 (the same arrays read as a 2e7 x 50,000 CSR matrix), per-kernel roofline
 figures, plain-call latency percentiles, reduced-precision value storage on
 the same matrix (binary32 / bfloat16 values, binary32 vectors, with their
@@ -41,6 +44,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+NROT = 4          # input vectors the timed pairs rotate through
 KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
@@ -106,10 +110,16 @@ def cpu_baseline(A, x, v, budget_s: float = 20.0):
 
 
 def time_pairs(M, xd, vd, yd, ud, steps, warmup):
+    """Event-timed y=Ax / u^T=v^T A pairs.  xd and vd may be lists of vectors,
+    which step i takes in turn (i mod len): inputs whose total exceeds the
+    256 MB Infinity Cache are then read from HBM on every step, as they are in
+    a solver whose vectors change from step to step."""
     import torch
-    for _ in range(warmup):
-        M.mv(xd, yd)
-        M.vtm(vd, ud)
+    xs = xd if isinstance(xd, (list, tuple)) else [xd]
+    vs = vd if isinstance(vd, (list, tuple)) else [vd]
+    for i in range(warmup):
+        M.mv(xs[i % len(xs)], yd)
+        M.vtm(vs[i % len(vs)], ud)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
            torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -121,9 +131,9 @@ def time_pairs(M, xd, vd, yd, ud, steps, warmup):
     for i in range(steps):
         a, b, c = ev[i]
         a.record()
-        M.mv(xd, yd)
+        M.mv(xs[i % len(xs)], yd)
         b.record()
-        M.vtm(vd, ud)
+        M.vtm(vs[i % len(vs)], ud)
         c.record()
     stop.record()
     torch.cuda.synchronize()
@@ -213,12 +223,18 @@ def main():
         print("[bench] profile run done", file=sys.stderr, flush=True)
         return
 
+    # the timed pairs take four different x and v in turn (4 x 160 MB of x), so
+    # that no input stays in the Infinity Cache from one step to the next
+    xrot = [xd] + [xd * (1.0 + 0.25 * i) for i in range(1, NROT)]
+    vrot = [vd] + [vd * (1.0 + 0.25 * i) for i in range(1, NROT)]
     spw_profile_reset()
     spw_profile_enable(True)
-    total_ms, wall, mv_ms, vtm_ms = time_pairs(M, xd, vd, yd, ud, args.steps, args.warmup)
+    total_ms, wall, mv_ms, vtm_ms = time_pairs(M, xrot, vrot, yd, ud, args.steps, args.warmup)
     spw_profile_enable(False)
     prof = spw_profile_read()
     spw_profile_reset()
+    same_ms, _, _, _ = time_pairs(M, xd, vd, yd, ud, args.steps, 2)
+    del xrot, vrot
     ms_per_step = total_ms / args.steps
     pair_bytes = 2 * model_bytes(A.m, A.n, A.nnz)
     value = pair_bytes / (ms_per_step * 1e-3) / 1e9
@@ -254,18 +270,21 @@ def main():
              "vtm_GBps": round(one_op / (percentile(vtm_ms, 50) * 1e-3) / 1e9, 1),
              "plan": {k: info[k] for k in ("n_chunks", "n_zones", "n_panels", "panel_rows", "mv_workgroups",
                                           "index_bytes", "relabeled", "device_bytes")},
-             "generate_s": round(gen_s, 2), "create_s": round(create_s, 2)}
+             "generate_s": round(gen_s, 2), "create_s": round(create_s, 2),
+             "inputs": "%d different x and v taken in turn" % NROT,
+             "pair_same_vectors_GBps": round(pair_bytes / (same_ms / args.steps * 1e-3) / 1e9, 1)}
     if traffic:
         extra["traffic_summary"] = os.path.relpath(TRAFFIC_FILE, ROOT)
 
     if not args.no_tall:
         # the tall mirror: the same arrays as CSR of the n x m transpose
         T = SpwMatrix(SPW_CSR, A.n, A.m, A.ptr, A.idx, A.val)
-        xt = vd          # tall x has m_tall' = 50,000 ... entries: the short side
+        xt = vd          # the tall x has the short side's 50,000 entries
         yt = torch.empty(A.n, dtype=torch.float64, device=dev)
-        vt = xd
+        vt = [xd] + [xd * (1.0 + 0.25 * i) for i in range(1, NROT)]   # the long v, taken in turn
         ut = torch.empty(A.m, dtype=torch.float64, device=dev)
         tot, _, tmv, tvtm = time_pairs(T, xt, vt, yt, ut, max(args.steps // 2, 5), 2)
+        del vt
         extra["tall"] = {"workload": "CSR m=%d n=%d (same arrays)" % (A.n, A.m),
                          "pair_GBps": round(pair_bytes / (tot / max(args.steps // 2, 5) * 1e-3) / 1e9, 1),
                          "mv_GBps": round(one_op / (percentile(tmv, 50) * 1e-3) / 1e9, 1),
@@ -892,7 +911,8 @@ def summarize_stats(stats_dir: str):
                          float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     rows.sort(key=lambda t: -t[5])
     out = ["# rocprofv3 kernel statistics for one benchmark run on the wide CSC matrix m=50000 n=2e7",
-           "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs.",
+           "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs on 4",
+           "# rotating x and v, then 2 + 20 pairs on one x and v.",
            "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND,
            "kernel_source_sha256_16=%s" % kernel_hash(),
            "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
