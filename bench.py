@@ -53,6 +53,9 @@ CACHE_COUNTERS = ("TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC
                   "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_WAIT_INST_LDS")
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
                  "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver --no-small")
+SOLVER_STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_cgls_wide_2e8.txt")
+SOLVER_STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 3 --warmup 1 "
+                        "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-small")
 
 
 def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, si: int = 4, sp: int = 4) -> int:
@@ -168,6 +171,8 @@ def main():
                     help="FETCH_SIZE and WRITE_SIZE rocprofv3 output directories -> traffic summary")
     ap.add_argument("--cache-summary", metavar="DIR",
                     help="summarize a rocprofv3 --pmc run with CACHE_COUNTERS of --profile-run and exit")
+    ap.add_argument("--solver-stats-summary", metavar="DIR",
+                    help="summarize a rocprofv3 --kernel-trace --stats run of SOLVER_STATS_COMMAND and exit")
     ap.add_argument("--stats-summary", metavar="DIR",
                     help="rocprofv3 --kernel-trace --stats output directory -> kernel statistics summary")
     args = ap.parse_args()
@@ -176,6 +181,8 @@ def main():
         return summarize_pmc(*args.pmc_summary)
     if args.stats_summary:
         return summarize_stats(args.stats_summary)
+    if args.solver_stats_summary:
+        return summarize_stats(args.solver_stats_summary, solver=True)
     if args.cache_summary:
         return summarize_cache(args.cache_summary)
     if args.gpus != 1:
@@ -481,9 +488,9 @@ def bench_solver(args, A, M, bd, pair_ms):
     """CGLS on the same matrix (spw_cgls, binary64): time per iteration from a
     K-iteration and a 0-iteration call (the difference removes the start-up
     product pair), against the plain product pair.  Byte model per iteration:
-    the two products plus the vector passes (||q||^2 and r -= alpha q on the
-    m-vectors: 32 m bytes; ||s||^2, then x += alpha p and p = s + beta p on the
-    n-vectors: 48 n bytes)."""
+    the two products plus the vector passes (q = t + beta q with ||q||^2, and
+    r -= alpha q, on the m-vectors: 48 m bytes; ||s||^2, then p = s + beta p
+    and x += alpha p on the n-vectors: 48 n bytes)."""
     import numpy as np
     import torch
     K = max(args.solver_iters, 1)
@@ -507,7 +514,7 @@ def bench_solver(args, A, M, bd, pair_ms):
     it_ms = (tk - t0) / K
     x.zero_()
     gamma, rho = M.cgls(bd, x, K)
-    by = 2 * model_bytes(A.m, A.n, A.nnz) + 32 * A.m + 48 * A.n
+    by = 2 * model_bytes(A.m, A.n, A.nnz) + 48 * A.m + 48 * A.n
     res = {"workload": "CGLS, min ||b - A x||_2 on the same matrix, x0 = 0, binary64",
            "iterations": K, "ms_per_iteration": round(it_ms, 4), "pair_ms": round(pair_ms, 4),
            "vector_overhead_pct": round(100.0 * (it_ms - pair_ms) / pair_ms, 1),
@@ -898,9 +905,10 @@ def summarize_cache(pmc_dir: str):
     print("\n".join(out))
 
 
-def summarize_stats(stats_dir: str):
+def summarize_stats(stats_dir: str, solver: bool = False):
     """Fold the kernel_stats.csv of a `rocprofv3 --kernel-trace --stats` run of
-    the main benchmark (STATS_COMMAND) into the kernel statistics summary."""
+    the main benchmark (STATS_COMMAND), or of the run that adds the solver
+    section (SOLVER_STATS_COMMAND), into its kernel statistics summary."""
     files = glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True)
     if not files:
         raise SystemExit("no kernel_stats.csv under %s" % stats_dir)
@@ -910,17 +918,23 @@ def summarize_stats(stats_dir: str):
             rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
                          float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     rows.sort(key=lambda t: -t[5])
-    out = ["# rocprofv3 kernel statistics for one benchmark run on the wide CSC matrix m=50000 n=2e7",
-           "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs on 4",
-           "# rotating x and v, then 2 + 20 pairs on one x and v.",
-           "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND,
-           "kernel_source_sha256_16=%s" % kernel_hash(),
-           "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
+    if solver:
+        head = ["# rocprofv3 kernel statistics for the CGLS loop on the wide CSC matrix m=50000 n=2e7",
+                "# nnz=200201679, binary64: 1 + 3 pairs on rotating x and v and 2 + 3 on one x and v, then",
+                "# spw_cgls calls of 2, 3 x 0, 4 x 20 iterations (about 90 of the 99 product pairs are the loop's).",
+                "# command: %s ; python3 bench.py --solver-stats-summary <dir>" % SOLVER_STATS_COMMAND]
+    else:
+        head = ["# rocprofv3 kernel statistics for one benchmark run on the wide CSC matrix m=50000 n=2e7",
+                "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs on 4",
+                "# rotating x and v, then 2 + 20 pairs on one x and v.",
+                "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND]
+    out = head + ["kernel_source_sha256_16=%s" % kernel_hash(),
+                  "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
     for name, calls, avg, mn, mx, pct in rows:
         short = name.replace("spw::(anonymous namespace)::", "").replace("void ", "")
         short = short.split("(")[0][:56]
         out.append("%-56s %5d %10.2f %10.2f %10.2f %7.2f%%" % (short, calls, avg, mn, mx, pct))
-    with open(STATS_FILE, "w") as f:
+    with open(SOLVER_STATS_FILE if solver else STATS_FILE, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 
