@@ -56,7 +56,9 @@ __device__ __forceinline__ void part_range(int64_t len, int64_t &a, int64_t &e)
     e = len * ((int64_t)blockIdx.x + 1) / DOT_PARTS;
 }
 
-// partial[g] = sum over workgroup g's range of a_i * a_i.
+// partial[g] = sum over workgroup g's range of a_i * a_i.  Eight loads are
+// issued before their squares are added (in the same order as one at a time),
+// so that more bytes are in flight.
 __global__ __launch_bounds__(SV_BLOCK) void sq_part(const double *__restrict__ a, int64_t len,
                                                     double *__restrict__ partial)
 {
@@ -64,7 +66,15 @@ __global__ __launch_bounds__(SV_BLOCK) void sq_part(const double *__restrict__ a
     int64_t s, e;
     part_range(len, s, e);
     double acc = 0.0;
-    for (int64_t i = s + threadIdx.x; i < e; i += SV_BLOCK) acc += a[i] * a[i];
+    int64_t i = s + threadIdx.x;
+    for (; i + 7 * SV_BLOCK < e; i += 8 * SV_BLOCK) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = a[i + u * SV_BLOCK];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += t[u] * t[u];
+    }
+    for (; i < e; i += SV_BLOCK) acc += a[i] * a[i];
     const double t = block_sum(acc, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
