@@ -112,11 +112,13 @@ def cpu_baseline(A, x, v, budget_s: float = 20.0):
                       "median pair %.3f s" % (len(t_pairs), A.nnz, t_med)}
 
 
-def time_pairs(M, xd, vd, yd, ud, steps, warmup):
+def time_pairs(M, xd, vd, yd, ud, steps, warmup, per_step=True):
     """Event-timed y=Ax / u^T=v^T A pairs.  xd and vd may be lists of vectors,
     which step i takes in turn (i mod len): inputs whose total exceeds the
     256 MB Infinity Cache are then read from HBM on every step, as they are in
-    a solver whose vectors change from step to step."""
+    a solver whose vectors change from step to step.  per_step adds events
+    around each product (for latency percentiles), which cost time of their
+    own; without it only the whole loop is bracketed."""
     import torch
     xs = xd if isinstance(xd, (list, tuple)) else [xd]
     vs = vd if isinstance(vd, (list, tuple)) else [vd]
@@ -125,19 +127,21 @@ def time_pairs(M, xd, vd, yd, ud, steps, warmup):
         M.vtm(vs[i % len(vs)], ud)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
-           torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+           torch.cuda.Event(enable_timing=True)) for _ in range(steps if per_step else 0)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
     for i in range(steps):
-        a, b, c = ev[i]
-        a.record()
+        if per_step:
+            ev[i][0].record()
         M.mv(xs[i % len(xs)], yd)
-        b.record()
+        if per_step:
+            ev[i][1].record()
         M.vtm(vs[i % len(vs)], ud)
-        c.record()
+        if per_step:
+            ev[i][2].record()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -195,7 +199,7 @@ def main():
 
     import synth
     from paper_1812_00904_amd import SPW_CSC, SPW_CSR, SpwMatrix, spw_profile_enable, spw_profile_read, \
-        spw_profile_reset
+        spw_profile_reset, spw_profile_select
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -234,13 +238,26 @@ def main():
     # that no input stays in the Infinity Cache from one step to the next
     xrot = [xd] + [xd * (1.0 + 0.25 * i) for i in range(1, NROT)]
     vrot = [vd] + [vd * (1.0 + 0.25 * i) for i in range(1, NROT)]
+    # 1. a profiled pass with events around every kernel and every product:
+    #    per-kernel figures, latency percentiles, and the dominant kernel
     spw_profile_reset()
+    spw_profile_select(None)
     spw_profile_enable(True)
-    total_ms, wall, mv_ms, vtm_ms = time_pairs(M, xrot, vrot, yd, ud, args.steps, args.warmup)
+    _, _, mv_ms, vtm_ms = time_pairs(M, xrot, vrot, yd, ud, args.steps, args.warmup)
     spw_profile_enable(False)
     prof = spw_profile_read()
     spw_profile_reset()
-    same_ms, _, _, _ = time_pairs(M, xd, vd, yd, ud, args.steps, 2)
+    dom = max(("mv_bucket", "vtm_wave"), key=lambda k: prof.get(k, (1, 0.0))[1] / max(prof.get(k, (1, 0.0))[0], 1))
+    # 2. the timed steps: events only around the dominant kernel's launches
+    spw_profile_select(dom)
+    spw_profile_enable(True)
+    total_ms, wall, _, _ = time_pairs(M, xrot, vrot, yd, ud, args.steps, 2, per_step=False)
+    spw_profile_enable(False)
+    prof_dom = spw_profile_read()
+    spw_profile_reset()
+    spw_profile_select(None)
+    # 3. the same with one fixed x and v, no events
+    same_ms, _, _, _ = time_pairs(M, xd, vd, yd, ud, args.steps, 2, per_step=False)
     del xrot, vrot
     ms_per_step = total_ms / args.steps
     pair_bytes = 2 * model_bytes(A.m, A.n, A.nnz)
@@ -259,17 +276,19 @@ def main():
             gbs = one_op / (kernels[name]["avg_us"] * 1e-6) / 1e9
             kernels[name]["achieved_GBps"] = round(gbs, 1)
             kernels[name]["op"] = op
-    dom = max(("mv_bucket", "vtm_wave"), key=lambda k: kernels.get(k, {}).get("avg_us", 0.0))
     traffic = read_traffic()
     tr_val = None
     if traffic and ("%s_bytes_per_launch" % dom) in traffic:
         tr_val = float(traffic["%s_bytes_per_launch" % dom])
-    achieved = kernels[dom]["achieved_GBps"]
+    launches, tot = prof_dom[dom]
+    dom_us = tot / max(launches, 1) * 1e3
+    achieved = round(one_op / (dom_us * 1e-6) / 1e9, 1)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr_val,
-                "algorithmic_bytes_per_launch": one_op}
+                "algorithmic_bytes_per_launch": one_op, "avg_launch_us": round(dom_us, 2),
+                "launches_timed": launches}
 
-    extra = {"kernels": kernels,
+    extra = {"kernels": kernels, "kernels_from": "a profiled pass of the same steps before the timed one",
              "latency_ms": {"mv_p50": round(percentile(mv_ms, 50), 4), "mv_p99": round(percentile(mv_ms, 99), 4),
                             "vtm_p50": round(percentile(vtm_ms, 50), 4),
                             "vtm_p99": round(percentile(vtm_ms, 99), 4)},
@@ -920,13 +939,13 @@ def summarize_stats(stats_dir: str, solver: bool = False):
     rows.sort(key=lambda t: -t[5])
     if solver:
         head = ["# rocprofv3 kernel statistics for the CGLS loop on the wide CSC matrix m=50000 n=2e7",
-                "# nnz=200201679, binary64: 1 + 3 pairs on rotating x and v and 2 + 3 on one x and v, then",
-                "# spw_cgls calls of 2, 3 x 0, 4 x 20 iterations (about 90 of the 99 product pairs are the loop's).",
+                "# nnz=200201679, binary64: 1 + 3 profiled and 2 + 3 timed pairs on rotating x and v, 2 + 3 on one",
+                "# x and v, then spw_cgls calls of 2, 3 x 0, 4 x 20 iterations (90 of the 104 product pairs).",
                 "# command: %s ; python3 bench.py --solver-stats-summary <dir>" % SOLVER_STATS_COMMAND]
     else:
         head = ["# rocprofv3 kernel statistics for one benchmark run on the wide CSC matrix m=50000 n=2e7",
-                "# nnz=200201679, binary64 values and vectors: 3 warm-up + 20 timed y=Ax / u^T=v^T A pairs on 4",
-                "# rotating x and v, then 2 + 20 pairs on one x and v.",
+                "# nnz=200201679, binary64 values and vectors, y=Ax / u^T=v^T A pairs on 4 rotating x and v:",
+                "# 3 + 20 profiled, 2 + 20 timed; then 2 + 20 on one x and v.",
                 "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND]
     out = head + ["kernel_source_sha256_16=%s" % kernel_hash(),
                   "# columns: kernel | calls | average us | min us | max us | share of GPU time"]

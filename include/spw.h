@@ -362,6 +362,11 @@ spw_status spw_plan_zones(int64_t n, const int64_t *ptr, int64_t chunk_nnz,
  * name, the launch count and total milliseconds of the launches completed
  * since the last reset (it synchronizes those events).  Off by default. */
 spw_status spw_profile_enable(int32_t on);
+/* Restricts the timing to kernels whose name begins with `prefix` (for
+ * example "vtm_wave"), so that the events of the other launches do not slow
+ * a timed loop; NULL or "" times every launch (the default).  The prefix is
+ * copied. */
+spw_status spw_profile_select(const char *prefix);
 spw_status spw_profile_reset(void);
 /* Fills up to `cap` entries; *count receives the number of distinct kernels. */
 typedef struct {

@@ -8,10 +8,12 @@ from .spw import (SPW_CSC, SPW_CSR, SPW_F64, SPW_F32, SPW_BF16, SPW_OP_MV, SPW_O
                   SPW_PART_COLUMN, Server, SpwError,
                   SpwMatrix, create_opts, load,
                   spw_create, spw_create_coo, spw_destroy, spw_info, spw_mv, spw_vtm, spw_mv_batch, spw_vtm_batch, spw_cgls,
-                  spw_plan_zones, spw_round_values, spw_profile_enable, spw_profile_reset, spw_profile_read)
+                  spw_plan_zones, spw_round_values, spw_profile_enable, spw_profile_select,
+                  spw_profile_reset, spw_profile_read)
 
 __all__ = ["SPW_CSC", "SPW_CSR", "SPW_F64", "SPW_F32", "SPW_BF16", "SPW_OP_MV", "SPW_OP_VTM", "SPW_PART_NONZERO",
            "SPW_PART_COLUMN", "Server",
            "SpwError", "SpwMatrix", "create_opts",
            "load", "spw_create", "spw_destroy", "spw_info", "spw_mv", "spw_vtm", "spw_mv_batch",
-           "spw_vtm_batch", "spw_create_coo", "spw_cgls", "spw_plan_zones", "spw_round_values", "spw_profile_enable", "spw_profile_reset", "spw_profile_read"]
+           "spw_vtm_batch", "spw_create_coo", "spw_cgls", "spw_plan_zones", "spw_round_values", "spw_profile_enable", "spw_profile_select",
+           "spw_profile_reset", "spw_profile_read"]

@@ -21,6 +21,7 @@ struct Rec {
 
 std::atomic<bool> g_on{false};
 std::mutex g_mu;
+std::string g_select;          // time only kernels whose name begins with this (empty: all)
 std::vector<Rec> g_pending;
 std::vector<hipEvent_t> g_pool;
 std::map<std::string, std::pair<int64_t, double>> g_totals;
@@ -59,6 +60,10 @@ bool profile_on() { return g_on.load(std::memory_order_relaxed); }
 void profile_begin(void *stream, const char *name, void **token)
 {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_select.empty() && std::strncmp(name, g_select.c_str(), g_select.size()) != 0) {
+        *token = nullptr;
+        return;
+    }
     Rec *r = new Rec{name, take_event(), take_event()};
     if (!r->start || !r->stop) {
         delete r;
@@ -92,6 +97,18 @@ static spw_status spw_profile_enable_impl(int32_t on)
 spw_status spw_profile_enable(int32_t on)
 {
     return spw::guarded("spw_profile_enable", [&] { return spw_profile_enable_impl(on); });
+}
+
+static spw_status spw_profile_select_impl(const char *prefix)
+{
+    std::lock_guard<std::mutex> lk(spw::g_mu);
+    spw::g_select = prefix ? prefix : "";
+    return SPW_OK;
+}
+
+spw_status spw_profile_select(const char *prefix)
+{
+    return spw::guarded("spw_profile_select", [&] { return spw_profile_select_impl(prefix); });
 }
 
 static spw_status spw_profile_reset_impl(void)

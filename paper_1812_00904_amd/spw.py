@@ -111,6 +111,7 @@ SIGNATURES = {
     "spw_plan_zones": (ctypes.c_int, [_I64, _VP, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                       _VP, _VP, _VP, _VP]),
     "spw_profile_enable": (ctypes.c_int, [_I32]),
+    "spw_profile_select": (ctypes.c_int, [ctypes.c_char_p]),
     "spw_profile_reset": (ctypes.c_int, []),
     "spw_profile_read": (ctypes.c_int, [ctypes.POINTER(ProfileEntry), _I32, ctypes.POINTER(_I32)]),
     "spw_last_error": (ctypes.c_char_p, []),
@@ -272,6 +273,11 @@ def spw_plan_zones(n: int, ptr, chunk_nnz: int):
 
 def spw_profile_enable(on: bool):
     _check(load().spw_profile_enable(1 if on else 0))
+
+
+def spw_profile_select(prefix: str | None):
+    """Time only kernels whose name begins with prefix (None: every kernel)."""
+    _check(load().spw_profile_select(prefix.encode() if prefix else None))
 
 
 def spw_profile_reset():

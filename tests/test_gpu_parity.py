@@ -241,3 +241,33 @@ def test_other_stream_while_busy(spw):
     torch.cuda.synchronize()
     assert torch.equal(u, u2)
     M.close()
+
+
+def test_profile_times_selected_kernels_only(spw):
+    # every launch is timed by default; with a prefix selected only the
+    # kernels whose name begins with it are
+    A = synth.config_matrix("c0", scale=0.2)
+    M = spw.SpwMatrix(spw.SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    x = torch.rand(A.n, dtype=torch.float64, device="cuda")
+    v = torch.rand(A.m, dtype=torch.float64, device="cuda")
+    try:
+        spw.spw_profile_reset()
+        spw.spw_profile_enable(True)
+        M.mv(x)
+        M.vtm(v)
+        torch.cuda.synchronize()
+        every = spw.spw_profile_read()
+        spw.spw_profile_reset()
+        spw.spw_profile_select("vtm_wave")
+        for _ in range(3):
+            M.mv(x)
+            M.vtm(v)
+        torch.cuda.synchronize()
+        chosen = spw.spw_profile_read()
+    finally:
+        spw.spw_profile_enable(False)
+        spw.spw_profile_select(None)
+        spw.spw_profile_reset()
+    assert {"mv_bucket", "vtm_wave"} <= set(every)
+    assert set(chosen) == {"vtm_wave"} and chosen["vtm_wave"][0] == 3 and chosen["vtm_wave"][1] > 0
+    M.close()
