@@ -321,7 +321,9 @@ spw_status spw_serve_create(spw_server *out, const spw_serve_opts *opts);
 spw_status spw_serve_register(spw_server s, spw_matrix A, int32_t *handle);
 /* Queues a request; *ticket identifies it.  SPW_ERR_BUSY at max_inflight,
  * SPW_ERR_SHUTDOWN while the server is being destroyed, SPW_ERR_INVALID_ARG
- * for a bad request (checked before queueing). */
+ * for a bad request (checked before queueing), SPW_ERR_UNSUPPORTED for an
+ * output leading dimension of 2^18 or more on the column-dot side (v^T A of
+ * a CSC matrix, A x of a CSR matrix). */
 spw_status spw_serve_submit(spw_server s, const spw_request *r, uint64_t *ticket);
 /* Starts issuing when the server was created paused (no-op otherwise). */
 spw_status spw_serve_resume(spw_server s);

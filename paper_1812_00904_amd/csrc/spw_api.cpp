@@ -1198,9 +1198,10 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
         } else {
             e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
-    } else if (k <= 6) {
+    } else if (k <= 6 && ldo < CHUNK_OUT_LD_LIMIT) {
         // up to 6 columns: each chunk read once and reduced per column (faster
-        // than the tiled column dots there; the tiles win from about 7 on)
+        // than the tiled column dots there; the tiles win from about 7 on, and
+        // take any output leading dimension)
         e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     } else {
         // column dots for k columns in one pass over the matrix

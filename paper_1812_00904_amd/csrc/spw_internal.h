@@ -162,6 +162,10 @@ int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *
 // every column is bit-identical to the k = 1 product on it.
 int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, int64_t ldx,
               void *y, int64_t ldy, void *stream);
+// The chunk-per-wave column dots address a chunk's outputs through a buffer
+// view of up to 1,024 columns x ld entries x 8 bytes, which must stay below
+// 2^31 bytes: their output leading dimension must be below this.
+constexpr int64_t CHUNK_OUT_LD_LIMIT = (int64_t)1 << 18;
 // Lanes per nonzero of the multi-RHS column dots: the power of two >= k.
 // A renumbered copy of V is stored with this row stride, so the scratch
 // (Scratch::kcap) must be grown to it before the call.

@@ -388,6 +388,10 @@ static spw_status spw_serve_submit_impl(spw_server S, const spw_request *r, uint
     const int64_t out_len = r->op == SPW_OP_MV ? A.m : A.n;
     if ((in_len > 0 && !r->in) || (out_len > 0 && !r->out))
         return sfail(SPW_ERR_INVALID_ARG, "spw_serve_submit: NULL vector");
+    const bool column_dots = (r->op == SPW_OP_VTM) == (A.format == SPW_CSC);
+    if (column_dots && r->ldo >= CHUNK_OUT_LD_LIMIT)
+        return sfail(SPW_ERR_UNSUPPORTED, "spw_serve_submit: output leading dimension must be below 2^18 for "
+                                          "this matrix and op");
     if ((int64_t)S->live.size() >= S->opts.max_inflight) {
         ++S->rejected_busy;
         return sfail(SPW_ERR_BUSY, "spw_serve_submit: " + std::to_string(S->opts.max_inflight) +

@@ -187,3 +187,13 @@ def test_batch_scatter_columns_bit_identical_to_plain(spw, fmt, storage):
                 else:
                     assert torch.allclose(Y[:, c].double(), y.double(), rtol=0, atol=tol * float(y.abs().max() + 1))
     M.close()
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("k", [2, 5])
+def test_column_dots_with_output_leading_dimension_past_chunk_views(spw, fmt, k):
+    # with an output leading dimension of 2^18 or more a chunk's outputs no
+    # longer fit the chunk kernel's 2^31-byte view; such blocks go to the tiled
+    # column dots, which index the output in 64 bits
+    A = synth.random_csc(200, 60, 5.0, 41, values="lognormal")
+    run_case(spw, A, fmt, k, torch.float64, (1 << 18), 41, "ld 2^18+k")

@@ -2,6 +2,7 @@
 alone and in a mix (bit for bit), merging, the HBM budget, a full queue, a
 wait time-out, draining on destroy, bad requests and submits from several
 threads."""
+import ctypes
 import threading
 
 import numpy as np
@@ -173,6 +174,16 @@ def test_bad_requests(spw, mats):
                 lambda: S.submit(h, spw.SPW_OP_MV, x.to(torch.int64), y)):
         with pytest.raises((spw.SpwError, TypeError)):
             bad()
+    # an output leading dimension of 2^18 or more on the column-dot side is
+    # refused before anything touches the (here too small) buffers
+    lib = spw.load()
+    r = spw.Request()
+    r.struct_size = ctypes.sizeof(spw.Request)
+    csc = M.info()["format"] == spw.SPW_CSC
+    r.matrix, r.op, r.vdt, r.k = h, (spw.SPW_OP_VTM if csc else spw.SPW_OP_MV), spw.SPW_F64, 2
+    r.in_, r.ldi, r.out, r.ldo = x.data_ptr(), 2, y.data_ptr(), 1 << 18
+    t = ctypes.c_uint64()
+    assert lib.spw_serve_submit(S.handle, ctypes.byref(r), ctypes.byref(t)) == 6     # SPW_ERR_UNSUPPORTED
     with pytest.raises(spw.SpwError) as ei:
         S.register(mats[0][3])                   # twice
     assert ei.value.status_name == "SPW_ERR_INVALID_ARG"
