@@ -271,3 +271,27 @@ def test_profile_times_selected_kernels_only(spw):
     assert {"mv_bucket", "vtm_wave"} <= set(every)
     assert set(chosen) == {"vtm_wave"} and chosen["vtm_wave"][0] == 3 and chosen["vtm_wave"][1] > 0
     M.close()
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("shape", [(0, 7), (6, 0), (0, 0)])
+def test_zero_dimension(spw, fmt, shape):
+    # a side of length 0: the products write all-zero outputs of the other side
+    m, n = shape
+    if fmt == spw.SPW_CSC:
+        ptr = np.zeros(n + 1, dtype=np.int64)
+    else:
+        ptr = np.zeros(m + 1, dtype=np.int64)
+    M = spw.SpwMatrix(fmt, m, n, ptr, np.zeros(0, dtype=np.int32), np.zeros(0))
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    v = torch.ones(m, dtype=torch.float64, device="cuda")
+    y = torch.full((m,), float("nan"), dtype=torch.float64, device="cuda")
+    u = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    M.mv(x, y)
+    M.vtm(v, u)
+    Y = M.mv_batch(torch.ones((n, 3), dtype=torch.float64, device="cuda"))
+    U = M.vtm_batch(torch.ones((m, 3), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert not y.any() and not u.any() and not Y.any() and not U.any()
+    assert not torch.isnan(y).any() and not torch.isnan(u).any()
+    M.close()
