@@ -197,3 +197,10 @@ def test_column_dots_with_output_leading_dimension_past_chunk_views(spw, fmt, k)
     # column dots, which index the output in 64 bits
     A = synth.random_csc(200, 60, 5.0, 41, values="lognormal")
     run_case(spw, A, fmt, k, torch.float64, (1 << 18), 41, "ld 2^18+k")
+
+
+@pytest.mark.parametrize("k, dtype", [(64, torch.float64), (16, torch.float32)])
+def test_batching_matrix_full_size(spw, k, dtype):
+    # the 5e7-nonzero batching matrix at full size, at widths the benchmark times
+    A = synth.config_matrix("c2")
+    run_case(spw, A, 0, k, dtype, 0, 50 + k, "c2 full")

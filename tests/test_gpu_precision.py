@@ -137,3 +137,11 @@ def test_integer_values_exact_in_every_storage(spw):
             u = M.vtm(torch.from_numpy(v).to(dt).cuda()).double().cpu().numpy()
             assert np.array_equal(y, y_ref) and np.array_equal(u, u_ref), (code, dt)
         M.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_storage_full_size(spw, storage):
+    # the 2e8-nonzero matrix with binary32 / bfloat16 values and binary32
+    # vectors, single vectors, as the benchmark runs it
+    A = synth.config_matrix("c1")
+    run(spw, A, 0, storage, torch.float32, 1, seed=60, name="c1 full")
