@@ -196,6 +196,21 @@ def test_large_config_full_size(spw):
     assert np.array_equal(ys[1], ys[0]) and np.array_equal(us[1], us[0])
 
 
+def test_large_config_full_size_tall(spw):
+    """The same arrays read as the 2e7 x 50,000 tall CSR matrix, at full size."""
+    A = synth.config_matrix("c1")
+    xw, vw = synth.config_vectors("c1", A.m, A.n)
+    x, v = vw, xw                  # tall x has the short side's entries, tall v the long side's
+    print("full-size tall case m=%d n=%d nnz=%d" % (A.n, A.m, A.nnz), flush=True)
+    ys, us, info = run_both(spw, A, 1, x, v, reps=2)
+    y, dy = oracle.mv_csr(A.n, A.m, A.ptr, A.idx, A.val, x, with_d=True)
+    check(ys[0], y, dy, "c1 tall mv")
+    del y, dy
+    u, du = oracle.vtm_csr(A.n, A.m, A.ptr, A.idx, A.val, v, with_d=True)
+    check(us[0], u, du, "c1 tall vtm")
+    assert np.array_equal(ys[1], ys[0]) and np.array_equal(us[1], us[0])
+
+
 def test_streams_and_determinism(spw):
     A = synth.config_matrix("c0", scale=0.5)
     M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val)
