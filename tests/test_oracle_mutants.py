@@ -24,6 +24,16 @@ MUTANTS = {
     "csr_vtm_transposed": ("u[j] = u[j] + prod;", "u[j] = u[j] + val[p] * v[i % (j + 1)];"),
     "denominator_signed": ("if (d) d[i] = d[i] + fabs(val[p]) * fabs(x[j]);",
                            "if (d) d[i] = d[i] + val[p] * fabs(x[j]);"),
+    "vtm_csc_denominator_inflated": ("a = a + fabs(val[p]) * fabs(v[idx[p]]);",
+                                     "a = a + fabs(val[p]) * (fabs(v[idx[p]]) + 1.0);"),
+    "csr_mv_denominator_inflated": ("a = a + fabs(val[p]) * fabs(x[idx[p]]);",
+                                    "a = a + fabs(val[p]) * (fabs(x[idx[p]]) + 1.0);"),
+    "csr_vtm_denominator_inflated": ("if (d) d[j] = d[j] + fabs(val[p]) * fabs(v[i]);",
+                                     "if (d) d[j] = d[j] + fabs(val[p]) * (fabs(v[i]) + 1.0);"),
+    "batch_denominator_is_output": ("if (D) scatter_col(D, out_len, ldd, c, dout);",
+                                    "if (D) scatter_col(D, out_len, ldd, c, yout);"),
+    "batch_denominator_wrong_column": ("if (D) scatter_col(D, out_len, ldd, c, dout);",
+                                       "if (D) scatter_col(D, out_len, ldd, 0, dout);"),
     "round_one_bit_short": ("double q = ldexp(1.0, ex - (p - 1));", "double q = ldexp(1.0, ex - (p - 2));"),
     "round_truncates": ("double r = nearbyint(x / q) * q;", "double r = trunc(x / q) * q;"),
     "paper_offsets_off_by_one": ("(i < big ? q + 1 : q)", "(i + 1 < big ? q + 1 : q)"),

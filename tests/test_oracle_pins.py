@@ -63,10 +63,35 @@ def test_products_exact_on_integers(shape, seed):
     assert np.array_equal(du, (np.abs(vi) @ np.abs(D)).astype(np.float64))
     # the tall (row-major) forms: the same arrays read as CSR of the n x m transpose
     yt, dyt = oracle.mv_csr(n, m, A.ptr, A.idx, A.val, v, with_d=True)
-    ut = oracle.vtm_csr(n, m, A.ptr, A.idx, A.val, x)
+    ut, dut = oracle.vtm_csr(n, m, A.ptr, A.idx, A.val, x, with_d=True)
     assert np.array_equal(yt, (D.T @ vi).astype(np.float64))
     assert np.array_equal(ut, (xi @ D.T).astype(np.float64))
     assert np.array_equal(dyt, (np.abs(D.T) @ np.abs(vi)).astype(np.float64))
+    # the tall v^T A denominator, d_j = sum_i |v_i||a_ij| over the n x m transpose
+    assert np.array_equal(dut, (np.abs(xi) @ np.abs(D.T)).astype(np.float64))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (9, 40), (33, 7)])
+@pytest.mark.parametrize("k", [1, 3])
+def test_batched_products_and_denominators_exact_on_integers(shape, k):
+    # Every output and every error denominator of the four multi-RHS forms
+    # against int64 dense products: |A| |X| for the y side, |V|^T |A| for u.
+    m, n = shape
+    A = _int_matrix(m, n, 3.0, 20 + k, empty_frac=0.2)
+    D = _dense_int(A)
+    X = synth.vector(n * k, 21, 1, kind="int").reshape(n, k)
+    V = synth.vector(m * k, 21, 2, kind="int").reshape(m, k)
+    Xi, Vi = X.astype(np.int64), V.astype(np.int64)
+    f = lambda a: a.astype(np.float64)
+    Y, DY = oracle.mv_csc_batch(m, n, A.ptr, A.idx, A.val, X, with_d=True)
+    U, DU = oracle.vtm_csc_batch(m, n, A.ptr, A.idx, A.val, V, with_d=True)
+    assert np.array_equal(Y, f(D @ Xi)) and np.array_equal(DY, f(np.abs(D) @ np.abs(Xi)))
+    assert np.array_equal(U, f(D.T @ Vi)) and np.array_equal(DU, f(np.abs(D.T) @ np.abs(Vi)))
+    # the same arrays read as CSR of the n x m transpose
+    Yt, DYt = oracle.mv_csr_batch(n, m, A.ptr, A.idx, A.val, V, with_d=True)
+    Ut, DUt = oracle.vtm_csr_batch(n, m, A.ptr, A.idx, A.val, X, with_d=True)
+    assert np.array_equal(Yt, f(D.T @ Vi)) and np.array_equal(DYt, f(np.abs(D.T) @ np.abs(Vi)))
+    assert np.array_equal(Ut, f(D @ Xi)) and np.array_equal(DUt, f(np.abs(D) @ np.abs(Xi)))
 
 
 @pytest.mark.parametrize("seed", [3, 4, 5])
