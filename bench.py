@@ -603,7 +603,7 @@ def bench_batched(args):
 
 def bench_partition(args):
     """Nonzero partitioning (the paper's method) against column partitioning
-    (its Section V comparison) on one GPU: the same kernels and results, only
+    (its Section VI comparison) on one GPU: the same kernels and results, only
     the assignment of work to workers differs.  Three 5e7-nonzero matrices:
     the batching matrix in generated order, the same with columns in
     descending length (the worst case for column partitioning), and a

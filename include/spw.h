@@ -62,7 +62,7 @@ typedef enum { SPW_F64 = 0, SPW_F32 = 1, SPW_BF16 = 2 } spw_dtype;
 typedef enum {
     SPW_PART_NONZERO = 0,  /* equal runs of nonzeros (Section II), the default */
     SPW_PART_COLUMN = 1    /* equal numbers of columns of the long dimension: the column
-                              partitioning the paper compares against (Section V); same
+                              partitioning the paper compares against (Section VI); same
                               results, kept for that comparison */
 } spw_partition;
 
@@ -136,7 +136,7 @@ typedef struct {
     spw_partition partition;
     int64_t workers;              /* P: workers of the single-vector column dots (waves) */
     int64_t worker_max_nnz;       /* nonzeros owned by the busiest / idlest of them; the paper's */
-    int64_t worker_min_nnz;       /* imbalance is P * (max - min) / nnz (Section V) */
+    int64_t worker_min_nnz;       /* imbalance is P * (max - min) / nnz (Section VI) */
 } spw_matrix_info;
 
 /* ---------------------------------------------------------------- matrices */
@@ -215,7 +215,7 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
 /* ------------------------------------------------------------- a solver */
 
 /* Conjugate gradients on the least-squares problem min ||b - A x||_2 (CGLS):
- * the first-order use of the two products that Section VI describes, where
+ * the first-order use of the two products that Section VII describes, where
  * each iteration alternates one y := A p with one u^T := r^T A and a few
  * vector updates and inner products.  The paper names conjugate gradients
  * without fixing a variant; this is the Hestenes-Stiefel form as arranged by

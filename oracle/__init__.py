@@ -265,7 +265,7 @@ def colp_imbalance(n, ptr, P) -> float:
 
 
 def cgls(fmt, m, n, ptr, idx, val, b, x0, iters):
-    """CGLS on min ||b - A x||_2 from x0 (Section VI's first-order use of the
+    """CGLS on min ||b - A x||_2 from x0 (Section VII's first-order use of the
     products; the variant is Hestenes-Stiefel / Bjorck, see oracle.c).  A is m x n,
     fmt "csc" (wide) or "csr" (tall).  Returns (x, gamma, rho) with gamma[k] =
     ||A^T r_k||^2 and rho[k] = ||r_k||^2 for k = 0 .. iters."""

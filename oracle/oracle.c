@@ -33,7 +33,7 @@
  *     algorithms of Section III (local products, then y = sum of y_(i)) and
  *     Section IV-A (local products, then zone sums over S_k).
  *   - orc_cgls: a first-order solver that alternates the two products with
- *     vector updates and inner products, as Section VI describes such methods.
+ *     vector updates and inner products, as Section VII describes such methods.
  *     The paper names conjugate gradients without fixing a variant; this is
  *     conjugate gradients on the least-squares problem min ||b - A x||_2
  *     (CGLS, Hestenes and Stiefel 1952, in the arrangement of Bjorck,
@@ -380,7 +380,7 @@ int orc_nzp_vtm(int64_t m, int64_t n, const int64_t *ptr, const int32_t *idx, co
     return 0;
 }
 
-/* Column partitioning comparison statistic (Section V): with the columns cut
+/* Column partitioning comparison statistic (Section VI): with the columns cut
  * into P contiguous spans of (almost) equal column count, the imbalance
  * Delta = P (max - min nonzeros per span) / Z.  Span i holds columns
  * [i*n/P, (i+1)*n/P) using the same first-n-mod-P-get-one-more rule. */
@@ -400,7 +400,7 @@ double orc_colp_imbalance(int64_t n, const int64_t *ptr, int64_t P)
 }
 
 /* ------------------------------------------------------------------------ */
-/* CGLS (Section VI's first-order use of the two products).  A is m x n, wide  */
+/* CGLS (Section VII's first-order use of the two products).  A is m x n, wide */
 /* CSC (csr = 0) or tall CSR (csr = 1).  x holds x_0 on entry and x_iters on  */
 /* exit.  hist_gamma[k] = ||A^T r_k||^2 and hist_rho[k] = ||r_k||^2 for        */
 /* k = 0 .. iters (either may be NULL).  An exact zero in a denominator (the  */

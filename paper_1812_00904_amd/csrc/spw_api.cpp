@@ -418,7 +418,7 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
 
 // Workers of the single-vector column dots and how much each owns.  Nonzero
 // partitioning: worker w reduces chunks w, w+P, ... (the kernel's grid
-// stride).  Column partitioning (Section V's comparison): worker w owns
+// stride).  Column partitioning (Section VI's comparison): worker w owns
 // columns [j0_w, j1_w), equal counts with the first cols mod P workers one
 // more, and reduces the chunks whose first position lies in its columns.
 spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_partition part)

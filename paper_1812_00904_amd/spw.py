@@ -183,6 +183,7 @@ def spw_create_coo(fmt: int, m: int, n: int, rows, cols, val, opts: CreateOpts |
 
 
 def spw_destroy(h: int):
+    _shapes.pop(h, None)
     _check(load().spw_destroy(h))
 
 
@@ -206,38 +207,97 @@ def _dev(t: torch.Tensor, name: str):
         raise ValueError("%s must be a device tensor" % name)
 
 
+# (m, n, device ordinal) of every live handle, so that the product calls can
+# check their tensors against the matrix without a library call.
+_shapes: dict = {}
+
+
+def _shape(h: int):
+    sh = _shapes.get(h)
+    if sh is None:
+        info = spw_info(h)
+        sh = (info["m"], info["n"], info["device"])
+        _shapes[h] = sh
+    return sh
+
+
+def check_operands(inp: torch.Tensor, out: torch.Tensor, in_len: int, out_len: int, device,
+                   batch: bool, names=("in", "out")) -> int:
+    """Checks a product's input and output tensors before any pointer reaches
+    the library: float64 or float32, the same type on both sides, the lengths
+    the matrix fixes, on `device` (a device ordinal; None skips the check).
+    Single-vector operands are 1-D and contiguous; multi-RHS operands are 2-D
+    (rows x k) with unit column stride and a row stride >= k (a 1-D tensor
+    counts as k = 1).  Raises ValueError (TypeError for a wrong element type)
+    and returns k."""
+    ni, no = names
+    _vec_dtype(inp)
+    if out.dtype != inp.dtype:
+        raise ValueError("%s is %s but %s is %s: the two must have the same type"
+                         % (no, out.dtype, ni, inp.dtype))
+    for t, nm in ((inp, ni), (out, no)):
+        if device is not None and (not t.is_cuda or t.device.index != device):
+            raise ValueError("%s must be on cuda:%d (the matrix's device), not %s" % (nm, device, t.device))
+    if not batch or (inp.dim() == 1 and out.dim() == 1):
+        for t, nm, ln in ((inp, ni, in_len), (out, no, out_len)):
+            if t.dim() != 1:
+                raise ValueError("%s must be 1-D, got shape %s" % (nm, tuple(t.shape)))
+            if t.numel() != ln:
+                raise ValueError("%s must have %d entries, got %d" % (nm, ln, t.numel()))
+            if ln > 1 and t.stride(0) != 1:
+                raise ValueError("%s must be contiguous (stride %d)" % (nm, t.stride(0)))
+        return 1
+    if inp.dim() != 2 or out.dim() != 2:
+        raise ValueError("%s and %s must both be 2-D (rows x k), got shapes %s and %s"
+                         % (ni, no, tuple(inp.shape), tuple(out.shape)))
+    k = inp.shape[1]
+    for t, nm, ln in ((inp, ni, in_len), (out, no, out_len)):
+        if tuple(t.shape) != (ln, k):
+            raise ValueError("%s must have shape (%d, %d), got %s" % (nm, ln, k, tuple(t.shape)))
+        if k > 1 and t.stride(1) != 1:
+            raise ValueError("%s must be row-major with unit column stride (strides %s)" % (nm, t.stride()))
+        if ln > 1 and t.stride(0) < k:
+            raise ValueError("%s row stride %d is below k = %d" % (nm, t.stride(0), k))
+    return k
+
+
+def _ld(t: torch.Tensor) -> int:
+    return 1 if t.dim() == 1 else max(t.stride(0), t.shape[1])
+
+
 def spw_mv(h: int, x: torch.Tensor, y: torch.Tensor, stream=None):
-    _dev(x, "x"), _dev(y, "y")
+    m, n, dev = _shape(h)
+    check_operands(x, y, n, m, dev, False, ("x", "y"))
     _check(load().spw_mv(h, _vec_dtype(x), x.data_ptr(), y.data_ptr(), _stream_ptr(stream)))
 
 
 def spw_vtm(h: int, v: torch.Tensor, u: torch.Tensor, stream=None):
-    _dev(v, "v"), _dev(u, "u")
+    m, n, dev = _shape(h)
+    check_operands(v, u, m, n, dev, False, ("v", "u"))
     _check(load().spw_vtm(h, _vec_dtype(v), v.data_ptr(), u.data_ptr(), _stream_ptr(stream)))
 
 
 def spw_mv_batch(h: int, X: torch.Tensor, Y: torch.Tensor, stream=None):
-    _dev(X, "X"), _dev(Y, "Y")
-    k = X.shape[1]
-    _check(load().spw_mv_batch(h, _vec_dtype(X), k, X.data_ptr(), X.stride(0), Y.data_ptr(), Y.stride(0),
+    m, n, dev = _shape(h)
+    k = check_operands(X, Y, n, m, dev, True, ("X", "Y"))
+    _check(load().spw_mv_batch(h, _vec_dtype(X), k, X.data_ptr(), _ld(X), Y.data_ptr(), _ld(Y),
                                _stream_ptr(stream)))
 
 
 def spw_vtm_batch(h: int, V: torch.Tensor, U: torch.Tensor, stream=None):
-    _dev(V, "V"), _dev(U, "U")
-    k = V.shape[1]
-    _check(load().spw_vtm_batch(h, _vec_dtype(V), k, V.data_ptr(), V.stride(0), U.data_ptr(), U.stride(0),
+    m, n, dev = _shape(h)
+    k = check_operands(V, U, m, n, dev, True, ("V", "U"))
+    _check(load().spw_vtm_batch(h, _vec_dtype(V), k, V.data_ptr(), _ld(V), U.data_ptr(), _ld(U),
                                 _stream_ptr(stream)))
 
 
 def spw_cgls(h: int, b: torch.Tensor, x: torch.Tensor, iters: int, hist: bool = True, stream=None):
     """CGLS on min ||b - A x||_2 in place on x (float64 device tensors).  With
     hist, returns (gamma, rho): ||A^T r_k||^2 and ||r_k||^2 for k = 0 .. iters."""
-    _dev(b, "b"), _dev(x, "x")
+    m, n, dev = _shape(h)
     if b.dtype != torch.float64 or x.dtype != torch.float64:
         raise ValueError("spw_cgls takes float64 vectors")
-    if not (b.is_contiguous() and x.is_contiguous()):
-        raise ValueError("spw_cgls takes contiguous vectors")
+    check_operands(b, x, m, n, dev, False, ("b", "x"))
     out = np.empty(2 * (iters + 1), dtype=np.float64) if hist else None
     _check(load().spw_cgls(h, SPW_F64, b.data_ptr(), x.data_ptr(), int(iters),
                            out.ctypes.data if hist else None, _stream_ptr(stream)))
@@ -368,21 +428,28 @@ class Server:
         _check(load().spw_serve_create(ctypes.byref(h), ctypes.byref(o)))
         self.handle = h.value
         self._keep = {}
+        self._shapes = {}
 
     def register(self, M: SpwMatrix) -> int:
         out = _I32()
         _check(load().spw_serve_register(self.handle, M.handle, ctypes.byref(out)))
+        self._shapes[out.value] = _shape(M.handle)
         return out.value
 
     def submit(self, matrix: int, op: int, X: torch.Tensor, Y: torch.Tensor, tag: int = 0) -> int:
         """X, Y: device tensors, 1-D (k = 1) or 2-D row-major (rows x k)."""
-        _dev(X, "in"), _dev(Y, "out")
-        k = 1 if X.dim() == 1 else X.shape[1]
+        if matrix not in self._shapes:
+            raise ValueError("matrix handle %r is not registered with this server" % (matrix,))
+        if op not in (SPW_OP_MV, SPW_OP_VTM):
+            raise ValueError("op must be SPW_OP_MV or SPW_OP_VTM")
+        m, n, dev = self._shapes[matrix]
+        in_len, out_len = (n, m) if op == SPW_OP_MV else (m, n)
+        k = check_operands(X, Y, in_len, out_len, dev, True)
         r = Request()
         r.struct_size = ctypes.sizeof(Request)
         r.matrix, r.op, r.vdt, r.k = matrix, op, _vec_dtype(X), k
-        r.in_, r.ldi = X.data_ptr(), (1 if X.dim() == 1 else X.stride(0))
-        r.out, r.ldo = Y.data_ptr(), (1 if Y.dim() == 1 else Y.stride(0))
+        r.in_, r.ldi = X.data_ptr(), _ld(X)
+        r.out, r.ldo = Y.data_ptr(), _ld(Y)
         r.tag = tag
         t = ctypes.c_uint64()
         _check(load().spw_serve_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))

@@ -253,7 +253,7 @@ def serving_requests(count: int, n_matrices: int, seed: int | None = None) -> di
 
 
 # --------------------------------------------------------------------------
-# Column-partitioning comparison (the paper's Section V experiments)
+# Column-partitioning comparison (the paper's Section VI experiments)
 # --------------------------------------------------------------------------
 def sort_columns_by_length(A: Sparse) -> Sparse:
     """The same matrix with its columns in descending order of length (ties by

@@ -283,3 +283,46 @@ def test_host_allocation_failure_is_a_status_not_an_abort():
     r = subprocess.run([sys.executable, "-c", _OOM_CHILD, root], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().splitlines()[-1] == "SPW_ERR_OUT_OF_MEMORY", r.stdout
+
+
+# ---------------------------------------------------------------------------
+# The binding's operand checks run before any pointer reaches the library, so
+# they are exercised here with host tensors (device check off).
+# ---------------------------------------------------------------------------
+def test_binding_rejects_mismatched_operands(spw):
+    import torch
+    chk = spw.check_operands
+    f64, f32 = torch.float64, torch.float32
+    x, y = torch.zeros(7, dtype=f64), torch.zeros(5, dtype=f64)
+    assert chk(x, y, 7, 5, None, False) == 1
+    bad_single = [
+        (torch.zeros(7, dtype=f64), torch.zeros(5, dtype=f32)),        # output narrower than input
+        (torch.zeros(7, dtype=f32), torch.zeros(5, dtype=f64)),        # output wider than input
+        (torch.zeros(6, dtype=f64), torch.zeros(5, dtype=f64)),        # short input
+        (torch.zeros(7, dtype=f64), torch.zeros(4, dtype=f64)),        # short output
+        (torch.zeros(14, dtype=f64)[::2], torch.zeros(5, dtype=f64)),  # strided view
+        (torch.zeros(7, 1, dtype=f64), torch.zeros(5, dtype=f64)),     # 2-D in a single-vector call
+    ]
+    for a, b in bad_single:
+        with pytest.raises(ValueError):
+            chk(a, b, 7, 5, None, False)
+    with pytest.raises(TypeError):
+        chk(torch.zeros(7, dtype=torch.int64), torch.zeros(5, dtype=torch.int64), 7, 5, None, False)
+    # multi-RHS blocks: (rows x k), unit column stride, row stride >= k
+    X, Y = torch.zeros(7, 3, dtype=f64), torch.zeros(5, 3, dtype=f64)
+    assert chk(X, Y, 7, 5, None, True) == 3
+    wide = torch.zeros(7, 8, dtype=f64)
+    assert chk(wide[:, :3], Y, 7, 5, None, True) == 3                 # padded leading dimension
+    assert chk(x, y, 7, 5, None, True) == 1                           # 1-D pair: k = 1
+    bad_batch = [
+        (X, torch.zeros(5, 3, dtype=f32)),                             # types differ
+        (X, torch.zeros(5, 2, dtype=f64)),                             # k differs
+        (X, torch.zeros(4, 3, dtype=f64)),                             # short output
+        (torch.zeros(6, 3, dtype=f64), Y),                             # short input
+        (torch.zeros(3, 7, dtype=f64).t(), Y),                         # column-major view
+        (wide[:, ::2][:, :3], Y),                                      # column stride 2
+        (x, Y),                                                        # 1-D against 2-D
+    ]
+    for a, b in bad_batch:
+        with pytest.raises(ValueError):
+            chk(a, b, 7, 5, None, True)

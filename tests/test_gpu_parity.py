@@ -310,3 +310,28 @@ def test_zero_dimension(spw, fmt, shape):
     assert not y.any() and not u.any() and not Y.any() and not U.any()
     assert not torch.isnan(y).any() and not torch.isnan(u).any()
     M.close()
+
+
+def test_binding_rejects_bad_operands_before_launch(spw):
+    # wrong output type, wrong lengths, strided and host tensors are refused by
+    # the binding; the sentinel outputs show that nothing was written
+    A = synth.random_csc(40, 300, 4.0, 5, values="lognormal")
+    M = spw.SpwMatrix(spw.SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val)
+    f64 = dict(dtype=torch.float64, device="cuda")
+    x, v = torch.ones(A.n, **f64), torch.ones(A.m, **f64)
+    y32 = torch.full((A.m,), 7.0, dtype=torch.float32, device="cuda")
+    ys = torch.full((A.m - 1,), 7.0, **f64)
+    xs = torch.ones(2 * A.n, **f64)[::2]
+    cases = [lambda: M.mv(x, y32), lambda: M.mv(x, ys), lambda: M.mv(xs, torch.empty(A.m, **f64)),
+             lambda: M.mv(x.cpu(), torch.empty(A.m, **f64)), lambda: M.vtm(v, torch.empty(A.n - 1, **f64)),
+             lambda: M.vtm(v[:-1], torch.empty(A.n, **f64))]
+    X = torch.ones((A.n, 4), **f64)
+    Y = torch.full((A.m, 4), 7.0, **f64)
+    cases += [lambda: M.mv_batch(X, Y[:, :3]), lambda: M.mv_batch(X, Y.float()),
+              lambda: M.mv_batch(X.t().contiguous().t(), Y), lambda: M.vtm_batch(Y[:-1], torch.empty((A.n, 4), **f64))]
+    for i, fn in enumerate(cases):
+        with pytest.raises(ValueError):
+            fn()
+    torch.cuda.synchronize()
+    assert bool((y32 == 7.0).all()) and bool((ys == 7.0).all()) and bool((Y == 7.0).all())
+    M.close()

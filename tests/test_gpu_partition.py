@@ -1,4 +1,4 @@
-"""Column partitioning (the comparison of Section V) through the C ABI: the
+"""Column partitioning (the comparison of Section VI) through the C ABI: the
 column dots give bit-identical results whichever way the work is divided,
 the scatter product agrees with the oracle, and the reported worker
 imbalance equals the oracle's Delta = P * (max - min) / nnz."""

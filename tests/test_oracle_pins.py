@@ -407,7 +407,7 @@ def test_colp_imbalance_closed_form():
 
 
 # ---------------------------------------------------------------------------
-# CGLS (Section VI: first-order methods alternating the two products)
+# CGLS (Section VII: first-order methods alternating the two products)
 # ---------------------------------------------------------------------------
 def _cgls_case(fmt, seed, m_w=12, n_w=40):
     """A small random matrix in the requested layout with its dense copy: wide
