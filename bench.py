@@ -167,7 +167,7 @@ def main():
     ap.add_argument("--no-small", action="store_true", help="skip the small-matrix latency section")
     ap.add_argument("--solver-iters", type=int, default=20)
     ap.add_argument("--serving-requests", type=int, default=10000)
-    ap.add_argument("--serving-loads", default="0.7",
+    ap.add_argument("--serving-loads", default="0.25,0.5,0.9,1.2,1.5",
                     help="comma-separated offered loads, as fractions of the plain path's capacity")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")

@@ -253,11 +253,12 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
  * and vector type are merged into one group (continuous batching: requests
  * that arrive while earlier groups run join the next group) and issued on one
  * of a few HIP streams, at most `depth` groups per stream.  A group's columns
- * run as column-dot passes of up to 8 columns that read the matrix once per
- * pass, or as one scatter pass per column, and every column is reduced exactly
- * as a lone single-vector call would reduce it: a request's output is
+ * run as passes of up to 8 columns (column dots or the scatter product, by
+ * direction) that each read the matrix once, and every column is reduced
+ * exactly as a lone single-vector call would reduce it: a request's output is
  * bit-identical whatever else it was batched with.  The memory a matrix holds
- * (spw_matrix_info.device_bytes, after its scratch grows to 8 columns at
+ * (spw_matrix_info.device_bytes, after its scratch -- carries, renumbered
+ * inputs and the scatter product's partial sums -- grows to 8 columns at
  * registration) is charged to the server's HBM budget. */
 typedef struct spw_server_s *spw_server;
 

@@ -154,8 +154,10 @@ int launch_vtm_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void 
 // columns per pass; every column is bit-identical to launch_vtm on it.
 int launch_vtm_multi(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *v, int64_t ldv, void *u,
                      int64_t ldu, void *stream);
-// Scatter products for k columns with their own bases and strides (host
-// arrays), one pass each.
+// Scatter products for k <= 8 columns with their own bases and strides (host
+// arrays): one pass over the matrix for all k when the multi-column partial
+// sums hold k columns (grow_partial_cols), else one pass per column.  Every
+// column is bit-identical to the single-column product on it.
 int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
                    void *const *out, const int64_t *ldo, void *stream);
 // Scatter product y = B x, k times over strided columns of X (ldx) and Y (ldy);

@@ -851,27 +851,42 @@ __global__ __launch_bounds__(BLOCK) void mv_bucket(
                                 partial + (int64_t)blockIdx.x * panel_rows, panel_rows, ypan);
 }
 
-// k columns of X in one launch.  Workgroup (column c, group g) runs the
-// ranges g*S .. g*S+S-1 of the single-column product for column c, each into
-// its own partial slot (c * W + range), so every column is summed exactly as
-// the single-column call sums it.  The k workgroups of a group are dispatched
-// to the same XCD (workgroup ids are dealt to the 8 XCDs round-robin: id b
-// goes to XCD b mod 8), so they read the same blocks, and the same lines of a
-// row-major X, through one L2 at about the same time (ordinary loads, so the
-// lines stay for the others): A streams from HBM about once for the k columns.
-template <int BLOCK, typename ValT, typename VecT>
+// k columns in one launch.  TAB = false: column c of a row-major X (x + c,
+// stride ldx).  TAB = true: column c read from xin.v[c] with stride
+// xin.ld[c] (the inputs of different served requests; the entry is picked by
+// a chain of selects on c, so the table stays in kernel-argument registers).
+// Workgroup (column c, group g) runs the ranges g*S .. g*S+S-1 of the
+// single-column product for column c, each into its own partial slot
+// (c * W + range), so every column is summed exactly as the single-column
+// call sums it.  The k workgroups of a group are dispatched to the same XCD
+// (workgroup ids are dealt to the 8 XCDs round-robin: id b goes to XCD b mod
+// 8), so they read the same blocks, and the same lines of a row-major X,
+// through one L2 at about the same time (ordinary loads, so the lines stay for
+// the others): A streams from HBM about once for the k columns.
+template <int BLOCK, typename ValT, typename VecT, bool TAB>
 __global__ __launch_bounds__(BLOCK) void mv_bucket_cols(
     const uint32_t *__restrict__ packed, const ValT *__restrict__ val, const int2 *__restrict__ blocks,
-    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, double *__restrict__ partial,
-    int panel_rows, int k, int W, int S)
+    const int32_t *__restrict__ wg_blk, const VecT *__restrict__ x, int64_t ldx, ColIn<VecT> xin,
+    double *__restrict__ partial, int panel_rows, int k, int W, int S)
 {
     extern __shared__ double ypan[];
     const int b = blockIdx.x;
     const int c = (b % (8 * k)) / 8;
     const int g = (b / (8 * k)) * 8 + b % 8;
     const int w0 = g * S, w1 = min(W, w0 + S);
+    const VecT *xc = x + c;
+    int64_t ld = ldx;
+    if constexpr (TAB) {
+        xc = xin.v[0];
+        ld = xin.ld[0];
+#pragma unroll
+        for (int t = 1; t < MULTI_MAX; ++t) {
+            xc = c == t ? xin.v[t] : xc;
+            ld = c == t ? xin.ld[t] : ld;
+        }
+    }
     for (int w = w0; w < w1; ++w)
-        mv_range<BLOCK, ValT, VecT, false>(packed, val, blocks, wg_blk, w, x + c, ldx,
+        mv_range<BLOCK, ValT, VecT, false>(packed, val, blocks, wg_blk, w, xc, ld,
                                     partial + ((int64_t)c * W + w) * panel_rows, panel_rows, ypan);
 }
 
@@ -1492,7 +1507,7 @@ int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT 
     const unsigned red_blocks = blocks_for(A.n_panels * A.panel_rows * 8, 256);
     if (k > 1 && A.mv_wgs > 0 && A.scratch.partial_cols && A.scratch.pcols > 0) {
         // columns in batches of up to pcols, one launch per batch
-        static const bool attr_c = allow_full_lds(mv_bucket_cols<MV_BLOCK, ValT, VecT>);
+        static const bool attr_c = allow_full_lds(mv_bucket_cols<MV_BLOCK, ValT, VecT, false>);
         (void)attr_c;
         const int W = (int)A.mv_wgs, cus = device_cu_count(A.device);
         for (int32_t c0 = 0; c0 < k; c0 += A.scratch.pcols) {
@@ -1506,10 +1521,10 @@ int mv_typed(const spw_matrix_s &A, int32_t k, const VecT *x, int64_t ldx, VecT 
             const unsigned grid = (unsigned)(kb * 8 * ((G + 7) / 8));
             {
                 ProfScope ps(stream, "mv_bucket");
-                hipLaunchKernelGGL((mv_bucket_cols<MV_BLOCK, ValT, VecT>), dim3(grid), dim3(MV_BLOCK),
+                hipLaunchKernelGGL((mv_bucket_cols<MV_BLOCK, ValT, VecT, false>), dim3(grid), dim3(MV_BLOCK),
                                    (size_t)A.panel_rows * 8, stream, (const uint32_t *)A.d_mpacked,
                                    (const ValT *)A.d_mval, (const int2 *)A.d_mblocks, A.d_wg_blk, x + c0, ldx,
-                                   A.scratch.partial_cols, (int)A.panel_rows, kb, W, S);
+                                   ColIn<VecT>{}, A.scratch.partial_cols, (int)A.panel_rows, kb, W, S);
                 if ((e = (int)hipGetLastError())) return e;
             }
             {
@@ -1625,14 +1640,71 @@ int launch_mv(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *x, in
     });
 }
 
+namespace {
+// One launch of the scatter kernel for k <= MULTI_MAX columns with their own
+// input bases and strides, then the fixed-order reduction of each column into
+// its own output: every column is summed exactly as a single-column call sums
+// it, and the matrix is read once for the k columns.
+template <typename ValT, typename VecT>
+int mv_cols_tab(const spw_matrix_s &A, int k, const ColIn<VecT> &xin, VecT *const *out, const int64_t *ldo,
+                hipStream_t stream)
+{
+    if (A.rows == 0) return 0;
+    int e;
+    const int W = (int)A.mv_wgs;
+    if (W > 0) {
+        static const bool attr_t = allow_full_lds(mv_bucket_cols<MV_BLOCK, ValT, VecT, true>);
+        (void)attr_t;
+        const int cus = device_cu_count(A.device);
+        // as in the row-major form: the fewest ranges per workgroup S for which
+        // all k * ceil(W / S) workgroups run at once
+        int S = (int)std::max<int64_t>(1, ((int64_t)W * k + cus - 1) / cus);
+        while (S < W && (int64_t)k * ((W + S - 1) / S) > cus) ++S;
+        const int G = (W + S - 1) / S;
+        const unsigned grid = (unsigned)(k * 8 * ((G + 7) / 8));
+        ProfScope ps(stream, "mv_bucket");
+        hipLaunchKernelGGL((mv_bucket_cols<MV_BLOCK, ValT, VecT, true>), dim3(grid), dim3(MV_BLOCK),
+                           (size_t)A.panel_rows * 8, stream, (const uint32_t *)A.d_mpacked, (const ValT *)A.d_mval,
+                           (const int2 *)A.d_mblocks, A.d_wg_blk, (const VecT *)nullptr, (int64_t)0, xin,
+                           A.scratch.partial_cols, (int)A.panel_rows, k, W, S);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    const unsigned red_blocks = blocks_for(A.n_panels * A.panel_rows * 8, 256);
+    for (int c = 0; c < k; ++c) {
+        ProfScope ps(stream, "mv_reduce");
+        hipLaunchKernelGGL(mv_reduce<VecT>, dim3(red_blocks), dim3(256), 0, stream,
+                           A.scratch.partial_cols + (int64_t)c * W * A.panel_rows, (int)A.panel_rows, A.d_panels,
+                           (int)A.n_panels, A.rows, A.relabeled ? A.d_inv : nullptr, out[c], ldo[c], (int64_t)0);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    return 0;
+}
+}  // namespace
+
 int launch_mv_cols(const spw_matrix_s &A, spw_dtype vdt, int32_t k, const void *const *in, const int64_t *ldi,
                    void *const *out, const int64_t *ldo, void *stream)
 {
-    for (int c = 0; c < k; ++c) {
-        const int e = launch_mv(A, vdt, 1, in[c], ldi[c], out[c], ldo[c], stream);
-        if (e) return e;
+    if (k < 1 || k > MULTI_MAX) return (int)hipErrorInvalidValue;
+    if (k == 1 || A.scratch.pcols < k || !A.scratch.partial_cols) {
+        // one column, or no multi-column partial sums: one pass per column
+        for (int c = 0; c < k; ++c) {
+            const int e = launch_mv(A, vdt, 1, in[c], ldi[c], out[c], ldo[c], stream);
+            if (e) return e;
+        }
+        return 0;
     }
-    return 0;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        ColIn<VecT> ti{};
+        VecT *to[MULTI_MAX];
+        for (int c = 0; c < k; ++c) {
+            ti.v[c] = (const VecT *)in[c];
+            ti.ld[c] = ldi[c];
+            to[c] = (VecT *)out[c];
+        }
+        return mv_cols_tab<ValT, VecT>(A, k, ti, to, ldo, (hipStream_t)stream);
+    });
 }
 
 namespace {

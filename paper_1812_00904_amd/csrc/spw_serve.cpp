@@ -132,7 +132,7 @@ spw_status issue_group(spw_matrix_s &A, const std::vector<spw_request> &reqs, hi
             set_error(std::string("serve: kernel launch failed: ") + hipGetErrorString((hipError_t)e));
             return SPW_ERR_DEVICE;
         }
-        *passes += scatter ? kk : 1;
+        *passes += (scatter && A.scratch.pcols < kk) ? kk : 1;
     }
     return SPW_OK;
 }
@@ -347,7 +347,8 @@ static spw_status spw_serve_register_impl(spw_server S, spw_matrix A, int32_t *h
         int prev = 0;
         (void)hipGetDevice(&prev);
         (void)hipSetDevice(S->device);
-        const spw_status st = grow_scratch(*A, PASS_COLS);
+        spw_status st = grow_scratch(*A, PASS_COLS);
+        if (!st) st = grow_partial_cols(*A, PASS_COLS);
         (void)hipSetDevice(prev);
         if (st) return st;
     }

@@ -110,7 +110,37 @@ def test_same_alone_and_in_a_mix(spw, mats):
         assert np.array_equal(a, b), "request %d differs between alone and mixed" % i
 
 
+def test_merged_scatter_group_reads_the_matrix_once(spw, mats):
+    # four 2-column A x requests on a wide matrix (the scatter direction) queued
+    # while paused: one group, one pass over the matrix for all 8 columns, and
+    # every column equal bit for bit to a lone single-vector product
+    for mi in (0, 1):
+        fmt, A, storage, M = mats[mi]
+        S = spw.Server(start_paused=1)
+        h = S.register(M)
+        dt = torch.float32 if storage else torch.float64
+        xs = [torch.from_numpy(synth.vector(M.n * 2, 50 + i, 3).reshape(M.n, 2)).to(dt).cuda() for i in range(4)]
+        ys = [torch.full((M.m, 2), float("nan"), dtype=dt, device="cuda") for _ in range(4)]
+        tickets = [S.submit(h, spw.SPW_OP_MV, x, y) for x, y in zip(xs, ys)]
+        S.resume()
+        for t in tickets:
+            S.wait(t)
+        st = S.stats()
+        S.close()
+        assert st["groups"] == 1 and st["merged_requests"] == 4 and st["passes"] == 1, st
+        for x, y in zip(xs, ys):
+            for c in range(2):
+                ref = M.mv(x[:, c].contiguous())
+                torch.cuda.synchronize()
+                assert torch.equal(y[:, c].contiguous(), ref), (mi, c)
+
+
 def test_budget(spw, mats):
+    # registration grows each matrix's scratch to 8 columns; measure after that
+    S0 = spw.Server()
+    for *_, M in mats:
+        S0.register(M)
+    S0.close()
     sizes = [M.info()["device_bytes"] for *_, M in mats]
     S = spw.Server(hbm_budget_bytes=sizes[0] + sizes[1] // 2)
     assert S.register(mats[0][3]) == 0
