@@ -1,0 +1,463 @@
+// Multi-RHS column dots for gfx950: the tiled kernel (one chunk per wave,
+// column lanes x position sub-groups), its zone reduction and the launch glue
+// of the k-column products that run it (spw_mv_batch / spw_vtm_batch with
+// the tiled plan).  Shared helpers: spw_device.h.
+#include "spw_device.h"
+
+namespace spw {
+namespace {
+
+// ------------------------------------------------------------------------
+// Multi-RHS column dots, tiled: U = C^T V for 2 <= k <= 64 right-hand sides.
+// One wave per 1,024-position chunk.  Lane g*L + c is column lane c (L = k
+// rounded up to a power of two) of sub-group g (S = 64/L sub-groups), and
+// sub-group g walks positions [g*16L, (g+1)*16L) of the chunk in batches of 8
+// (layout lanes g*L .. g*L+L-1 of the interleaved storage; the L lanes of a
+// sub-group read the same words).  Column boundaries come from the
+// column-start bits as in the single-vector kernel, with sub-groups in place
+// of lanes: a sub-group's interior columns are final, its first and last runs
+// are joined across sub-groups by the segmented scan, and chunk-cut columns
+// leave k-wide carries.  V is row-major (leading dimension ldv): the L lanes of
+// a sub-group read one contiguous row segment per item, so every v gather
+// touches one or two cache lines.  Products are fused multiply-adds.  Loads
+// run ahead of the arithmetic: indices two batches ahead, values and v
+// entries one batch ahead, across chunk boundaries.
+// ------------------------------------------------------------------------
+template <typename IdxT> struct Idx8;            // indices of items half*8 .. half*8+7 of one layout lane
+template <> struct Idx8<uint16_t> {
+    uint32_t w[4];
+    __device__ __forceinline__ void load(const uint16_t *cb, int ll, int half)
+    {
+        const u32x4_t q = *reinterpret_cast<const u32x4_t *>(cb + (int64_t)(half * 64 + ll) * 8);
+        w[0] = q.x;
+        w[1] = q.y;
+        w[2] = q.z;
+        w[3] = q.w;
+    }
+    __device__ __forceinline__ int get(int j) const { return (int)((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu); }
+};
+template <> struct Idx8<int32_t> {
+    uint32_t w[8];
+    __device__ __forceinline__ void load(const int32_t *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const u32x4_t q = *reinterpret_cast<const u32x4_t *>(cb + (int64_t)((half * 2 + p) * 64 + ll) * 4);
+            w[4 * p] = q.x;
+            w[4 * p + 1] = q.y;
+            w[4 * p + 2] = q.z;
+            w[4 * p + 3] = q.w;
+        }
+    }
+    __device__ __forceinline__ int get(int j) const { return (int)w[j]; }
+};
+template <typename ValT> struct Val8;           // values of items half*8 .. half*8+7 of one layout lane
+template <> struct Val8<double> {
+    double a[8];
+    __device__ __forceinline__ void load(const double *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const f64x2_t q = *reinterpret_cast<const f64x2_t *>(cb + (int64_t)((half * 4 + p) * 64 + ll) * 2);
+            a[2 * p] = q.x;
+            a[2 * p + 1] = q.y;
+        }
+    }
+    __device__ __forceinline__ double get(int j) const { return a[j]; }
+};
+template <> struct Val8<float> {
+    float a[8];
+    __device__ __forceinline__ void load(const float *cb, int ll, int half)
+    {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const f32x4_t q = *reinterpret_cast<const f32x4_t *>(cb + (int64_t)((half * 2 + p) * 64 + ll) * 4);
+            a[4 * p] = q.x;
+            a[4 * p + 1] = q.y;
+            a[4 * p + 2] = q.z;
+            a[4 * p + 3] = q.w;
+        }
+    }
+    __device__ __forceinline__ double get(int j) const { return (double)a[j]; }
+};
+template <> struct Val8<Bf16> {
+    uint32_t w[4];
+    __device__ __forceinline__ void load(const Bf16 *cb, int ll, int half)
+    {
+        const u32x4_t q =
+            *reinterpret_cast<const u32x4_t *>(reinterpret_cast<const uint16_t *>(cb) + (int64_t)(half * 64 + ll) * 8);
+        w[0] = q.x;
+        w[1] = q.y;
+        w[2] = q.z;
+        w[3] = q.w;
+    }
+    __device__ __forceinline__ double get(int j) const
+    {
+        return bf16_bits_to_f64((w[j >> 1] >> ((j & 1) * 16)) & 0xFFFFu);
+    }
+};
+
+// BS consecutive items of one layout lane: part p holds items p*BS .. p*BS+BS-1.
+template <typename IdxT, int BS> struct IdxB;
+template <typename IdxT> struct IdxB<IdxT, 8> {
+    Idx8<IdxT> r;
+    __device__ __forceinline__ void load(const IdxT *cb, int ll, int part) { r.load(cb, ll, part); }
+    __device__ __forceinline__ int get(int j) const { return r.get(j); }
+};
+template <typename IdxT> struct IdxB<IdxT, 16> {
+    IdxRaw<IdxT, 16> r;
+    __device__ __forceinline__ void load(const IdxT *cb, int ll, int) { r.load(cb, ll); }
+    __device__ __forceinline__ int get(int j) const { return r.get(j); }
+};
+template <typename ValT, int BS> struct ValB;
+template <typename ValT> struct ValB<ValT, 8> {
+    Val8<ValT> a;
+    __device__ __forceinline__ void load(const ValT *cb, int ll, int part) { a.load(cb, ll, part); }
+    __device__ __forceinline__ double get(int j) const { return a.get(j); }
+};
+template <typename ValT> struct ValB<ValT, 16> {
+    ValRaw<ValT, 16> a;
+    __device__ __forceinline__ void load(const ValT *cb, int ll, int) { a.load(cb, ll); }
+    __device__ __forceinline__ double get(int j) const { return a.get(j); }
+};
+
+template <typename VecT, int BS> struct TileGather {
+    VecT gv[BS];                // v at the rows of the batch's items
+    uint32_t m;                 // column-start bits of the batch's items
+};
+
+#ifndef SPW_TILE_BS
+#define SPW_TILE_BS 8
+#endif
+constexpr int TILE_BS = SPW_TILE_BS;            // positions per batch
+
+constexpr int TILE_BLOCK = 256;
+
+template <typename IdxT, typename ValT, typename VecT, int L, int BS = TILE_BS>
+__global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
+    const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
+    const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
+    const VecT *__restrict__ V, int64_t ldv, VecT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
+{
+    constexpr int S = WAVE / L;                   // sub-groups per wave
+    constexpr int PPL = 16 / BS;                  // batches per layout lane
+    constexpr int NB = L * PPL;                   // batches per sub-group and chunk
+    constexpr int SPAN = 16 * L;                  // positions per sub-group
+    constexpr int WCH = 1024;
+    constexpr int NW = TILE_BLOCK / WAVE;
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int g = lane / L, cl = lane % L;
+    const bool colok = cl < k;
+    const int vc = min(cl, k - 1);                // idle lanes read a valid column
+    const int64_t nw = (int64_t)gridDim.x * NW;
+    const int64_t chunk0 = (int64_t)blockIdx.x * NW + wave;
+    if (chunk0 >= nchunks) return;
+    const int64_t nchunk_w = (nchunks - 1 - chunk0) / nw + 1;     // chunks of this wave
+    const int64_t nq = nchunk_w * NB;                              // batches of this wave
+    const int64_t clast = chunk0 + (nchunk_w - 1) * nw;
+
+    auto chunk_of = [&](int64_t q) __attribute__((always_inline)) { return chunk0 + (q / NB) * nw; };
+    auto load_idx = [&](IdxB<IdxT, BS> &R, uint32_t &m, int64_t q) __attribute__((always_inline)) {
+        q = min(q, nq - 1);
+        const int64_t cc = chunk_of(q);
+        const int b = (int)(q % NB), ll = g * L + b / PPL, part = b % PPL;
+        R.load(idx + cc * WCH, ll, part);
+        m = ((uint32_t)heads[cc * WAVE + ll] >> (part * BS)) & ((1u << BS) - 1u);
+    };
+    auto load_val = [&](ValB<ValT, BS> &A, int64_t q) __attribute__((always_inline)) {
+        q = min(q, nq - 1);
+        const int64_t cc = chunk_of(q);
+        const int b = (int)(q % NB);
+        A.load(val + cc * WCH, g * L + b / PPL, b % PPL);
+    };
+    auto gather = [&](TileGather<VecT, BS> &G, const IdxB<IdxT, BS> &R, uint32_t m) __attribute__((always_inline)) {
+#pragma unroll
+        for (int j = 0; j < BS; ++j) G.gv[j] = V[(int64_t)R.get(j) * ldv + vc];
+        G.m = m;
+    };
+
+    // per-chunk walk state; the next chunk's description and column-start
+    // bits are loaded one chunk ahead
+    int4 ci = make_int4(0, 0, 0, 0), ci_n = cinfo[chunk0];
+    uint32_t mask_n = heads[chunk0 * WAVE + lane];
+    int base = 0, rel = 0, hk = 0, my_n = 0, s = 0, e = 0;
+    double run = 0.0, head_sum = 0.0;
+    bool multi = false;
+    int64_t cc = chunk0;
+
+    auto column = [&](int q) __attribute__((always_inline)) -> int64_t {
+        return (ci.w & CHUNK_DENSE) ? (int64_t)ci.x + q : (int64_t)segcol[ci.y + q];
+    };
+    auto emit = [&](int q, double value) __attribute__((always_inline)) {
+        if (!colok) return;
+        const bool before = q == 0 && !(ci.w & CHUNK_START_HEAD);
+        const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
+        if (before) carry[(2 * cc) * k + cl] = value;
+        else if (after) carry[(2 * cc + 1) * k + cl] = value;
+        else U[column(q) * ldu + cl] = (VecT)value;
+    };
+    auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
+        cc = c;
+        ci = ci_n;
+        const uint32_t mask = mask_n;
+        {
+            const int64_t cn = min(c + nw, clast);
+            ci_n = cinfo[cn];
+            mask_n = heads[cn * WAVE + lane];
+        }
+        s = (int)(c * WCH);
+        e = (int)min((int64_t)s + WCH, nnz);
+        // first segment of each sub-group: column starts after position s in
+        // earlier layout lanes, plus its own first position
+        const uint32_t after_s = lane == 0 ? (mask & ~1u) : mask;
+        const int cnt = __popc(after_s);
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int t = __shfl_up(incl, off, WAVE);
+            if (lane >= off) incl += t;
+        }
+        const int first_ll = g * L;
+        const int excl = __shfl(incl - cnt, first_ll, WAVE);
+        const uint32_t m0 = (uint32_t)__shfl((int)mask, first_ll, WAVE);
+        base = excl + (g > 0 ? (int)(m0 & 1u) : 0);
+        my_n = max(0, min(SPAN, e - (s + g * SPAN)));
+        rel = 0;
+        run = 0.0;
+        head_sum = 0.0;
+        multi = false;
+    };
+    auto chunk_end = [&]() __attribute__((always_inline)) {
+        const int klast = my_n > 0 ? base + rel : -2 - g;
+        const int hkey = my_n > 0 ? (multi ? base + hk : klast) : -2 - g;
+        SegPair x{run, klast};
+#pragma unroll
+        for (int off = 1; off < S; off <<= 1) {
+            const double ps = __shfl_up(x.s, off * L, WAVE);
+            const int pk = __shfl_up(x.k, off * L, WAVE);
+            if (g >= off) x = seg_op(SegPair{ps, pk}, x);
+        }
+        double prev_s = 0.0;
+        int prev_k = -1, next_hk = -1;
+        if (S > 1) {
+            prev_s = __shfl_up(x.s, L, WAVE);
+            prev_k = __shfl_up(x.k, L, WAVE);
+            next_hk = __shfl_down(hkey, L, WAVE);
+        }
+        if (my_n > 0) {
+            if (multi) {
+                double tot = head_sum;
+                if (g > 0 && prev_k == hkey) tot = prev_s + head_sum;
+                emit(hkey, tot);
+            }
+            if (g == S - 1 || next_hk != klast) emit(klast, x.s);
+        }
+    };
+    auto compute = [&](int64_t q, const ValB<ValT, BS> &A, const TileGather<VecT, BS> &G) __attribute__((always_inline)) {
+        const int b = (int)(q % NB);
+        if (b == 0) chunk_start(chunk_of(q));
+#pragma unroll
+        for (int j = 0; j < BS; ++j) {
+            const int t = b * BS + j;
+            if (t < my_n) {
+                if (t > 0 && ((G.m >> j) & 1u)) {
+                    if (!multi) {
+                        head_sum = run;
+                        hk = rel;
+                        multi = true;
+                    } else {
+                        if (colok) U[column(base + rel) * ldu + cl] = (VecT)run;   // column wholly inside
+                    }
+                    ++rel;
+                    run = 0.0;
+                }
+                run = __fma_rn(A.get(j), (double)G.gv[j], run);
+            }
+        }
+        if (b == NB - 1) chunk_end();
+    };
+
+    ValB<ValT, BS> A0, A1;
+    IdxB<IdxT, BS> R0, R1;
+    uint32_t m0 = 0, m1 = 0;
+    TileGather<VecT, BS> G0, G1;
+    load_idx(R0, m0, 0);
+    load_val(A0, 0);
+    load_idx(R1, m1, 1);
+    gather(G0, R0, m0);
+    // step q: values of q+1, indices of q+2, gathers of q+1, then batch q
+    for (int64_t q = 0;; q += 2) {
+        load_val(A1, q + 1);
+        load_idx(R0, m0, q + 2);
+        gather(G1, R1, m1);
+        compute(q, A0, G0);
+        if (q + 1 >= nq) break;
+        load_val(A0, q + 2);
+        load_idx(R1, m1, q + 3);
+        gather(G0, R0, m0);
+        compute(q + 1, A1, G1);
+        if (q + 2 >= nq) break;
+    }
+}
+
+// Multi-RHS zone reduction: one lane per (zone, right-hand side).
+template <typename VoutT>
+__global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
+                                 const int32_t *__restrict__ zlast, int64_t nz, int k,
+                                 const double *__restrict__ carry, VoutT *__restrict__ U, int64_t ldu)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= nz * k) return;
+    const int64_t z = g / k;
+    const int cc = (int)(g - z * k);
+    const int a = zfirst[z], b = zlast[z];
+    double s = carry[(2 * (int64_t)a + 1) * k + cc];
+    for (int c = a + 1; c <= b; ++c) s += carry[(2 * (int64_t)c) * k + cc];
+    U[(int64_t)zcol[z] * ldu + cc] = (VoutT)s;
+}
+
+template <typename VoutT>
+__global__ void zero_cols_batch(const int32_t *__restrict__ cols, int64_t count, int k, VoutT *__restrict__ U,
+                                int64_t ldu)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= count * k) return;
+    const int64_t i = g / k;
+    U[(int64_t)cols[i] * ldu + (g - i * k)] = (VoutT)0;
+}
+
+// Renumber the rows of a k-wide block: out[r*ldo + c] = in[inv[r]*ldv + c].
+template <typename VinT>
+__global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k, const VinT *__restrict__ in,
+                            int64_t ldv, VinT *__restrict__ out, int64_t ldo)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    const int cc = (int)(g - r * k);
+    out[r * ldo + cc] = in[(int64_t)inv[r] * ldv + cc];
+}
+
+}  // namespace
+
+namespace {
+template <typename IdxT, typename ValT, typename VecT>
+int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
+                hipStream_t stream)
+{
+    int L = 2;
+    while (L < k) L <<= 1;
+    const int cus = device_cu_count(A.device);
+    const int64_t want = (C.zp.n_chunks + TILE_BLOCK / WAVE - 1) / (TILE_BLOCK / WAVE);
+    // persistent: as many workgroups as the chip keeps resident
+    auto per_cu = [](const void *kern) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, TILE_BLOCK, 0) != hipSuccess || nb < 1) {
+            (void)hipGetLastError();
+            nb = 1;
+        }
+        return nb;
+    };
+#define SPW_TILE_CASE(LL)                                                                                           \
+    case LL: {                                                                                                      \
+        static const int nb = per_cu((const void *)cdot_tile<IdxT, ValT, VecT, LL>);                               \
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));        \
+        hipLaunchKernelGGL((cdot_tile<IdxT, ValT, VecT, LL>), dim3(grid), dim3(TILE_BLOCK), 0, stream,              \
+                           (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,         \
+                           C.d_segcol, C.nnz, C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);                   \
+        break;                                                                                                      \
+    }
+    switch (L) {
+        SPW_TILE_CASE(2)
+        SPW_TILE_CASE(4)
+        SPW_TILE_CASE(8)
+        SPW_TILE_CASE(16)
+        SPW_TILE_CASE(32)
+        SPW_TILE_CASE(64)
+    default: return (int)hipErrorInvalidValue;
+    }
+#undef SPW_TILE_CASE
+    return (int)hipGetLastError();
+}
+
+template <typename ValT, typename VecT>
+int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VecT *V,
+                       int64_t ldv, VecT *U, int64_t ldu, hipStream_t stream)
+{
+    int e;
+    if (C.n_empty > 0) {
+        ProfScope ps(stream, "zero_cols_batch");
+        hipLaunchKernelGGL(zero_cols_batch<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
+                           C.d_empty, C.n_empty, k, U, ldu);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    if (C.nnz == 0) return 0;
+    {
+        ProfScope ps(stream, "cdot_tile");
+        const VecT *Vin = V;
+        int64_t ldin = ldv;
+        if (inv) {
+            // rows padded to the tile width, so that every gathered row starts
+            // on a multiple of its size (a 12-wide binary64 row would straddle
+            // two 128-byte lines half of the time)
+            const int32_t L = coldot_tile_width(k);
+            if (A.scratch.kcap < L) return (int)hipErrorInvalidValue;
+            VecT *vp = reinterpret_cast<VecT *>(A.scratch.vperm);
+            hipLaunchKernelGGL(gather_rows<VecT>, dim3(blocks_for(C.rows * k, 256)), dim3(256), 0, stream, inv,
+                               C.rows, k, V, ldv, vp, (int64_t)L);
+            if ((e = (int)hipGetLastError())) return e;
+            Vin = vp;
+            ldin = L;
+        }
+        e = C.idx_kind == IdxKind::U16 ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream)
+                                       : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream);
+        if (e) return e;
+    }
+    if (C.n_zones > 0) {
+        ProfScope ps(stream, "zone_fixup_batch");
+        hipLaunchKernelGGL(zone_fixup_batch<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+                           C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
+        if ((e = (int)hipGetLastError())) return e;
+    }
+    return 0;
+}
+}  // namespace
+
+int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream)
+{
+    if (k < 1 || k > 64) return (int)hipErrorNotSupported;
+    if (C.cols == 0) return 0;
+    return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
+        using ValT = decltype(vt);
+        using VecT = decltype(xt);
+        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
+                                              (hipStream_t)stream);
+    });
+}
+
+template <typename T>
+__global__ void zero_fill_rows(T *__restrict__ out, int64_t rows, int k, int64_t ld)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    out[r * ld + (g - r * k)] = (T)0;
+}
+
+int launch_zero_fill(spw_dtype vdt, int32_t k, void *out, int64_t ld, int64_t rows, void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (rows <= 0) return 0;
+    if (vdt == SPW_F64)
+        hipLaunchKernelGGL(zero_fill_rows<double>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, (double *)out,
+                           rows, (int)k, ld);
+    else
+        hipLaunchKernelGGL(zero_fill_rows<float>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, (float *)out,
+                           rows, (int)k, ld);
+    return (int)hipGetLastError();
+}
+
+}  // namespace spw
