@@ -54,6 +54,9 @@ CACHE_COUNTERS = ("TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
                  "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver --no-small")
 SOLVER_STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_cgls_wide_2e8.txt")
+SERVING_BUSY_FILE = os.path.join(ROOT, "profiles", "serving_busy_64_matrices.txt")
+SERVING_BUSY_COMMAND = ("rocprofv3 --kernel-trace -f csv -d <dir> -- python3 bench.py --serving-only "
+                        "--serving-requests 4000 --serving-loads 1.5")
 SOLVER_STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 3 --warmup 1 "
                         "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-small")
 
@@ -92,24 +95,64 @@ def percentile(xs, q):
     return xs[i]
 
 
+def host_cpu():
+    """Model name of this host's CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
 def cpu_baseline(A, x, v, budget_s: float = 20.0):
-    """The oracle, untuned, single-threaded, on this host: as many full mv+vtm
-    pairs over the same matrix as fit about `budget_s` seconds (at least one)."""
+    """The oracle, untuned, single-threaded and pinned to one core of this
+    host: as many full mv+vtm pairs over the same matrix as fit about
+    `budget_s` seconds (at least one)."""
     import oracle
-    t_pairs = []
-    t0 = time.perf_counter()
-    while True:
-        t = time.perf_counter()
-        oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x)
-        oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v)
-        t_pairs.append(time.perf_counter() - t)
-        if time.perf_counter() - t0 + t_pairs[-1] > budget_s or len(t_pairs) >= 20:
-            break
+    model, ncpu, allowed = host_cpu()
+    keep = os.sched_getaffinity(0)
+    core = min(keep)
+    os.sched_setaffinity(0, {core})
+    try:
+        t_pairs = []
+        t0 = time.perf_counter()
+        while True:
+            t = time.perf_counter()
+            oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x)
+            oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v)
+            t_pairs.append(time.perf_counter() - t)
+            if time.perf_counter() - t0 + t_pairs[-1] > budget_s or len(t_pairs) >= 20:
+                break
+    finally:
+        os.sched_setaffinity(0, keep)
     t_med = sorted(t_pairs)[len(t_pairs) // 2]
     pair_bytes = 2 * model_bytes(A.m, A.n, A.nnz)
     return {"value": round(pair_bytes / t_med / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": "%d full y=Ax + u^T=v^T A pairs over the same %d-nonzero matrix, single thread, "
-                      "median pair %.3f s" % (len(t_pairs), A.nnz, t_med)}
+            "sample": "%d full y=Ax + u^T=v^T A pairs over the same %d-nonzero matrix, single thread pinned to "
+                      "core %d, median pair %.3f s" % (len(t_pairs), A.nnz, core, t_med),
+            "host_cpu": model, "host_nproc": ncpu, "host_cores_allowed": allowed}
+
+
+def read_stream_ceiling(dev, gib: int = 4, reps: int = 5):
+    """The library's bandwidth probe over `gib` GiB: read-only stream and copy."""
+    import torch
+    from paper_1812_00904_amd.spw import spw_probe_bandwidth
+    n = (gib << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    r_ms, c_ms = spw_probe_bandwidth(src, dst, reps)
+    nbytes = n * 8
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"kernel": "bw_probe_read / bw_probe_copy", "bytes": nbytes, "read_ms": round(r_ms, 4),
+            "read_GBps": round(nbytes / (r_ms * 1e-3) / 1e9, 1), "copy_ms": round(c_ms, 4),
+            "copy_GBps_read_plus_write": round(2 * nbytes / (c_ms * 1e-3) / 1e9, 1)}
 
 
 def time_pairs(M, xd, vd, yd, ud, steps, warmup, per_step=True):
@@ -177,6 +220,10 @@ def main():
                     help="summarize a rocprofv3 --pmc run with CACHE_COUNTERS of --profile-run and exit")
     ap.add_argument("--solver-stats-summary", metavar="DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats run of SOLVER_STATS_COMMAND and exit")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving section (for a kernel trace of the server) and print its result")
+    ap.add_argument("--serving-busy-summary", metavar="DIR",
+                    help="rocprofv3 --kernel-trace output of SERVING_BUSY_COMMAND -> GPU busy time of the server")
     ap.add_argument("--stats-summary", metavar="DIR",
                     help="rocprofv3 --kernel-trace --stats output directory -> kernel statistics summary")
     args = ap.parse_args()
@@ -189,6 +236,8 @@ def main():
         return summarize_stats(args.solver_stats_summary, solver=True)
     if args.cache_summary:
         return summarize_cache(args.cache_summary)
+    if args.serving_busy_summary:
+        return summarize_serving_busy(args.serving_busy_summary)
     if args.gpus != 1:
         print("bench.py: the library runs on one GPU; --gpus %d is not supported (sharding a matrix "
               "over several GPUs is not implemented)" % args.gpus, file=sys.stderr)
@@ -203,6 +252,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.serving_only:
+        print(json.dumps({"serving": bench_serving(args)}), flush=True)
+        return
     t = time.perf_counter()
     A = synth.config_matrix("c1", scale=args.scale)
     x, v = synth.config_vectors("c1", A.m, A.n)
@@ -287,6 +339,18 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr_val,
                 "algorithmic_bytes_per_launch": one_op, "avg_launch_us": round(dom_us, 2),
                 "launches_timed": launches}
+    # the same launches against the bytes the stored format has to move (the
+    # 60 % target is stated on the algorithmic model above)
+    if dom == "vtm_wave":
+        stored = (A.nnz * (8 + info["index_bytes"]) + info["n_chunks"] * (64 * 2 + 16)
+                  + 8 * (A.m + A.n))
+        roofline["stored_format_bytes_per_launch"] = stored
+        roofline["stored_format_frac"] = round(stored / (dom_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["target_basis"] = "algorithmic byte model (ABI: 4-byte indices and pointers)"
+    ceiling = read_stream_ceiling(dev)
+    roofline["read_stream_ceiling_GBps"] = ceiling["read_GBps"]
+    roofline["frac_of_read_ceiling"] = round(achieved / ceiling["read_GBps"], 4)
+    print("[bench] read-stream ceiling %s" % ceiling, file=sys.stderr, flush=True)
 
     extra = {"kernels": kernels, "kernels_from": "a profiled pass of the same steps before the timed one",
              "latency_ms": {"mv_p50": round(percentile(mv_ms, 50), 4), "mv_p99": round(percentile(mv_ms, 99), 4),
@@ -298,7 +362,8 @@ def main():
                                           "index_bytes", "relabeled", "device_bytes")},
              "generate_s": round(gen_s, 2), "create_s": round(create_s, 2),
              "inputs": "%d different x and v taken in turn" % NROT,
-             "pair_same_vectors_GBps": round(pair_bytes / (same_ms / args.steps * 1e-3) / 1e9, 1)}
+             "pair_same_vectors_GBps": round(pair_bytes / (same_ms / args.steps * 1e-3) / 1e9, 1),
+             "read_stream_ceiling": ceiling}
     if traffic:
         extra["traffic_summary"] = os.path.relpath(TRAFFIC_FILE, ROOT)
 
@@ -550,17 +615,23 @@ def bench_batched(args):
     """Multi-RHS blocks on the batching matrix (m=20,000, n=5e6, ~5e7 nonzeros):
     one fused pass for k right-hand sides against k plain single-vector calls,
     binary64 (values and vectors) and binary32 (values and vectors), both
-    directions.  Each row names the kernel plan the library picks for that k."""
+    directions.  The matrix is created with the autotuner on: creation times
+    the column-dot chunk size and workgroup size, and the first call of each
+    (direction, k) times the multi-RHS plans on its own buffers (that call is
+    not in the timings).  Each row names the tuned choices."""
     import torch
     import synth
-    from paper_1812_00904_amd import SPW_CSC, SPW_F32, SpwMatrix
+    from paper_1812_00904_amd import SPW_CSC, SPW_F32, SPW_F64, SPW_OP_MV, SPW_OP_VTM, SpwMatrix
     A = synth.config_matrix("c2", scale=args.scale)
     res = {"workload": "wide CSC m=%d n=%d nnz=%d (Zipf(1.1) lengths + 100 half-dense columns, Zipf(0.8) rows)"
                        % (A.m, A.n, A.nnz), "rows": []}
     for dtype, sx in ((torch.float64, 8), (torch.float32, 4)):
-        M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val,
+        t_create = time.perf_counter()
+        M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, autotune=1, transpose=1,
                       **({} if sx == 8 else {"value_storage": SPW_F32}))
+        t_create = time.perf_counter() - t_create
         info = M.info()
+        vdt = SPW_F64 if sx == 8 else SPW_F32
         for k in (1, 4, 16, 64):
             X = torch.rand((A.n, k), dtype=dtype, device="cuda") * 2 - 1
             V = torch.rand((A.m, k), dtype=dtype, device="cuda") * 2 - 1
@@ -571,6 +642,11 @@ def bench_batched(args):
             ys = [torch.empty(A.m, dtype=dtype, device="cuda") for _ in range(k)]
             us = [torch.empty(A.n, dtype=dtype, device="cuda") for _ in range(k)]
             reps = 3
+            t_tune = time.perf_counter()
+            M.mv_batch(X, Y)          # first calls: the plans are timed here
+            M.vtm_batch(V, U)
+            torch.cuda.synchronize()
+            t_tune = time.perf_counter() - t_tune
             t_mv = _time(lambda: M.mv_batch(X, Y), reps)
             t_vtm = _time(lambda: M.vtm_batch(V, U), reps)
 
@@ -585,7 +661,11 @@ def bench_batched(args):
             t_pvtm = _time(plain_vtm, reps)
             by = model_bytes(A.m, A.n, A.nnz, k=k, sv=sx, sx=sx)
             by1 = model_bytes(A.m, A.n, A.nnz, k=1, sv=sx, sx=sx)
-            row = {"dtype": "f64" if sx == 8 else "f32", "k": k, "plan": batch_plan(info, k),
+            pmv, _ = M.batch_plan(SPW_OP_MV, vdt, k)
+            pvtm, _ = M.batch_plan(SPW_OP_VTM, vdt, k)
+            row = {"dtype": "f64" if sx == 8 else "f32", "k": k,
+                   "plan": batch_plan(info, k, pmv, pvtm, sx), "create_with_tuning_s": round(t_create, 2),
+                   "first_calls_with_tuning_s": round(t_tune, 3),
                    "mv_batch_ms": round(t_mv, 4), "vtm_batch_ms": round(t_vtm, 4),
                    "mv_plain_k_calls_ms": round(t_pmv, 4), "vtm_plain_k_calls_ms": round(t_pvtm, 4),
                    "mv_batch_GBps": round(by / (t_mv * 1e-3) / 1e9, 1),
@@ -813,26 +893,32 @@ def bench_serving(args):
     return res
 
 
-def batch_plan(info, k):
-    """The kernel configuration the library uses for a k-wide block (its fixed rule)."""
+def batch_plan(info, k, plan_mv, plan_vtm, sx):
+    """The kernel configuration a k-wide block runs with (the tuned plan per
+    direction, the tuned column-dot chunk and workgroup sizes)."""
     L = 2
     while L < k:
         L *= 2
-    tile = ("chunks of 1024 nonzeros, one chunk per wave: %d column lanes x %d position sub-groups of %d "
-            "nonzeros, batches of 8, 256-thread workgroups" % (L, 64 // L, 16 * L))
-    if k < 16:
-        mv = ("scatter over %d column(s) in launches of up to 8: %d row panel(s) of %d rows in LDS, %d workgroup "
-              "ranges x 4 waves per column, blocks of 1024 nonzeros"
-              % (k, info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
-    else:
-        mv = "column dots over the kept transpose: " + tile
+    chunk = info["chunk_nnz"]
+    wg = info["wg_size_f64"] if sx == 8 else info["wg_size_f32"]
+    def tile(ch):
+        return ("tiled column dots: chunks of %d nonzeros, one chunk per wave, %d column lanes x %d position "
+                "sub-groups of %d nonzeros, batches of 8, 256-thread workgroups" % (ch, L, 64 // L, (ch // 64) * L))
+    scatter = ("scatter product: %d row panel(s) of %d rows in LDS, %d workgroup ranges x 4 waves per column, "
+               "blocks of 1024 nonzeros" % (info["n_panels"], info["panel_rows"], info["mv_workgroups"]))
+    names = {1: "single", 2: "passes", 3: "tile"}
     if k == 1:
-        vtm = "column dots: chunks of 1024 nonzeros, one wave per chunk, persistent workgroups"
-    elif k <= 6:
-        vtm = "column dots, chunk loaded once and reduced per column: chunks of 1024 nonzeros, one wave per chunk"
+        mv, vtm = scatter, ("column dots: chunks of %d nonzeros, one wave per chunk, %d-thread workgroups"
+                            % (chunk, wg))
     else:
-        vtm = "column dots: " + tile
-    return {"mv": mv, "vtm": vtm, "chunk_nnz": info["chunk_nnz"]}
+        mv = {1: "%d single-column passes of the " % k + scatter,
+              2: "passes of up to 8 columns of the " + scatter,
+              3: tile(1024) + ", over the kept transpose"}[plan_mv]
+        vtm = {1: "%d single-column passes of the column dots (chunks of %d)" % (k, chunk),
+               2: "column-dot passes of up to 8 columns, each chunk (of %d) loaded once per pass" % chunk,
+               3: tile(chunk)}[plan_vtm]
+    return {"mv": mv, "vtm": vtm, "mv_plan": names.get(plan_mv, "single"), "vtm_plan": names.get(plan_vtm, "single"),
+            "chunk_nnz": chunk, "coldot_wg_size": wg, "tuned": bool(info["tuned"])}
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str):
@@ -920,6 +1006,58 @@ def summarize_cache(pmc_dir: str):
             out.append("%s_LDS_bank_conflict_pct_of_active=%.1f" % (name, 100.0 * bc / act))
     os.makedirs(os.path.dirname(CACHE_FILE), exist_ok=True)
     with open(CACHE_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def summarize_serving_busy(trace_dir: str):
+    """From the kernel trace of a serving-only run (SERVING_BUSY_COMMAND): the
+    span of the last offered load (the server's run follows the plain path's),
+    the share of it during which at least one kernel ran, and the idle gaps
+    between kernels.  A persistent kernel pulling work from a device ring can
+    only remove the idle share, so this bounds what it would gain."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no kernel_trace.csv under %s" % trace_dir)
+    ev = []
+    with open(files[0]) as fh:
+        for r in csv.DictReader(fh):
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    ev.sort()
+    # the plain path's run and the server's run are separated by the largest
+    # idle gap of the trace's second half (setup and the plain run come first)
+    half = ev[len(ev) // 2:]
+    cut, gap = 0, -1
+    for (s0, e0, _), (s1, e1, _) in zip(half, half[1:]):
+        if s1 - e0 > gap:
+            gap, cut = s1 - e0, s1
+    served = [e for e in ev if e[0] >= cut]
+    start, end = served[0][0], max(e[1] for e in served)
+    busy, cur_s, cur_e = 0, served[0][0], served[0][1]
+    gaps = []
+    for s_, e_, _ in served[1:]:
+        if s_ > cur_e:
+            busy += cur_e - cur_s
+            gaps.append(s_ - cur_e)
+            cur_s, cur_e = s_, e_
+        else:
+            cur_e = max(cur_e, e_)
+    busy += cur_e - cur_s
+    span = end - start
+    gaps.sort()
+    pick = lambda q: gaps[min(len(gaps) - 1, int(q * (len(gaps) - 1)))] / 1e3 if gaps else 0.0
+    out = ["# GPU busy time of the server at 1.5x the plain path's capacity (64 resident matrices, the",
+           "# serving workload's request stream), from a rocprofv3 kernel trace of the serving section alone.",
+           "# command: %s ; python3 bench.py --serving-busy-summary <dir>" % SERVING_BUSY_COMMAND,
+           "kernel_source_sha256_16=%s" % kernel_hash(),
+           "server_kernels %d" % len(served),
+           "server_span_ms %.3f" % (span / 1e6),
+           "gpu_busy_ms %.3f" % (busy / 1e6),
+           "gpu_busy_fraction %.4f" % (busy / max(span, 1)),
+           "idle_gaps %d" % len(gaps),
+           "idle_gap_us p50 %.2f p90 %.2f p99 %.2f max %.2f" % (pick(0.5), pick(0.9), pick(0.99), pick(1.0)),
+           "idle_total_ms %.3f" % (sum(gaps) / 1e6)]
+    with open(SERVING_BUSY_FILE, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 

@@ -75,8 +75,10 @@ typedef struct spw_matrix_s *spw_matrix;
  *                   (BF16 directly from binary64, no double rounding); a value
  *                   that overflows the storage type is SPW_ERR_BAD_MATRIX.
  *                   Products promote stored values exactly to binary64.
- *   chunk_nnz     : nonzeros per column-dot chunk (0 = automatic; this version
- *                   supports only its default, 1024).
+ *   chunk_nnz     : nonzeros per column-dot chunk: 0 = automatic (1024, or the
+ *                   tuner's choice with autotune), 512 or 1024; any other value is
+ *                   SPW_ERR_UNSUPPORTED.  Smaller chunks give small matrices more
+ *                   workers (Section II's P grows as the chunk shrinks).
  *   relabel       : -1 automatic, 0 off, 1 on.  On: rows are renumbered inside
  *                   the library by descending nonzero count, so the most used
  *                   entries of the short vector share cache lines; results are
@@ -99,7 +101,26 @@ typedef struct spw_matrix_s *spw_matrix;
  *                   inside a column (row) and, in spw_create_coo, repeated
  *                   (row, column) pairs; 1 sorts each column (row) by index and
  *                   sums the values of a repeated index in the order they were
- *                   given.  Indices out of range are rejected either way. */
+ *                   given.  Indices out of range are rejected either way.
+ *   wg_size       : threads per workgroup of the single-vector column dots (v^T A
+ *                   of a CSC matrix, A x of a CSR one): 0 = automatic (512, or 1024
+ *                   for binary32 vectors with binary32 / bfloat16 values, or the
+ *                   tuner's choice), 256, 512 or 1024 (1024 only takes effect
+ *                   with binary32 vectors and 4- or 2-byte values; 512 is used
+ *                   otherwise).  Smaller workgroups run two to a CU.  Results are
+ *                   bit-identical whatever the workgroup size (it only changes
+ *                   which wave reduces which chunk); the chunk size moves the
+ *                   chunk boundaries, so columns cut by them can round
+ *                   differently (both within the stated bounds).
+ *   autotune      : 0 (default) off.  1: at creation, time the column dots for
+ *                   every chunk size and workgroup size not fixed above (binary64
+ *                   and binary32 vectors) and keep the fastest; on the first
+ *                   multi-RHS call of each (direction, vector type, k) not under
+ *                   graph capture, time the multi-RHS plans (spw_plan) on the
+ *                   caller's own buffers and stream (that call synchronizes the
+ *                   stream) and keep the fastest.  Choices are recorded per matrix
+ *                   fingerprint in the tuning cache (spw_tune_cache_path), and a
+ *                   recorded choice is taken without timing. */
 typedef struct {
     uint32_t struct_size;
     spw_dtype value_storage;
@@ -111,7 +132,9 @@ typedef struct {
     int32_t transpose;
     spw_partition partition;
     int32_t canonicalize;
-    int32_t reserved[5];
+    int32_t wg_size;
+    int32_t autotune;
+    int32_t reserved[3];
 } spw_create_opts;
 
 /* Read-only description of a created matrix. */
@@ -137,6 +160,10 @@ typedef struct {
     int64_t workers;              /* P: workers of the single-vector column dots (waves) */
     int64_t worker_max_nnz;       /* nonzeros owned by the busiest / idlest of them; the paper's */
     int64_t worker_min_nnz;       /* imbalance is P * (max - min) / nnz (Section VI) */
+    int32_t wg_size_f64;          /* column-dot workgroup size used with binary64 vectors */
+    int32_t wg_size_f32;          /* ... and with binary32 vectors */
+    int32_t tuned;                /* 1: chunk and workgroup sizes came from the tuner (timed or cached) */
+    uint64_t fingerprint;         /* the key of the matrix's tuning-cache records */
 } spw_matrix_info;
 
 /* ---------------------------------------------------------------- matrices */
@@ -179,6 +206,8 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *out);
 
 /* --------------------------------------------------------------- products */
 
+typedef enum { SPW_OP_MV = 0 /* y := A x */, SPW_OP_VTM = 1 /* u^T := v^T A */ } spw_op;
+
 /* Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
  * stream); results are valid once the stream reaches the end of the call's
  * work.  A matrix's scratch serves one stream at a time: a product or solver
@@ -211,6 +240,32 @@ spw_status spw_mv_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *X, i
 /* V: device, row-major m x k (ldv >= k); U: device, row-major n x k (ldu >= k). */
 spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, int64_t ldv,
                          void *U, int64_t ldu, void *stream);
+
+/* How a multi-RHS call (k >= 2) runs.  Every plan gives each column within the
+ * binary64 / binary32 bounds of the oracle; SINGLE and PASSES give every
+ * column bit-identical to a single-vector call on it.
+ *   SPW_PLAN_AUTO   : the library's rule, or the tuner's choice (autotune)
+ *   SPW_PLAN_SINGLE : k passes of the single-vector kernels, one per column
+ *   SPW_PLAN_PASSES : passes of up to 8 columns that each read the matrix once
+ *                     (column dots with one chunk load per pass, or the
+ *                     scatter product with one partial-sum slot per column)
+ *   SPW_PLAN_TILE   : the tiled column dots, all k columns in one pass; for the
+ *                     scatter direction (A x of a CSC matrix, v^T A of a CSR
+ *                     one) they run over the kept transpose
+ * The fixed rule: scatter direction PASSES below k = 16 (or without a kept
+ * transpose), TILE from 16; column-dot direction PASSES up to k = 6, TILE
+ * above.  Column dots with an output leading dimension of 2^18 or more always
+ * take TILE. */
+typedef enum { SPW_PLAN_AUTO = 0, SPW_PLAN_SINGLE = 1, SPW_PLAN_PASSES = 2, SPW_PLAN_TILE = 3 } spw_plan;
+
+/* The plan a k-column call of op with vector type vdt takes now (never
+ * SPW_PLAN_AUTO); *tuned = 1 when it was chosen by timing (or set, or read
+ * from the tuning cache).  Host only; does not tune. */
+spw_status spw_batch_plan(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan *plan, int32_t *tuned);
+/* Fixes the plan of k-column calls of op with vector type vdt on this matrix
+ * (SPW_PLAN_AUTO returns to the rule / tuner).  SPW_ERR_UNSUPPORTED for
+ * SPW_PLAN_TILE in the scatter direction when the transpose is not kept. */
+spw_status spw_set_batch_plan(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan plan);
 
 /* ------------------------------------------------------------- a solver */
 
@@ -261,8 +316,6 @@ spw_status spw_cgls(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t
  * inputs and the scatter product's partial sums -- grows to 8 columns at
  * registration) is charged to the server's HBM budget. */
 typedef struct spw_server_s *spw_server;
-
-typedef enum { SPW_OP_MV = 0 /* y := A x */, SPW_OP_VTM = 1 /* u^T := v^T A */ } spw_op;
 
 /* Zero-initialise and set struct_size, or call spw_serve_opts_default. */
 typedef struct {
@@ -341,6 +394,27 @@ spw_status spw_serve_destroy(spw_server s);
 
 /* ---------------------------------------------------------- host-only helpers */
 
+/* Tuning cache (the autotuner's records; see spw_create_opts.autotune).  A
+ * record is (matrix fingerprint, key, value); keys are 1..63 printable
+ * characters without blanks.  Records live in memory for the process and, when
+ * a cache file is set, in that file (text: a header line, then one
+ * "<16 hex digits> <key> <value>" line per record, rewritten whole after each
+ * new record).  The environment variable SPW_TUNE_CACHE names the file unless
+ * spw_tune_cache_path is called first.
+ *   spw_tune_cache_path  : use `path` (NULL: memory only) and load its records
+ *   spw_tune_cache_clear : forget the records held in memory (not the file)
+ *   spw_tune_cache_put   : record a value (SPW_ERR_DEVICE if the file cannot be written)
+ *   spw_tune_cache_get   : *found = 1 and *value when recorded, else *found = 0
+ *   spw_matrix_fingerprint : the key spw_create uses for a matrix: a 64-bit FNV-1a
+ *                   hash of format, value storage, shape and 4,097 evenly spaced
+ *                   entries of ptr and of idx (values do not enter it). */
+spw_status spw_tune_cache_path(const char *path);
+spw_status spw_tune_cache_clear(void);
+spw_status spw_tune_cache_put(uint64_t fingerprint, const char *key, int32_t value);
+spw_status spw_tune_cache_get(uint64_t fingerprint, const char *key, int32_t *value, int32_t *found);
+spw_status spw_matrix_fingerprint(spw_format fmt, spw_dtype storage, int64_t m, int64_t n, int64_t nnz,
+                                  const int64_t *ptr, const int32_t *idx, uint64_t *out);
+
 /* Rounds n binary64 values the way spw_create stores them for `storage`
  * (nearest, ties to even) and returns them promoted back to binary64, so that
  * a caller can form the exact matrix a product uses.  in/out are host arrays
@@ -378,6 +452,21 @@ typedef struct {
     double total_ms;
 } spw_profile_entry;
 spw_status spw_profile_read(spw_profile_entry *entries, int32_t cap, int32_t *count);
+
+/* ------------------------------------------------------------ bandwidth probe */
+
+/* The HBM ceilings the products are measured against, with the library's
+ * own kernels: a read-only stream over `bytes` of device memory at src
+ * (16-byte non-temporal loads, eight in flight per thread, four 512-thread
+ * workgroups per CU) and, when dst is not NULL, a copy of the same bytes to
+ * dst.  One untimed run, then `reps` timed runs (HIP events on `stream`); the
+ * medians go to *read_ms and *copy_ms.  Nothing is written to src; dst
+ * receives the copy.  src and dst are device buffers of at least `bytes`,
+ * 16-byte aligned; bytes is a positive multiple of 16.  Waits for the stream.
+ * Errors: SPW_ERR_INVALID_ARG, SPW_ERR_OUT_OF_MEMORY (an 8-KB result buffer),
+ * SPW_ERR_DEVICE. */
+spw_status spw_probe_bandwidth(const void *src, void *dst, int64_t bytes, int32_t reps, double *read_ms,
+                               double *copy_ms, void *stream);
 
 /* ----------------------------------------------------------------- errors */
 

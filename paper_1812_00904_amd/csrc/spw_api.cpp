@@ -110,6 +110,29 @@ void free_all(spw_matrix_s *A)
     A->allocations.clear();
 }
 
+// Frees one device buffer of the matrix and forgets it.
+void free_one(spw_matrix_s &A, void *p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < A.allocations.size(); ++i)
+        if (A.allocations[i].first == p) {
+            A.device_bytes -= A.allocations[i].second;
+            A.allocations.erase(A.allocations.begin() + (long)i);
+            break;
+        }
+    (void)hipFree(p);
+}
+
+// Frees the device arrays of a column-dot storage and resets it.
+void free_coldot(spw_matrix_s &A, ColDot &C)
+{
+    for (void *p : {C.d_idx, C.d_val, (void *)C.d_empty, (void *)C.d_zone_col, (void *)C.d_zone_first,
+                    (void *)C.d_zone_last, (void *)C.d_wchunks, (void *)C.d_heads, (void *)C.d_cinfo,
+                    (void *)C.d_segcol})
+        free_one(A, p);
+    C = ColDot();
+}
+
 spw_status validate(int64_t outer, int64_t inner, int64_t nnz, const int64_t *ptr, const int32_t *idx,
                     const char *outer_name)
 {
@@ -307,7 +330,7 @@ spw_status release_stream(spw_matrix_s &A, void *stream, const char *fname)
 // Column-dot storage of a rows x cols CSC matrix (ptr over columns, rows[]
 // already in the numbering the kernel will use).
 spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, const int64_t *ptr,
-                        const int32_t *rowi, const double *val, spw_dtype storage)
+                        const int32_t *rowi, const double *val, spw_dtype storage, int64_t chunk)
 {
     const int64_t nnz = ptr[cols];
     C.rows = rows;
@@ -315,7 +338,7 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
     C.nnz = nnz;
     C.idx_kind = rows <= 65536 ? IdxKind::U16 : IdxKind::I32;
     spw_status st;
-    const int64_t WCH = vtm_chunk_default(), ITEMS = WCH / 64;
+    const int64_t WCH = chunk, ITEMS = WCH / 64;
     const int64_t zpad = round_up(std::max<int64_t>(nnz, 1), 4096);
     // Chunk-interleaved copies: inside each chunk of W = 64*I positions, item i
     // of lane l (position l*I + i) is stored at ((i/G)*64 + l)*G + i%G, G being
@@ -423,7 +446,7 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
 // more, and reduces the chunks whose first position lies in its columns.
 spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_partition part)
 {
-    const int64_t nch = C.zp.n_chunks, P = vtm_workers(A.device, nch), W = vtm_chunk_default();
+    const int64_t nch = C.zp.n_chunks, P = vtm_workers(A.device, nch), W = C.zp.chunk;
     C.n_workers = P;
     C.worker_max_nnz = C.worker_min_nnz = 0;
     if (nch == 0) return SPW_OK;
@@ -699,7 +722,9 @@ spw_status grow_scratch(spw_matrix_s &A, int32_t k)
         if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows, "partial sums")))
             return st;
     }
-    if (A.scratch.kcap >= k) return SPW_OK;
+    const int64_t nch = std::max<int64_t>(A.cd.zp.n_chunks, A.cdt.zp.n_chunks);
+    if (A.scratch.kcap >= k && A.scratch.carry_chunks >= nch) return SPW_OK;
+    k = std::max<int32_t>(k, A.scratch.kcap);
     // grow the k-wide buffers: free the old ones once the device is idle
     auto drop = [&](double *&p) {
         if (!p) return;
@@ -721,10 +746,160 @@ spw_status grow_scratch(spw_matrix_s &A, int32_t k)
     drop(A.scratch.carry);
     drop(A.scratch.vperm);
     A.scratch.kcap = 0;
-    const int64_t nch = std::max<int64_t>(A.cd.zp.n_chunks, A.cdt.zp.n_chunks);
+    A.scratch.carry_chunks = 0;
     if ((st = dev_alloc(A, &A.scratch.carry, std::max<int64_t>(2 * nch, 1) * k, "carries"))) return st;
     if ((st = dev_alloc(A, &A.scratch.vperm, std::max<int64_t>(A.rows, 1) * k, "renumbered vector"))) return st;
     A.scratch.kcap = k;
+    A.scratch.carry_chunks = nch;
+    return SPW_OK;
+}
+
+// ------------------------------------------------------------------ tuner
+namespace {
+
+// Median time in ms of `reps` runs of fn on stream s, after `warm` untimed
+// runs; fn returns a HIP error code.  *err receives the first error.
+template <typename F>
+double time_median(hipStream_t s, F &&fn, int warm, int reps, int *err)
+{
+    *err = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        *err = (int)hipErrorOutOfMemory;
+        return 0.0;
+    }
+    std::vector<float> t;
+    for (int i = 0; i < warm + reps && !*err; ++i) {
+        if (i >= warm) (void)hipEventRecord(e0, s);
+        *err = fn();
+        if (*err) break;
+        if (i >= warm) {
+            (void)hipEventRecord(e1, s);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                *err = (int)hipGetLastError();
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t.push_back(ms);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (*err || t.empty()) return 0.0;
+    std::sort(t.begin(), t.end());
+    return (double)t[t.size() / 2];
+}
+
+const char *vdt_tag(spw_dtype vdt) { return vdt == SPW_F64 ? "f64" : "f32"; }
+
+}  // namespace
+
+// The host arrays a column-dot storage is built from (kept by spw_create
+// while it runs, so the tuner can build other chunk sizes).
+struct ColdotSource {
+    int64_t rows, cols;
+    const int64_t *ptr;
+    const int32_t *rowi;
+    const double *val;
+};
+
+// Chooses the column-dot chunk size and the workgroup size per vector type
+// by timing spw_vtm-shaped column dots (u = B^T v) on scratch vectors, or
+// takes the choices recorded for this matrix's fingerprint.  fixed_chunk /
+// fixed_wg (non-zero) are the caller's and are not varied.  On return A.cd
+// holds the storage of the chosen chunk size.
+spw_status tune_coldot(spw_matrix_s &A, const ColdotSource &src, int32_t fixed_chunk, int32_t fixed_wg)
+{
+    spw_status st;
+    const bool small_vals = A.value_storage != SPW_F64;
+    auto wg_ok = [&](int32_t w, bool f32) { return w == 256 || w == 512 || (w == 1024 && f32 && small_vals); };
+    auto use_chunk = [&](int64_t chunk) -> spw_status {
+        if (A.cd.zp.chunk == chunk) return SPW_OK;
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SPW_ERR_DEVICE, "spw_create: device error while tuning");
+        }
+        free_coldot(A, A.cd);
+        spw_status s2 = build_coldot(A, A.cd, src.rows, src.cols, src.ptr, src.rowi, src.val, A.value_storage, chunk);
+        if (!s2) s2 = plan_workers(A, A.cd, src.ptr, SPW_PART_NONZERO);
+        if (!s2) s2 = grow_scratch(A, 1);
+        return s2;
+    };
+    int32_t rc = 0, r64 = 0, r32 = 0;
+    if (tune_get(A.fingerprint, "coldot.chunk", &rc) && tune_get(A.fingerprint, "coldot.wg.f64", &r64) &&
+        tune_get(A.fingerprint, "coldot.wg.f32", &r32) && vtm_chunk_supported(rc) && wg_ok(r64, false) &&
+        wg_ok(r32, true) && (fixed_chunk == 0 || fixed_chunk == rc)) {
+        if ((st = use_chunk(rc))) return st;
+        A.vtm_block[0] = fixed_wg ? fixed_wg : r64;
+        A.vtm_block[1] = fixed_wg ? fixed_wg : r32;
+        A.tuned = 1;
+        return SPW_OK;
+    }
+    // scratch vectors: v (rows entries), u (cols entries), 8 bytes each
+    void *dv = nullptr, *du = nullptr;
+    hipStream_t s = nullptr;
+    if (hipMalloc(&dv, (size_t)std::max<int64_t>(A.rows, 1) * 8) != hipSuccess ||
+        hipMalloc(&du, (size_t)std::max<int64_t>(A.cols, 1) * 8) != hipSuccess ||
+        hipMemset(dv, 0, (size_t)std::max<int64_t>(A.rows, 1) * 8) != hipSuccess ||
+        hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        if (dv) (void)hipFree(dv);
+        if (du) (void)hipFree(du);
+        return fail(SPW_ERR_OUT_OF_MEMORY, "spw_create: no device memory for tuning");
+    }
+    struct Release {
+        void *a, *b;
+        hipStream_t s;
+        ~Release()
+        {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+            (void)hipFree(a);
+            (void)hipFree(b);
+        }
+    } rel{dv, du, s};
+    std::vector<int64_t> chunks = fixed_chunk ? std::vector<int64_t>{fixed_chunk} : std::vector<int64_t>{1024, 512};
+    std::vector<int32_t> w64 = fixed_wg ? std::vector<int32_t>{fixed_wg} : std::vector<int32_t>{256, 512};
+    std::vector<int32_t> w32 = fixed_wg ? std::vector<int32_t>{fixed_wg} : std::vector<int32_t>{256, 512};
+    if (!fixed_wg && small_vals) w32.push_back(1024);
+    double best = -1.0;
+    int64_t best_chunk = A.cd.zp.chunk;
+    int32_t best64 = w64[0], best32 = w32[0];
+    int err = 0;
+    for (int64_t ch : chunks) {
+        if ((st = use_chunk(ch))) return st;
+        for (int32_t w : w64) {
+            A.vtm_block[0] = w;
+            const double t = time_median(s, [&] { return launch_vtm(A, SPW_F64, dv, du, s); }, 2, 5, &err);
+            if (err) return fail(SPW_ERR_DEVICE, "spw_create: a kernel failed while tuning");
+            if (best < 0 || t < best) {
+                best = t;
+                best_chunk = ch;
+                best64 = w;
+            }
+        }
+    }
+    if ((st = use_chunk(best_chunk))) return st;
+    A.vtm_block[0] = best64;
+    best = -1.0;
+    for (int32_t w : w32) {
+        A.vtm_block[1] = w;
+        const double t = time_median(s, [&] { return launch_vtm(A, SPW_F32, dv, du, s); }, 2, 5, &err);
+        if (err) return fail(SPW_ERR_DEVICE, "spw_create: a kernel failed while tuning");
+        if (best < 0 || t < best) {
+            best = t;
+            best32 = w;
+        }
+    }
+    A.vtm_block[1] = best32;
+    A.tuned = 1;
+    // a cache file that cannot be written keeps the records in memory
+    (void)tune_put(A.fingerprint, "coldot.chunk", (int32_t)best_chunk);
+    (void)tune_put(A.fingerprint, "coldot.wg.f64", best64);
+    (void)tune_put(A.fingerprint, "coldot.wg.f32", best32);
     return SPW_OK;
 }
 
@@ -868,6 +1043,8 @@ static spw_status spw_create_opts_default_impl(spw_create_opts *o)
     o->panel_rows = 0;
     o->device = -1;
     o->transpose = -1;
+    o->wg_size = 0;
+    o->autotune = 0;
     return SPW_OK;
 }
 
@@ -898,8 +1075,11 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
     if (opts.partition != SPW_PART_NONZERO && opts.partition != SPW_PART_COLUMN)
         return fail(SPW_ERR_INVALID_ARG, "spw_create: bad partition");
     const int64_t chunk = opts.chunk_nnz > 0 ? opts.chunk_nnz : vtm_chunk_default();
-    if (chunk != vtm_chunk_default())
-        return fail(SPW_ERR_UNSUPPORTED, "spw_create: chunk_nnz must be " + std::to_string(vtm_chunk_default()));
+    if (opts.chunk_nnz < 0 || !vtm_chunk_supported(chunk))
+        return fail(SPW_ERR_UNSUPPORTED, "spw_create: chunk_nnz must be 0, 512 or 1024");
+    if (opts.wg_size != 0 && opts.wg_size != 256 && opts.wg_size != 512 && opts.wg_size != 1024)
+        return fail(SPW_ERR_UNSUPPORTED, "spw_create: wg_size must be 0, 256, 512 or 1024");
+    if (opts.autotune != 0 && opts.autotune != 1) return fail(SPW_ERR_INVALID_ARG, "spw_create: autotune must be 0 or 1");
 
     const int64_t rows = fmt == SPW_CSC ? m : n;
     const int64_t cols = fmt == SPW_CSC ? n : m;
@@ -991,7 +1171,10 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
             for (int64_t p = a; p < b; ++p) rowi[(size_t)p] = rl ? rank[(size_t)idx[p]] : idx[p];
         });
     }
-    if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val, A->value_storage))) return st;
+    A->vtm_block[0] = A->vtm_block[1] = opts.wg_size;
+    A->autotune = opts.autotune;
+    A->fingerprint = matrix_fingerprint(fmt, opts.value_storage, m, n, nnz, ptr, idx);
+    if ((st = build_coldot(*A, A->cd, rows, cols, ptr, rowi.data(), val, A->value_storage, chunk))) return st;
     if ((st = plan_workers(*A, A->cd, ptr, A->partition))) return st;
 
     // The transpose (caller's numbering), used by the multi-RHS scatter
@@ -1011,7 +1194,8 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
                     tval[(size_t)dst] = val[p];
                 }
         }
-        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data(), A->value_storage)))
+        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data(), A->value_storage,
+                               vtm_chunk_default())))
             return st;
     }
 
@@ -1020,6 +1204,10 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
         if ((st = build_mv_storage(*A, ptr, rowi.data(), val, opts.panel_rows))) return st;
     }
     if ((st = grow_scratch(*A, 1))) return st;
+    if (opts.autotune && nnz > 0 && rows > 0 && A->partition == SPW_PART_NONZERO) {
+        ColdotSource src{rows, cols, ptr, rowi.data(), val};
+        if ((st = tune_coldot(*A, src, opts.chunk_nnz, opts.wg_size))) return st;
+    }
     if (hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
         return fail(SPW_ERR_DEVICE, "device error during spw_create");
@@ -1155,6 +1343,12 @@ static spw_status spw_info_impl(spw_matrix A, spw_matrix_info *o)
     o->relabeled = A->relabeled;
     o->device = A->device;
     o->device_bytes = A->device_bytes;
+    o->wg_size_f64 = A->vtm_block[0] ? A->vtm_block[0] : 512;
+    o->wg_size_f32 = A->vtm_block[1] ? A->vtm_block[1] : (A->value_storage != SPW_F64 ? 1024 : 512);
+    if (o->wg_size_f32 == 1024 && A->value_storage == SPW_F64) o->wg_size_f32 = 512;
+    if (o->wg_size_f64 == 1024) o->wg_size_f64 = 512;
+    o->tuned = A->tuned;
+    o->fingerprint = A->fingerprint;
     return SPW_OK;
 }
 
@@ -1162,6 +1356,89 @@ spw_status spw_info(spw_matrix A, spw_matrix_info *o)
 {
     return guarded("spw_info", [&] { return spw_info_impl(A, o); });
 }
+
+// ---------------------------------------------------------- multi-RHS plans
+namespace spw {
+namespace {
+
+// The fixed rule (see spw_plan in spw.h).  Scatter direction: passes of up to
+// 8 columns below 16 columns (they beat the tiled column dots over the
+// transpose there, whose gathers of the caller's k-wide rows of X cross cache
+// lines unless k is a power of two), tiles from 16.  Column dots: each chunk
+// read once and reduced per column up to 6 columns, tiles from about 7 on.
+int32_t rule_plan(const spw_matrix_s &A, bool scatter, int32_t k, int64_t ldo)
+{
+    if (scatter) return (k < 16 || !A.cdt.built) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
+    return (k <= 6 && ldo < CHUNK_OUT_LD_LIMIT) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
+}
+
+bool plan_runs(const spw_matrix_s &A, bool scatter, int32_t plan, int64_t ldo)
+{
+    if (plan < SPW_PLAN_SINGLE || plan > SPW_PLAN_TILE) return false;
+    if (scatter) return plan != SPW_PLAN_TILE || A.cdt.built;
+    // the chunk-per-wave column dots address outputs through a 2^31-byte view
+    return plan == SPW_PLAN_TILE || ldo < CHUNK_OUT_LD_LIMIT;
+}
+
+int64_t plan_slot(bool scatter, spw_dtype vdt, int32_t k)
+{
+    return ((int64_t)(scatter ? 1 : 0) << 40) | ((int64_t)vdt << 32) | (int64_t)k;
+}
+
+std::string plan_cache_key(bool scatter, spw_dtype vdt, int32_t k)
+{
+    return std::string("plan.") + (scatter ? "sc." : "cd.") + vdt_tag(vdt) + ".k" + std::to_string(k);
+}
+
+// Runs a k-column product with one plan; returns a HIP error code.
+int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
+             void *out, int64_t ldo, void *stream)
+{
+    const size_t es = vdt == SPW_F64 ? 8 : 4;
+    if (plan == SPW_PLAN_TILE) {
+        if (scatter) {
+            if (A.nnz == 0) return launch_zero_fill(vdt, k, out, ldo, A.rows, stream);   // all outputs are zero
+            return launch_coldot_batch(A, A.cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
+        }
+        return launch_coldot_batch(A, A.cd, A.relabeled ? A.d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
+    }
+    if (plan == SPW_PLAN_SINGLE) {
+        for (int32_t c = 0; c < k; ++c) {
+            const void *ic = (const char *)in + (size_t)c * es;
+            void *oc = (char *)out + (size_t)c * es;
+            const int e = scatter ? launch_mv(A, vdt, 1, ic, ldi, oc, ldo, stream)
+                                  : launch_vtm_cols(A, vdt, 1, &ic, &ldi, &oc, &ldo, stream);
+            if (e) return e;
+        }
+        return 0;
+    }
+    return scatter ? launch_mv(A, vdt, k, in, ldi, out, ldo, stream)
+                   : launch_vtm_multi(A, vdt, k, in, ldi, out, ldo, stream);
+}
+
+// Times every plan that can run on the caller's buffers and stream (the
+// output is overwritten by each) and returns the fastest; 0 on a kernel error.
+int32_t tune_plan(spw_matrix_s &A, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi, void *out,
+                  int64_t ldo, void *stream, int *err)
+{
+    double best = -1.0;
+    int32_t choice = 0;
+    for (int32_t plan : {SPW_PLAN_SINGLE, SPW_PLAN_PASSES, SPW_PLAN_TILE}) {
+        if (!plan_runs(A, scatter, plan, ldo)) continue;
+        const double t = time_median((hipStream_t)stream,
+                                     [&] { return run_plan(A, plan, scatter, vdt, k, in, ldi, out, ldo, stream); },
+                                     1, 3, err);
+        if (*err) return 0;
+        if (best < 0 || t < best) {
+            best = t;
+            choice = plan;
+        }
+    }
+    return choice;
+}
+
+}  // namespace
+}  // namespace spw
 
 static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
                               void *out, int64_t ldo, void *stream, const char *fname)
@@ -1181,36 +1458,103 @@ static spw_status run_product(spw_matrix A, bool want_mv, spw_dtype vdt, int32_t
     spw_status st = claim_stream(*A, stream, fname);
     if (st) return st;
     if ((st = grow_scratch(*A, coldot_tile_width(k)))) return st;
-    int e;
-    if (k == 1 && ldi == 1 && ldo == 1) {
-        e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
-    } else if (scatter && (k < 16 || !A->cdt.built)) {
-        // few right-hand sides (or no transpose kept): scatter launches of up
-        // to 8 columns whose workgroups read A together.  Below 16 columns
-        // these beat the column dots over the transpose, whose gathers of the
-        // caller's k-wide rows of X cross cache lines unless k is a power of two.
-        if ((st = grow_partial_cols(*A, std::min<int32_t>(k, 8)))) return st;
-        e = launch_mv(*A, vdt, k, in, ldi, out, ldo, stream);
-    } else if (scatter) {
-        // k right-hand sides in one pass: column dots over the kept transpose
-        if (A->nnz == 0) {
-            e = launch_zero_fill(vdt, k, out, ldo, A->rows, stream);   // no nonzeros: all outputs are zero
+    int e = 0;
+    if (k == 1) {
+        if (ldi == 1 && ldo == 1) {
+            e = scatter ? launch_mv(*A, vdt, 1, in, 1, out, 1, stream) : launch_vtm(*A, vdt, in, out, stream);
+        } else if (scatter) {
+            e = launch_mv(*A, vdt, 1, in, ldi, out, ldo, stream);
+        } else if (ldo < CHUNK_OUT_LD_LIMIT) {
+            e = launch_vtm_multi(*A, vdt, 1, in, ldi, out, ldo, stream);
         } else {
-            e = launch_coldot_batch(*A, A->cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
+            e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, 1, in, ldi, out, ldo, stream);
         }
-    } else if (k <= 6 && ldo < CHUNK_OUT_LD_LIMIT) {
-        // up to 6 columns: each chunk read once and reduced per column (faster
-        // than the tiled column dots there; the tiles win from about 7 on, and
-        // take any output leading dimension)
-        e = launch_vtm_multi(*A, vdt, k, in, ldi, out, ldo, stream);
     } else {
-        // column dots for k columns in one pass over the matrix
-        e = launch_coldot_batch(*A, A->cd, A->relabeled ? A->d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
+        // the plan: set by the caller or the tuner, recorded for this matrix, timed now, or the fixed rule
+        const int64_t slot = plan_slot(scatter, vdt, k);
+        int32_t plan = 0;
+        {
+            std::lock_guard<std::mutex> lk(A->plan_mu);
+            const auto it = A->plans.find(slot);
+            if (it != A->plans.end()) plan = it->second;
+        }
+        if (!plan_runs(*A, scatter, plan, ldo)) plan = 0;
+        if (!plan && A->autotune) {
+            int32_t rec = 0;
+            if (tune_get(A->fingerprint, plan_cache_key(scatter, vdt, k), &rec) && plan_runs(*A, scatter, rec, ldo))
+                plan = rec;
+            if (scatter && (st = grow_partial_cols(*A, std::min<int32_t>(k, 8)))) return st;
+            if (!plan && !capturing(stream)) {
+                plan = tune_plan(*A, scatter, vdt, k, in, ldi, out, ldo, stream, &e);
+                if (e) return fail(SPW_ERR_DEVICE, std::string(fname) + ": a kernel failed while tuning: " +
+                                                       hipGetErrorString((hipError_t)e));
+                if (plan) (void)tune_put(A->fingerprint, plan_cache_key(scatter, vdt, k), plan);
+            }
+            if (plan) {
+                std::lock_guard<std::mutex> lk(A->plan_mu);
+                A->plans[slot] = plan;
+            }
+        }
+        if (!plan) plan = rule_plan(*A, scatter, k, ldo);
+        if (scatter && plan == SPW_PLAN_PASSES && (st = grow_partial_cols(*A, std::min<int32_t>(k, 8)))) return st;
+        e = run_plan(*A, plan, scatter, vdt, k, in, ldi, out, ldo, stream);
     }
     if (e == (int)hipErrorNotSupported)
         return fail(SPW_ERR_UNSUPPORTED, std::string(fname) + ": this dtype / k / storage combination is not available");
     if (e) return fail(SPW_ERR_DEVICE, std::string(fname) + ": kernel launch failed: " + hipGetErrorString((hipError_t)e));
     return release_stream(*A, stream, fname);
+}
+
+static spw_status batch_plan_impl(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan *plan, int32_t *tuned)
+{
+    if (!A || !plan || !tuned) return fail(SPW_ERR_INVALID_ARG, "spw_batch_plan: NULL argument");
+    if ((op != SPW_OP_MV && op != SPW_OP_VTM) || (vdt != SPW_F64 && vdt != SPW_F32) || k < 1 || k > 64)
+        return fail(SPW_ERR_INVALID_ARG, "spw_batch_plan: bad op, vector type or k");
+    const bool scatter = (A->format == SPW_CSC) == (op == SPW_OP_MV);
+    *tuned = 0;
+    if (k == 1) {
+        *plan = SPW_PLAN_SINGLE;
+        return SPW_OK;
+    }
+    int32_t p = 0;
+    {
+        std::lock_guard<std::mutex> lk(A->plan_mu);
+        const auto it = A->plans.find(plan_slot(scatter, vdt, k));
+        if (it != A->plans.end()) p = it->second;
+    }
+    if (!plan_runs(*A, scatter, p, k)) p = 0;
+    if (!p && A->autotune) {
+        int32_t rec = 0;
+        if (tune_get(A->fingerprint, plan_cache_key(scatter, vdt, k), &rec) && plan_runs(*A, scatter, rec, k)) p = rec;
+    }
+    *tuned = p ? 1 : 0;
+    *plan = (spw_plan)(p ? p : rule_plan(*A, scatter, k, k));
+    return SPW_OK;
+}
+
+spw_status spw_batch_plan(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan *plan, int32_t *tuned)
+{
+    return guarded("spw_batch_plan", [&] { return batch_plan_impl(A, op, vdt, k, plan, tuned); });
+}
+
+static spw_status set_batch_plan_impl(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan plan)
+{
+    if (!A) return fail(SPW_ERR_INVALID_ARG, "spw_set_batch_plan: NULL matrix");
+    if ((op != SPW_OP_MV && op != SPW_OP_VTM) || (vdt != SPW_F64 && vdt != SPW_F32) || k < 2 || k > 64 ||
+        plan < SPW_PLAN_AUTO || plan > SPW_PLAN_TILE)
+        return fail(SPW_ERR_INVALID_ARG, "spw_set_batch_plan: bad op, vector type, k (2..64) or plan");
+    const bool scatter = (A->format == SPW_CSC) == (op == SPW_OP_MV);
+    if (plan == SPW_PLAN_TILE && scatter && !A->cdt.built)
+        return fail(SPW_ERR_UNSUPPORTED, "spw_set_batch_plan: the tiled plan of this direction needs the kept transpose");
+    std::lock_guard<std::mutex> lk(A->plan_mu);
+    if (plan == SPW_PLAN_AUTO) A->plans.erase(plan_slot(scatter, vdt, k));
+    else A->plans[plan_slot(scatter, vdt, k)] = plan;
+    return SPW_OK;
+}
+
+spw_status spw_set_batch_plan(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k, spw_plan plan)
+{
+    return guarded("spw_set_batch_plan", [&] { return set_batch_plan_impl(A, op, vdt, k, plan); });
 }
 
 static spw_status spw_mv_impl(spw_matrix A, spw_dtype vdt, const void *x, void *y, void *stream)

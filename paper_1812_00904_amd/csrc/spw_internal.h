@@ -12,6 +12,7 @@
 
 #include <cstdint>
 #include <exception>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -92,6 +93,7 @@ struct Scratch {
     double *partial_cols = nullptr;   // pcols * mv_wgs * panel_rows (multi-column scatter launches)
     int32_t pcols = 0;
     double *carry = nullptr;      // 2 * max chunks * kcap
+    int64_t carry_chunks = 0;     // the chunk count the carries were sized for
     double *vperm = nullptr;      // rows * kcap elements of 8 bytes (renumbered input of the column dots)
     int32_t kcap = 0;
 };
@@ -110,6 +112,16 @@ struct spw_matrix_s {
     int32_t *d_inv = nullptr;           // rows: internal row -> caller row
 
     spw::ColDot cd;                     // B itself (renumbered rows)
+    // Column-dot workgroup size per vector type ([0] binary64, [1] binary32):
+    // 0 = the default rule, else 256 / 512 / 1024 (wg_size or the tuner's).
+    int32_t vtm_block[2] = {0, 0};
+    int32_t autotune = 0;
+    int32_t tuned = 0;                  // chunk / workgroup sizes from the tuner (timed or cached)
+    uint64_t fingerprint = 0;           // tuning-cache key (spw_tune.cpp)
+    // Multi-RHS plans chosen per (direction, vector type, k): set by the
+    // caller or the tuner (spw_plan values); absent = the fixed rule.
+    std::mutex plan_mu;
+    std::map<int64_t, int32_t> plans;
     spw::ColDot cdt;                    // B^T (caller's numbering), for multi-RHS scatter products
 
     // scatter-product storage: row panels; inside a panel, per workgroup column
@@ -188,6 +200,8 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k);
 int64_t mv_block_nnz();
 int64_t mv_waves();
 int64_t vtm_chunk_default();
+// Column-dot chunk sizes the kernels take (512 or 1,024 nonzeros).
+bool vtm_chunk_supported(int64_t chunk);
 // Waves the single-vector column-dot kernel runs for nchunks chunks on device.
 int64_t vtm_workers(int device, int64_t nchunks);
 int64_t vtm_hot_rows_limit(spw_dtype vdt);
@@ -223,6 +237,14 @@ int64_t cgls_dot_parts();
 bool profile_on();
 void profile_begin(void *stream, const char *name, void **token);
 void profile_end(void *stream, void *token);
+
+// Tuning cache (spw_tune.cpp): fingerprint of a matrix's shape and structure,
+// and the recorded choices.  tune_put returns false if the cache file could
+// not be written (the record stays in memory).
+uint64_t matrix_fingerprint(spw_format fmt, spw_dtype storage, int64_t m, int64_t n, int64_t nnz,
+                            const int64_t *ptr, const int32_t *idx);
+bool tune_get(uint64_t fp, const std::string &key, int32_t *value);
+bool tune_put(uint64_t fp, const std::string &key, int32_t value);
 
 // Error text for the calling thread (spw_api.cpp).
 void set_error(const std::string &msg);

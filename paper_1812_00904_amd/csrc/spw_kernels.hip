@@ -455,52 +455,87 @@ __global__ void gather_tab(const int32_t *__restrict__ inv, int64_t rows, int k,
     out[g] = in.v[c][src * in.ld[c]];
 }
 
+// Resident column-dot workgroups per CU for a workgroup of `block` threads:
+// smaller workgroups run two to a CU (8 waves, as one 512-thread workgroup),
+// each with half the LDS.
+int vtm_wgs_per_cu(int block) { return block >= VTM_BLOCK ? VTM_WG_PER_CU : VTM_BLOCK / block; }
 // LDS of one column-dot workgroup outside the hot rows: the waves' segment
 // stages, for binary64 vectors.
-int64_t vtm_stage_bytes(size_t elem_bytes)
+int64_t vtm_stage_bytes(size_t elem_bytes, int block = VTM_BLOCK)
 {
-    return elem_bytes == 8 ? (int64_t)(VTM_BLOCK / WAVE) * STAGE_STRIDE * (int64_t)sizeof(double) : 0;
+    return elem_bytes == 8 ? (int64_t)(block / WAVE) * STAGE_STRIDE * (int64_t)sizeof(double) : 0;
 }
 // Hot rows of v that fit beside the stages, for k columns of elem_bytes each.
-int64_t hot_rows_limit(size_t elem_bytes, int64_t k)
+int64_t hot_rows_limit(size_t elem_bytes, int64_t k, int block = VTM_BLOCK)
 {
-    return (LDS_BYTES / VTM_WG_PER_CU - 256 - vtm_stage_bytes(elem_bytes)) / ((int64_t)elem_bytes * k);
+    return (LDS_BYTES / vtm_wgs_per_cu(block) - 256 - vtm_stage_bytes(elem_bytes, block)) /
+           ((int64_t)elem_bytes * k);
 }
 
-template <typename IdxT, typename ValT, typename VecT, bool MULTI>
-int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
+// The column-dot workgroup size for a single-vector call: the matrix's choice
+// for the vector type (spw_create_opts.wg_size or the tuner's), else 1,024
+// threads for binary32 vectors with 4- or 2-byte values (few enough registers
+// for 16 waves, which hide more latency) and 512 otherwise.  1,024 needs
+// those types; a column partition keeps 512 (its worker table assumes it).
+template <typename ValT, typename VecT>
+int vtm_block_for(const spw_matrix_s &A, bool colpart)
+{
+    constexpr bool small_regs = sizeof(VecT) == 4 && sizeof(ValT) <= 4;
+    if (colpart) return VTM_BLOCK;
+    int b = A.vtm_block[sizeof(VecT) == 8 ? 0 : 1];
+    if (b == 0) b = small_regs ? VTM_BLOCK_F32 : VTM_BLOCK;
+    if (b == 1024 && !small_regs) b = VTM_BLOCK;
+    return b;
+}
+
+template <int ITEMS, typename IdxT, typename ValT, typename VecT, bool MULTI>
+int launch_vtm_wave_items(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out,
+                          hipStream_t stream)
 {
     const ColDot &C = A.cd;
-    if (C.zp.chunk != vtm_chunk_default()) return (int)hipErrorNotSupported;
-    const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT), k));
-    const size_t lds = (size_t)vtm_stage_bytes(sizeof(VecT)) + (size_t)vhot * k * sizeof(VecT);
     const int cus = device_cu_count(A.device);
     // column partitioning: one wave per worker of the plan (single-vector calls)
     const int32_t *wch = (!MULTI && C.d_wchunks) ? C.d_wchunks : nullptr;
-    auto run = [&](auto kernel, int block) -> int {
+    const int block = MULTI ? VTM_BLOCK : vtm_block_for<ValT, VecT>(A, wch != nullptr);
+    const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT), k, block));
+    const size_t lds = (size_t)vtm_stage_bytes(sizeof(VecT), block) + (size_t)vhot * k * sizeof(VecT);
+    auto run = [&](auto kernel) -> int {
         const int nw = block / WAVE;
         const int64_t wgs_needed = (C.zp.n_chunks + nw - 1) / nw;
         const unsigned grid =
             wch ? (unsigned)(C.n_workers / nw)
-                : (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * VTM_WG_PER_CU, wgs_needed));
+                : (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * vtm_wgs_per_cu(block), wgs_needed));
         hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), lds, stream, (const IdxT *)C.d_idx, (const ValT *)C.d_val,
                            C.d_heads, (const int4 *)C.d_cinfo, C.d_segcol, C.nnz, C.zp.n_chunks, wch, vin, k, vhot,
                            out, A.scratch.carry);
         return (int)hipGetLastError();
     };
     if constexpr (!MULTI && sizeof(VecT) == 4 && sizeof(ValT) <= 4) {
-        // binary32 or bfloat16 values with binary32 vectors, one column: few
-        // enough registers for 16 waves per workgroup, which hide more latency
-        // (the plan's worker table of a column partition assumes VTM_BLOCK)
-        if (!wch) {
-            static const bool attr_w = allow_full_lds(vtm_wave<VTM_BLOCK_F32, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
+        if (block == 1024) {
+            static const bool attr_w = allow_full_lds(vtm_wave<1024, ITEMS, IdxT, ValT, VecT, MULTI>);
             (void)attr_w;
-            return run(vtm_wave<VTM_BLOCK_F32, VTM_ITEMS, IdxT, ValT, VecT, MULTI>, VTM_BLOCK_F32);
+            return run(vtm_wave<1024, ITEMS, IdxT, ValT, VecT, MULTI>);
         }
     }
-    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>);
+    if constexpr (!MULTI) {
+        if (block == 256) {
+            static const bool attr_q = allow_full_lds(vtm_wave<256, ITEMS, IdxT, ValT, VecT, MULTI>);
+            (void)attr_q;
+            return run(vtm_wave<256, ITEMS, IdxT, ValT, VecT, MULTI>);
+        }
+    }
+    static const bool attr = allow_full_lds(vtm_wave<VTM_BLOCK, ITEMS, IdxT, ValT, VecT, MULTI>);
     (void)attr;
-    return run(vtm_wave<VTM_BLOCK, VTM_ITEMS, IdxT, ValT, VecT, MULTI>, VTM_BLOCK);
+    return run(vtm_wave<VTM_BLOCK, ITEMS, IdxT, ValT, VecT, MULTI>);
+}
+
+// Chunks of 1,024 (16 positions per lane) or 512 (8 per lane) nonzeros.
+template <typename IdxT, typename ValT, typename VecT, bool MULTI>
+int launch_vtm_wave(const spw_matrix_s &A, const VecT *vin, int k, const ColOut<VecT> &out, hipStream_t stream)
+{
+    if (A.cd.zp.chunk == 1024) return launch_vtm_wave_items<16, IdxT, ValT, VecT, MULTI>(A, vin, k, out, stream);
+    if (A.cd.zp.chunk == 512) return launch_vtm_wave_items<8, IdxT, ValT, VecT, MULTI>(A, vin, k, out, stream);
+    return (int)hipErrorNotSupported;
 }
 
 template <typename ValT, typename VecT>
@@ -669,6 +704,7 @@ int64_t mv_lds_rows_limit(spw_dtype vdt, int32_t k)
 int64_t mv_block_nnz() { return MV_BLK; }
 int64_t mv_waves() { return MV_BLOCK / WAVE; }
 int64_t vtm_chunk_default() { return (int64_t)WAVE * VTM_ITEMS; }
+bool vtm_chunk_supported(int64_t chunk) { return chunk == 512 || chunk == 1024; }
 int64_t vtm_workers(int device, int64_t nchunks)
 {
     const int64_t nw = VTM_BLOCK / WAVE;

@@ -133,17 +133,18 @@ constexpr int TILE_BS = SPW_TILE_BS;            // positions per batch
 
 constexpr int TILE_BLOCK = 256;
 
-template <typename IdxT, typename ValT, typename VecT, int L, int BS = TILE_BS>
+template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
     const VecT *__restrict__ V, int64_t ldv, VecT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
 {
     constexpr int S = WAVE / L;                   // sub-groups per wave
-    constexpr int PPL = 16 / BS;                  // batches per layout lane
+    constexpr int PPL = ITEMS / BS;               // batches per layout lane
     constexpr int NB = L * PPL;                   // batches per sub-group and chunk
-    constexpr int SPAN = 16 * L;                  // positions per sub-group
-    constexpr int WCH = 1024;
+    constexpr int SPAN = ITEMS * L;               // positions per sub-group
+    constexpr int WCH = WAVE * ITEMS;             // positions per chunk
+    static_assert(ITEMS % BS == 0, "a layout lane holds whole batches");
     constexpr int NW = TILE_BLOCK / WAVE;
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -343,9 +344,9 @@ __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k
 }  // namespace
 
 namespace {
-template <typename IdxT, typename ValT, typename VecT>
-int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
-                hipStream_t stream)
+template <int ITEMS, typename IdxT, typename ValT, typename VecT>
+int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U,
+                      int64_t ldu, hipStream_t stream)
 {
     int L = 2;
     while (L < k) L <<= 1;
@@ -362,9 +363,9 @@ int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, in
     };
 #define SPW_TILE_CASE(LL)                                                                                           \
     case LL: {                                                                                                      \
-        static const int nb = per_cu((const void *)cdot_tile<IdxT, ValT, VecT, LL>);                               \
+        static const int nb = per_cu((const void *)cdot_tile<IdxT, ValT, VecT, LL, ITEMS>);                        \
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));        \
-        hipLaunchKernelGGL((cdot_tile<IdxT, ValT, VecT, LL>), dim3(grid), dim3(TILE_BLOCK), 0, stream,              \
+        hipLaunchKernelGGL((cdot_tile<IdxT, ValT, VecT, LL, ITEMS>), dim3(grid), dim3(TILE_BLOCK), 0, stream,       \
                            (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,         \
                            C.d_segcol, C.nnz, C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);                   \
         break;                                                                                                      \
@@ -380,6 +381,16 @@ int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, in
     }
 #undef SPW_TILE_CASE
     return (int)hipGetLastError();
+}
+
+// Chunks of 1,024 or 512 nonzeros (16 or 8 positions per layout lane).
+template <typename IdxT, typename ValT, typename VecT>
+int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
+                hipStream_t stream)
+{
+    if (C.zp.chunk == 1024) return launch_tile_items<16, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, stream);
+    if (C.zp.chunk == 512) return launch_tile_items<8, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, stream);
+    return (int)hipErrorNotSupported;
 }
 
 template <typename ValT, typename VecT>

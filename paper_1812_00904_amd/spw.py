@@ -38,7 +38,8 @@ class CreateOpts(ctypes.Structure):
                 ("chunk_nnz", ctypes.c_int32), ("relabel", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("panel_rows", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("transpose", ctypes.c_int32), ("partition", ctypes.c_int),
-                ("canonicalize", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("canonicalize", ctypes.c_int32), ("wg_size", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class MatrixInfo(ctypes.Structure):
@@ -50,10 +51,14 @@ class MatrixInfo(ctypes.Structure):
                 ("mv_workgroups", ctypes.c_int64), ("index_bytes", ctypes.c_int64),
                 ("relabeled", ctypes.c_int32), ("device", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
                 ("has_transpose", ctypes.c_int32), ("partition", ctypes.c_int), ("workers", ctypes.c_int64),
-                ("worker_max_nnz", ctypes.c_int64), ("worker_min_nnz", ctypes.c_int64)]
+                ("worker_max_nnz", ctypes.c_int64), ("worker_min_nnz", ctypes.c_int64),
+                ("wg_size_f64", ctypes.c_int32), ("wg_size_f32", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("fingerprint", ctypes.c_uint64)]
 
 
 SPW_OP_MV, SPW_OP_VTM = 0, 1
+SPW_PLAN_AUTO, SPW_PLAN_SINGLE, SPW_PLAN_PASSES, SPW_PLAN_TILE = 0, 1, 2, 3
+PLAN_NAMES = {SPW_PLAN_SINGLE: "single", SPW_PLAN_PASSES: "passes", SPW_PLAN_TILE: "tile"}
 
 
 class ServeOpts(ctypes.Structure):
@@ -98,6 +103,18 @@ SIGNATURES = {
     "spw_mv_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_vtm_batch": (ctypes.c_int, [_VP, ctypes.c_int, _I32, _VP, _I64, _VP, _I64, _VP]),
     "spw_round_values": (ctypes.c_int, [ctypes.c_int, _I64, _VP, _VP]),
+    "spw_batch_plan": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I32, ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(_I32)]),
+    "spw_set_batch_plan": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, _I32, ctypes.c_int]),
+    "spw_probe_bandwidth": (ctypes.c_int, [_VP, _VP, _I64, _I32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), _VP]),
+    "spw_tune_cache_path": (ctypes.c_int, [ctypes.c_char_p]),
+    "spw_tune_cache_clear": (ctypes.c_int, []),
+    "spw_tune_cache_put": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_char_p, _I32]),
+    "spw_tune_cache_get": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_char_p, ctypes.POINTER(_I32),
+                                          ctypes.POINTER(_I32)]),
+    "spw_matrix_fingerprint": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _I64, _I64, _I64, _VP, _VP,
+                                              ctypes.POINTER(ctypes.c_uint64)]),
     "spw_cgls": (ctypes.c_int, [_VP, ctypes.c_int, _VP, _VP, ctypes.c_int32, _VP, _VP]),
     "spw_serve_opts_default": (ctypes.c_int, [ctypes.POINTER(ServeOpts)]),
     "spw_serve_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.POINTER(ServeOpts)]),
@@ -306,6 +323,34 @@ def spw_cgls(h: int, b: torch.Tensor, x: torch.Tensor, iters: int, hist: bool = 
     return out[:iters + 1].copy(), out[iters + 1:].copy()
 
 
+def spw_batch_plan(h: int, op: int, vdt: int, k: int):
+    """(plan, tuned) that a k-column call of op with vector type vdt takes now."""
+    plan, tuned = ctypes.c_int(), _I32()
+    _check(load().spw_batch_plan(h, op, vdt, k, ctypes.byref(plan), ctypes.byref(tuned)))
+    return plan.value, bool(tuned.value)
+
+
+def spw_set_batch_plan(h: int, op: int, vdt: int, k: int, plan: int):
+    _check(load().spw_set_batch_plan(h, op, vdt, k, plan))
+
+
+def spw_probe_bandwidth(src: torch.Tensor, dst: torch.Tensor | None = None, reps: int = 5, stream=None):
+    """Median ms of the library's read-only stream over src (and of a copy into
+    dst when given): (read_ms, copy_ms or None)."""
+    nbytes = src.numel() * src.element_size()
+    if dst is not None and dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    r, c = ctypes.c_double(), ctypes.c_double()
+    _check(load().spw_probe_bandwidth(src.data_ptr(), dst.data_ptr() if dst is not None else None, nbytes, reps,
+                                      ctypes.byref(r), ctypes.byref(c), _stream_ptr(stream)))
+    return r.value, (c.value if dst is not None else None)
+
+
+def spw_tune_cache_path(path: str | None):
+    """Use `path` as the tuning cache file (None: memory only) and load its records."""
+    _check(load().spw_tune_cache_path(path.encode() if path else None))
+
+
 def spw_round_values(storage: int, val) -> np.ndarray:
     """Host-only: the values spw_create stores for `storage`, promoted to float64."""
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -397,6 +442,13 @@ class SpwMatrix:
             U = torch.empty((self.n, V.shape[1]), dtype=V.dtype, device=V.device)
         spw_vtm_batch(self.handle, V, U, stream)
         return U
+
+    def batch_plan(self, op: int, vdt: int, k: int):
+        """(plan, tuned) of a k-column call; see spw_batch_plan."""
+        return spw_batch_plan(self.handle, op, vdt, k)
+
+    def set_batch_plan(self, op: int, vdt: int, k: int, plan: int):
+        spw_set_batch_plan(self.handle, op, vdt, k, plan)
 
     def cgls(self, b: torch.Tensor, x: torch.Tensor, iters: int, hist: bool = True, stream=None):
         """CGLS iterations on min ||b - A x||_2, in place on x; see spw_cgls."""

@@ -335,3 +335,16 @@ def test_binding_rejects_bad_operands_before_launch(spw):
     torch.cuda.synchronize()
     assert bool((y32 == 7.0).all()) and bool((ys == 7.0).all()) and bool((Y == 7.0).all())
     M.close()
+
+
+def test_bandwidth_probe(spw):
+    # the read stream writes nothing; the copy reproduces the source exactly
+    src = torch.arange(3 * (1 << 20) + 2, dtype=torch.float64, device="cuda")   # 16-byte multiple
+    dst = torch.zeros_like(src)
+    before = src.clone()
+    r_ms, c_ms = spw.spw_probe_bandwidth(src, dst, reps=2)
+    torch.cuda.synchronize()
+    assert r_ms > 0 and c_ms > 0
+    assert torch.equal(src, before) and torch.equal(dst, src)
+    with pytest.raises(spw.SpwError):
+        spw.spw_probe_bandwidth(src[1:], None)             # not 16-byte aligned / not a multiple of 16
