@@ -61,9 +61,12 @@ typedef enum { SPW_F64 = 0, SPW_F32 = 1, SPW_BF16 = 2 } spw_dtype;
 /* How the work of one product is divided among the GPU's workers. */
 typedef enum {
     SPW_PART_NONZERO = 0,  /* equal runs of nonzeros (Section II), the default */
-    SPW_PART_COLUMN = 1    /* equal numbers of columns of the long dimension: the column
+    SPW_PART_COLUMN = 1,   /* equal numbers of columns of the long dimension: the column
                               partitioning the paper compares against (Section VI); same
                               results, kept for that comparison */
+    SPW_PART_MERGE = 2     /* merge path: equal runs of (nonzeros + columns), so that
+                              workers whose share holds many short or empty columns
+                              (many outputs to write) take fewer nonzeros */
 } spw_partition;
 
 typedef struct spw_matrix_s *spw_matrix;
@@ -86,17 +89,23 @@ typedef struct spw_matrix_s *spw_matrix;
  *   validate      : 1 (default) checks the arrays in O(nnz); 0 trusts them.
  *   panel_rows    : rows per on-chip accumulation panel for A x (0 = automatic).
  *   device        : HIP device ordinal, -1 = the current device.
- *   partition     : SPW_PART_NONZERO (default) or SPW_PART_COLUMN.  With column
- *                   partitioning each worker of the single-vector products (a wave
- *                   of the column dots, a workgroup of a scatter row panel) owns an
- *                   equal number of consecutive columns, the first `cols mod P`
- *                   workers one more; column dots give bit-identical results in
- *                   either mode, the scatter product the same up to rounding order.
- *   transpose     : -1 (default) or 1 also keeps the transpose, which the
- *                   multi-RHS products of the long-to-short direction (CSC A x,
- *                   CSR v^T A) use for k > 8 (one pass over A for all k
- *                   columns); 0 saves that memory, and those blocks then run
- *                   one scatter pass per column.
+ *   partition     : SPW_PART_NONZERO (default), SPW_PART_COLUMN or SPW_PART_MERGE.
+ *                   With column partitioning each worker of the single-vector
+ *                   products (a wave of the column dots, a workgroup of a scatter
+ *                   row panel) owns an equal number of consecutive columns, the
+ *                   first `cols mod P` workers one more; with merge-path
+ *                   partitioning each owns a consecutive run of about equal
+ *                   (nonzeros + columns): column-dot workers take whole chunks
+ *                   (a chunk costs its nonzeros plus the columns starting in it),
+ *                   scatter workgroups split their panel's column-ordered
+ *                   nonzeros on the merge-path diagonals.  Column dots give
+ *                   bit-identical results in every mode, the scatter product the
+ *                   same up to rounding order.
+ *   transpose     : 1 also keeps the transpose (the column-dot storage of A^T),
+ *                   which the tiled multi-RHS plan of the long-to-short direction
+ *                   (CSC A x, CSR v^T A) reads; 0 does not; -1 (default) keeps it
+ *                   only with autotune (so the tuner can choose that plan).
+ *                   Without it those blocks run scatter passes.
  *   canonicalize  : 0 (default) rejects indices that are not strictly increasing
  *                   inside a column (row) and, in spw_create_coo, repeated
  *                   (row, column) pairs; 1 sorts each column (row) by index and
@@ -282,7 +291,8 @@ spw_status spw_set_batch_plan(spw_matrix A, spw_op op, spw_dtype vdt, int32_t k,
  * equations) has size zero.  The product with A is taken of s_k and q = A p_k
  * formed by linearity, q_k = A s_k + beta_k q_{k-1} (equal in exact
  * arithmetic), so that the update of p and x can run before the product with
- * A^T.  Inner products are summed in a fixed order, so a call is bit-identical
+ * A^T; every 50th iteration takes q_k = A p_k with a product of its own
+ * (after forming p_k), so rounding does not accumulate in that recurrence.  Inner products are summed in a fixed order, so a call is bit-identical
  * from run to run.
  *   vdt   : SPW_F64 (SPW_ERR_UNSUPPORTED otherwise)
  *   b     : device, m binary64 entries (not written)

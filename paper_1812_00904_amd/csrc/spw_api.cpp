@@ -94,9 +94,106 @@ spw_status dev_alloc(spw_matrix_s &A, T **out, int64_t count, const char *what)
     return SPW_OK;
 }
 
+// Copies host arrays to the device in pieces through a ring of pinned
+// staging slots on a stream of its own: put() returns once the last piece is
+// staged (the caller may then free its array), so the copy of one array runs
+// while the host builds the next.  Arrays below one slot, and every array
+// when no pinned memory can be had, are copied synchronously.  finish()
+// waits for every copy; the destructor does too, before the slots go.
+class Uploader {
+public:
+    static constexpr size_t SLOT = (size_t)32 << 20;
+    static constexpr int NSLOT = 4;
+    ~Uploader()
+    {
+        (void)finish();
+        for (int i = 0; i < NSLOT; ++i) {
+            if (ev_[i]) (void)hipEventDestroy(ev_[i]);
+            if (slot_[i]) (void)hipHostFree(slot_[i]);
+        }
+        if (s_) (void)hipStreamDestroy(s_);
+    }
+    spw_status put(void *dst, const void *src, size_t bytes, const char *what)
+    {
+        if (bytes == 0) return SPW_OK;
+        if (bytes < SLOT || !ready()) {
+            if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(SPW_ERR_DEVICE, std::string("hipMemcpy to device failed for ") + what);
+            }
+            return SPW_OK;
+        }
+        for (size_t off = 0; off < bytes; off += SLOT) {
+            const size_t n = std::min(SLOT, bytes - off);
+            const int i = next_;
+            next_ = (next_ + 1) % NSLOT;
+            if (used_[i] && hipEventSynchronize(ev_[i]) != hipSuccess) return device_error(what);
+            // stage the piece with several host threads, then hand it to the DMA engine
+            char *slot = static_cast<char *>(slot_[i]);
+            const char *from = static_cast<const char *>(src) + off;
+            parallel_for((int64_t)n, [&](int64_t a, int64_t b) { std::memcpy(slot + a, from + a, (size_t)(b - a)); });
+            if (hipMemcpyAsync(static_cast<char *>(dst) + off, slot, n, hipMemcpyHostToDevice, s_) != hipSuccess ||
+                hipEventRecord(ev_[i], s_) != hipSuccess)
+                return device_error(what);
+            used_[i] = true;
+        }
+        return SPW_OK;
+    }
+    spw_status finish()
+    {
+        if (s_ && hipStreamSynchronize(s_) != hipSuccess) return device_error("the staged copies");
+        return SPW_OK;
+    }
+
+private:
+    bool ready()
+    {
+        if (tried_) return s_ != nullptr;
+        tried_ = true;
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        for (int i = 0; i < NSLOT; ++i)
+            if (hipHostMalloc(&slot_[i], SLOT, hipHostMallocDefault) != hipSuccess ||
+                hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                s_ = s;   // the destructor releases what was made
+                (void)finish();
+                for (int k = 0; k < NSLOT; ++k) {
+                    if (ev_[k]) (void)hipEventDestroy(ev_[k]);
+                    if (slot_[k]) (void)hipHostFree(slot_[k]);
+                    ev_[k] = nullptr;
+                    slot_[k] = nullptr;
+                }
+                (void)hipStreamDestroy(s);
+                s_ = nullptr;
+                return false;
+            }
+        s_ = s;
+        return true;
+    }
+    spw_status device_error(const char *what)
+    {
+        (void)hipGetLastError();
+        return fail(SPW_ERR_DEVICE, std::string("staged copy to device failed for ") + what);
+    }
+    hipStream_t s_ = nullptr;
+    void *slot_[NSLOT] = {};
+    hipEvent_t ev_[NSLOT] = {};
+    bool used_[NSLOT] = {};
+    int next_ = 0;
+    bool tried_ = false;
+};
+
+// The uploader of the spw_create running on this thread (NULL outside one).
+thread_local Uploader *t_uploader = nullptr;
+
 spw_status h2d(void *dst, const void *src, size_t bytes, const char *what)
 {
     if (bytes == 0) return SPW_OK;
+    if (t_uploader) return t_uploader->put(dst, src, bytes, what);
     if (hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipGetLastError();
         return fail(SPW_ERR_DEVICE, std::string("hipMemcpy to device failed for ") + what);
@@ -444,6 +541,10 @@ spw_status build_coldot(spw_matrix_s &A, ColDot &C, int64_t rows, int64_t cols, 
 // stride).  Column partitioning (Section VI's comparison): worker w owns
 // columns [j0_w, j1_w), equal counts with the first cols mod P workers one
 // more, and reduces the chunks whose first position lies in its columns.
+// Merge-path partitioning: the chunks are cut into P contiguous runs of about
+// equal cost, a chunk costing its nonzeros plus the columns whose start lies
+// in it (empty columns included), so a worker whose chunks hold many short
+// or empty columns (many outputs) gets fewer nonzeros.
 spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_partition part)
 {
     const int64_t nch = C.zp.n_chunks, P = vtm_workers(A.device, nch), W = C.zp.chunk;
@@ -469,6 +570,23 @@ spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_part
     const int64_t cols = C.cols, q = cols / P, big = cols % P;
     std::vector<int32_t> first((size_t)P + 1, (int32_t)nch);
     int64_t mx = -1, mn = -1, j0 = 0, c = 0;
+    if (part == SPW_PART_MERGE) {
+        // prefix cost up to chunk c: its positions plus the columns owned by chunks before it
+        auto cost_before = [&](int64_t cc) -> int64_t { return std::min(cc * W, C.nnz) + C.zp.owned[(size_t)cc]; };
+        const int64_t total = C.nnz + cols;
+        int64_t cc = 0;
+        for (int64_t w = 0; w < P; ++w) {
+            const int64_t target = total * w / P;
+            while (cc < nch && cost_before(cc) < target) ++cc;
+            first[(size_t)w] = (int32_t)cc;
+        }
+        for (int64_t w = 0; w < P; ++w) {
+            const int64_t a = first[(size_t)w], b = first[(size_t)w + 1];
+            const int64_t z = std::min(b * W, C.nnz) - std::min(a * W, C.nnz);
+            mx = mx < 0 ? z : std::max(mx, z);
+            mn = mn < 0 ? z : std::min(mn, z);
+        }
+    } else {
     for (int64_t w = 0; w < P; ++w) {
         const int64_t j1 = j0 + (w < big ? q + 1 : q);
         const int64_t z = ptr[j1] - ptr[j0];
@@ -478,6 +596,7 @@ spw_status plan_workers(spw_matrix_s &A, ColDot &C, const int64_t *ptr, spw_part
         first[(size_t)w] = (int32_t)c;
         while (c < nch && C.zp.jlo[(size_t)c] < j1) ++c;
         j0 = j1;
+    }
     }
     first[(size_t)P] = (int32_t)nch;
     C.worker_max_nnz = mx;
@@ -612,6 +731,25 @@ spw_status build_mv_storage(spw_matrix_s &A, const int64_t *ptr, const int32_t *
                     a = pq[j0];
                     b = pq[j1];
                     j0 = j1;
+                } else if (A.partition == SPW_PART_MERGE) {
+                    // merge path over (columns, nonzeros): range w starts at
+                    // diagonal d = w * (cols + panel nonzeros) / nw; i columns
+                    // and d - i nonzeros lie before it, with i the largest
+                    // count of whole columns that fits
+                    auto split = [&](int64_t ww) -> int64_t {
+                        const int64_t d = (cols + (qb - qa)) * ww / nw;
+                        int64_t lo = 0, hi = cols;        // largest i with (pq[i] - qa) + i <= d
+                        while (lo < hi) {
+                            const int64_t mid = (lo + hi + 1) / 2;
+                            if (pq[mid] - qa + mid <= d) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        const int64_t k = std::min(std::max(d - lo, pq[lo] - qa),
+                                                   (lo < cols ? pq[lo + 1] : pq[cols]) - qa);
+                        return qa + k;
+                    };
+                    a = split(w);
+                    b = split(w + 1);
                 } else {
                     a = qa + (qb - qa) * w / nw;
                     b = qa + (qb - qa) * (w + 1) / nw;
@@ -826,6 +964,7 @@ spw_status tune_coldot(spw_matrix_s &A, const ColdotSource &src, int32_t fixed_c
         spw_status s2 = build_coldot(A, A.cd, src.rows, src.cols, src.ptr, src.rowi, src.val, A.value_storage, chunk);
         if (!s2) s2 = plan_workers(A, A.cd, src.ptr, SPW_PART_NONZERO);
         if (!s2) s2 = grow_scratch(A, 1);
+        if (!s2 && t_uploader) s2 = t_uploader->finish();     // the arrays are on the device before timing
         return s2;
     };
     int32_t rc = 0, r64 = 0, r32 = 0;
@@ -1072,7 +1211,8 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
     }
     if (opts.value_storage != SPW_F64 && opts.value_storage != SPW_F32 && opts.value_storage != SPW_BF16)
         return fail(SPW_ERR_INVALID_ARG, "spw_create: bad value_storage");
-    if (opts.partition != SPW_PART_NONZERO && opts.partition != SPW_PART_COLUMN)
+    if (opts.partition != SPW_PART_NONZERO && opts.partition != SPW_PART_COLUMN &&
+        opts.partition != SPW_PART_MERGE)
         return fail(SPW_ERR_INVALID_ARG, "spw_create: bad partition");
     const int64_t chunk = opts.chunk_nnz > 0 ? opts.chunk_nnz : vtm_chunk_default();
     if (opts.chunk_nnz < 0 || !vtm_chunk_supported(chunk))
@@ -1146,6 +1286,15 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
             if (armed) free_all(a);
         }
     } cleanup{A.get()};
+    // large host-to-device copies go through pinned staging, overlapped with
+    // the host work that follows them; declared after `cleanup`, so it waits
+    // for its copies before the device buffers can be freed
+    Uploader up;
+    struct UploaderScope {
+        Uploader *prev;
+        explicit UploaderScope(Uploader *u) : prev(t_uploader) { t_uploader = u; }
+        ~UploaderScope() { t_uploader = prev; }
+    } up_scope(&up);
 
     spw_status st;
     // Row renumbering by descending count (ties by row), so that the busiest
@@ -1179,7 +1328,7 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
 
     // The transpose (caller's numbering), used by the multi-RHS scatter
     // products: its column dots are the rows of B.
-    if (opts.transpose != 0 && nnz > 0) {
+    if ((opts.transpose > 0 || (opts.transpose < 0 && opts.autotune)) && nnz > 0) {
         std::vector<int64_t> tptr((size_t)rows + 1, 0);
         for (int64_t p = 0; p < nnz; ++p) tptr[(size_t)idx[p] + 1]++;
         for (int64_t r = 0; r < rows; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
@@ -1204,6 +1353,7 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
         if ((st = build_mv_storage(*A, ptr, rowi.data(), val, opts.panel_rows))) return st;
     }
     if ((st = grow_scratch(*A, 1))) return st;
+    if ((st = up.finish())) return st;
     if (opts.autotune && nnz > 0 && rows > 0 && A->partition == SPW_PART_NONZERO) {
         ColdotSource src{rows, cols, ptr, rowi.data(), val};
         if ((st = tune_coldot(*A, src, opts.chunk_nnz, opts.wg_size))) return st;
@@ -1601,6 +1751,9 @@ spw_status spw_vtm_batch(spw_matrix A, spw_dtype vdt, int32_t k, const void *V, 
     return guarded("spw_vtm_batch", [&] { return spw_vtm_batch_impl(A, vdt, k, V, ldv, U, ldu, stream); });
 }
 
+// Iterations between direct products q = A p in the CGLS loop.
+constexpr int64_t CGLS_REFRESH = 50;
+
 static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void *x, int32_t iters, double *hist,
                                 void *stream)
 {
@@ -1639,12 +1792,21 @@ static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void
     };
     // one iteration k: t = A s_k, q_k = t + beta_k q_{k-1} (= A p_k), alpha_k, r_{k+1};
     // p_k = s_k + beta_k p_{k-1}, x_{k+1} = x_k + alpha_k p_k; s_{k+1} = A^T r_{k+1}, gamma_{k+1},
-    // beta_{k+1}.  The first iteration takes q_0 = t and p_0 = s_0.
-    auto iteration = [&](bool first) -> spw_status {
+    // beta_{k+1}.  The first iteration takes q_0 = t and p_0 = s_0.  Every CGLS_REFRESH-th
+    // iteration forms p_k first and takes q_k = A p_k with a product of its own, so the
+    // rounding that the linear recurrence for q gathers is dropped at that point.
+    auto iteration = [&](bool first, bool refresh) -> spw_status {
         spw_status s2;
-        if ((s2 = run_product(A, true, SPW_F64, 1, w.s, 1, w.t, 1, stream, "spw_cgls"))) return s2;   // t = A s
-        if ((s2 = vec(first ? CglsVecOp::ALPHA_R0 : CglsVecOp::ALPHA_R))) return s2;
-        if ((s2 = vec(first ? CglsVecOp::PX0 : CglsVecOp::PX))) return s2;
+        if (refresh) {
+            if ((s2 = vec(CglsVecOp::P))) return s2;                                                   // p = s + beta p
+            if ((s2 = run_product(A, true, SPW_F64, 1, w.p, 1, w.t, 1, stream, "spw_cgls"))) return s2;  // t = A p
+            if ((s2 = vec(CglsVecOp::ALPHA_R0))) return s2;                                            // q = t
+            if ((s2 = vec(CglsVecOp::X))) return s2;
+        } else {
+            if ((s2 = run_product(A, true, SPW_F64, 1, w.s, 1, w.t, 1, stream, "spw_cgls"))) return s2;   // t = A s
+            if ((s2 = vec(first ? CglsVecOp::ALPHA_R0 : CglsVecOp::ALPHA_R))) return s2;
+            if ((s2 = vec(first ? CglsVecOp::PX0 : CglsVecOp::PX))) return s2;
+        }
         if ((s2 = run_product(A, false, SPW_F64, 1, w.r, 1, w.s, 1, stream, "spw_cgls"))) return s2;  // s = A^T r
         return vec(CglsVecOp::GAMMA);
     };
@@ -1657,7 +1819,7 @@ static spw_status spw_cgls_impl(spw_matrix A, spw_dtype vdt, const void *b, void
     // arguments (the history index lives on the device), so a caller may
     // capture a whole call without a history in a graph and replay it.
     for (int64_t k = 1; k <= iters; ++k)
-        if ((st = iteration(k == 1))) return st;
+        if ((st = iteration(k == 1, k > 1 && k % CGLS_REFRESH == 0))) return st;
     if ((st = release_stream(*A, stream, "spw_cgls"))) return st;
     if (hist) {
         if (hipMemcpyAsync(hist, W.hist, (size_t)hl * sizeof(double), hipMemcpyDeviceToHost, (hipStream_t)stream) !=

@@ -226,6 +226,8 @@ enum class CglsVecOp : int {
     ALPHA_R,     // q = t + beta q; alpha = gamma / ||q||^2; r = r - alpha q; rho_k = ||r||^2
     PX0,         // first iteration: p = s; x = x + alpha p
     PX,          // p = s + beta p; x = x + alpha p
+    P,           // p = s + beta p          (an iteration that forms q = A p directly)
+    X,           // x = x + alpha p
     GAMMA        // gamma_k = ||s||^2 (s = A^T r); beta = gamma_k / gamma_{k-1}
 };
 // The history index advances on the device (see spw_solve.hip), so the

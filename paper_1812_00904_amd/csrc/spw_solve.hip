@@ -180,6 +180,24 @@ __global__ __launch_bounds__(SV_BLOCK) void px_step(double *__restrict__ x, doub
     }
 }
 
+// The two halves of px_step for an iteration that forms q = A p directly:
+// p = s + beta p before the product, x = x + alpha p after alpha is known.
+__global__ __launch_bounds__(SV_BLOCK) void p_step(double *__restrict__ p, const double *__restrict__ s, int64_t len,
+                                                   const double *__restrict__ scal)
+{
+    const double beta = scal[S_BETA];
+    const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
+    for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) p[i] = s[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(SV_BLOCK) void x_step(double *__restrict__ x, const double *__restrict__ p, int64_t len,
+                                                   const double *__restrict__ scal)
+{
+    const double alpha = scal[S_ALPHA];
+    const int64_t stride = (int64_t)gridDim.x * SV_BLOCK;
+    for (int64_t i = blockIdx.x * (int64_t)SV_BLOCK + threadIdx.x; i < len; i += stride) x[i] = x[i] + alpha * p[i];
+}
+
 unsigned stream_grid(int64_t len)
 {
     const int64_t g = (len + SV_BLOCK - 1) / SV_BLOCK;
@@ -221,6 +239,12 @@ int launch_cgls_vec(CglsVecOp op, const CglsWork &w, void *stream)
         break;
     case CglsVecOp::PX:         // p = s + beta p, x = x + alpha p
         hipLaunchKernelGGL(px_step<false>, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.s, w.n, w.scal);
+        break;
+    case CglsVecOp::P:          // p = s + beta p
+        hipLaunchKernelGGL(p_step, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.p, w.s, w.n, w.scal);
+        break;
+    case CglsVecOp::X:          // x = x + alpha p
+        hipLaunchKernelGGL(x_step, dim3(stream_grid(w.n)), dim3(SV_BLOCK), 0, st, w.x, w.p, w.n, w.scal);
         break;
     case CglsVecOp::GAMMA:      // gamma_k = ||s||^2, beta
         hipLaunchKernelGGL(sq_part, dim3(DOT_PARTS), dim3(SV_BLOCK), 0, st, w.s, w.n, w.partial);

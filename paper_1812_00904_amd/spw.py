@@ -22,7 +22,7 @@ STATUS_NAMES = ["SPW_OK", "SPW_ERR_INVALID_ARG", "SPW_ERR_BAD_MATRIX", "SPW_ERR_
                 "SPW_ERR_TIMEOUT", "SPW_ERR_SHUTDOWN"]
 SPW_CSC, SPW_CSR = 0, 1
 SPW_F64, SPW_F32, SPW_BF16 = 0, 1, 2
-SPW_PART_NONZERO, SPW_PART_COLUMN = 0, 1
+SPW_PART_NONZERO, SPW_PART_COLUMN, SPW_PART_MERGE = 0, 1, 2
 DTYPES = {SPW_F64: torch.float64, SPW_F32: torch.float32}
 
 

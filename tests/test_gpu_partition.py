@@ -64,3 +64,42 @@ def test_column_partition(spw, case, fmt):
     assert inz["worker_max_nnz"] - inz["worker_min_nnz"] <= 1024
     Mn.close()
     Mc.close()
+
+
+MERGE_CASES = dict(CASES, news20=lambda: synth.news20_shaped(scale=0.15),
+                   news20_sorted=lambda: synth.sort_columns_by_length(synth.news20_shaped(scale=0.15)))
+
+
+@pytest.mark.parametrize("case", sorted(MERGE_CASES))
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_merge_path_partition(spw, case, fmt):
+    # merge-path workers balance nonzeros plus columns: the column dots stay
+    # bit-identical to the nonzero split, the scatter product meets the bar
+    A = MERGE_CASES[case]()
+    m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
+    print("merge partition case %s fmt=%d nnz=%d" % (case, fmt, A.nnz), flush=True)
+    Mn = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=0)
+    Mm = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=0, partition=spw.SPW_PART_MERGE)
+    x = torch.from_numpy(synth.vector(n, 5, 1)).cuda()
+    v = torch.from_numpy(synth.vector(m, 5, 2)).cuda()
+    yn, un = Mn.mv(x), Mn.vtm(v)
+    ym, um = Mm.mv(x), Mm.vtm(v)
+    if fmt == 0:
+        assert torch.equal(un, um)
+    else:
+        assert torch.equal(yn, ym)
+    if fmt == 0:
+        yr, dy = oracle.mv_csc(A.m, A.n, A.ptr, A.idx, A.val, x.cpu().numpy(), with_d=True)
+        ur, du = oracle.vtm_csc(A.m, A.n, A.ptr, A.idx, A.val, v.cpu().numpy(), with_d=True)
+    else:
+        yr, dy = oracle.mv_csr(A.n, A.m, A.ptr, A.idx, A.val, x.cpu().numpy(), with_d=True)
+        ur, du = oracle.vtm_csr(A.n, A.m, A.ptr, A.idx, A.val, v.cpu().numpy(), with_d=True)
+    for got, ref, d in ((ym, yr, dy), (um, ur, du)):
+        g = got.cpu().numpy()
+        assert not np.isnan(g).any()
+        assert np.all(np.abs(g - ref) <= 1e-13 * d)
+    im = Mm.info()
+    assert im["partition"] == 2 and im["workers"] == Mn.info()["workers"]
+    assert 0 <= im["worker_min_nnz"] <= im["worker_max_nnz"] <= A.nnz
+    Mn.close()
+    Mm.close()

@@ -189,3 +189,24 @@ def test_cgls_call_captured_in_a_graph(spw):
         torch.cuda.synchronize()
     del graph
     M.close()
+
+
+@pytest.mark.parametrize("fmt", ["csc", "csr"])
+def test_cgls_long_run_reaches_least_squares(spw, fmt):
+    # 250 iterations (five direct q = A p refreshes): the iterate must sit at
+    # numpy's least-squares solution and at the oracle's, and the recurred
+    # residual norm must match the residual of the returned iterate, so the
+    # recurrences have not drifted
+    B = synth.random_csc(40, 1500, 4.0, 21)
+    code, m, n, D = layout(spw, B, fmt)
+    rng = np.random.default_rng(8)
+    b = rng.uniform(-1, 1, m)
+    x, gamma, rho = run(spw, B, fmt, b, np.zeros(n), 250)
+    xo, go, ro = oracle.cgls(fmt, m, n, B.ptr, B.idx, B.val, b, np.zeros(n), 250)
+    xs = np.linalg.lstsq(D, b, rcond=None)[0]
+    scale = np.max(np.abs(xs))
+    assert np.max(np.abs(x - xs)) <= 1e-9 * scale
+    assert np.max(np.abs(x - xo)) <= 1e-9 * scale
+    r_true = b - D @ x
+    assert abs(rho[-1] - r_true @ r_true) <= 1e-9 * (b @ b)
+    assert np.all(np.isfinite(gamma)) and np.all(np.isfinite(rho))
