@@ -220,6 +220,8 @@ def main():
                     help="summarize a rocprofv3 --pmc run with CACHE_COUNTERS of --profile-run and exit")
     ap.add_argument("--solver-stats-summary", metavar="DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats run of SOLVER_STATS_COMMAND and exit")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the multi-RHS section and print its result")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving section (for a kernel trace of the server) and print its result")
     ap.add_argument("--serving-busy-summary", metavar="DIR",
@@ -254,6 +256,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.serving_only:
         print(json.dumps({"serving": bench_serving(args)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": bench_batched(args)}), flush=True)
         return
     t = time.perf_counter()
     A = synth.config_matrix("c1", scale=args.scale)
