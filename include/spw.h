@@ -114,9 +114,9 @@ typedef struct spw_matrix_s *spw_matrix;
  *   wg_size       : threads per workgroup of the single-vector column dots (v^T A
  *                   of a CSC matrix, A x of a CSR one): 0 = automatic (512, or 1024
  *                   for binary32 vectors with binary32 / bfloat16 values, or the
- *                   tuner's choice), 256, 512 or 1024 (1024 only takes effect
- *                   with binary32 vectors and 4- or 2-byte values; 512 is used
- *                   otherwise).  Smaller workgroups run two to a CU.  Results are
+ *                   tuner's choice), 256, 512 or 1024 (1024 takes effect with
+ *                   chunks of 512, or with binary32 vectors and 4- or 2-byte
+ *                   values; 512 is used otherwise).  Smaller workgroups run two to a CU.  Results are
  *                   bit-identical whatever the workgroup size (it only changes
  *                   which wave reduces which chunk); the chunk size moves the
  *                   chunk boundaries, so columns cut by them can round

@@ -472,19 +472,27 @@ int64_t hot_rows_limit(size_t elem_bytes, int64_t k, int block = VTM_BLOCK)
            ((int64_t)elem_bytes * k);
 }
 
+// Whether the single-vector column dots fit 16 waves per CU (128 registers
+// per lane): binary32 vectors with 4- or 2-byte values, or chunks of 512
+// (8 positions per lane) of any type.
+template <int ITEMS, typename ValT, typename VecT>
+constexpr bool vtm_fits_1024()
+{
+    return (sizeof(VecT) == 4 && sizeof(ValT) <= 4) || ITEMS <= 8;
+}
+
 // The column-dot workgroup size for a single-vector call: the matrix's choice
 // for the vector type (spw_create_opts.wg_size or the tuner's), else 1,024
-// threads for binary32 vectors with 4- or 2-byte values (few enough registers
-// for 16 waves, which hide more latency) and 512 otherwise.  1,024 needs
-// those types; a column partition keeps 512 (its worker table assumes it).
-template <typename ValT, typename VecT>
+// threads for binary32 vectors with 4- or 2-byte values (16 waves hide more
+// latency) and 512 otherwise.  1,024 needs few enough registers (above); a
+// column partition keeps 512 (its worker table assumes it).
+template <int ITEMS, typename ValT, typename VecT>
 int vtm_block_for(const spw_matrix_s &A, bool colpart)
 {
-    constexpr bool small_regs = sizeof(VecT) == 4 && sizeof(ValT) <= 4;
     if (colpart) return VTM_BLOCK;
     int b = A.vtm_block[sizeof(VecT) == 8 ? 0 : 1];
-    if (b == 0) b = small_regs ? VTM_BLOCK_F32 : VTM_BLOCK;
-    if (b == 1024 && !small_regs) b = VTM_BLOCK;
+    if (b == 0) b = (sizeof(VecT) == 4 && sizeof(ValT) <= 4) ? VTM_BLOCK_F32 : VTM_BLOCK;
+    if (b == 1024 && !vtm_fits_1024<ITEMS, ValT, VecT>()) b = VTM_BLOCK;
     return b;
 }
 
@@ -496,7 +504,7 @@ int launch_vtm_wave_items(const spw_matrix_s &A, const VecT *vin, int k, const C
     const int cus = device_cu_count(A.device);
     // column partitioning: one wave per worker of the plan (single-vector calls)
     const int32_t *wch = (!MULTI && C.d_wchunks) ? C.d_wchunks : nullptr;
-    const int block = MULTI ? VTM_BLOCK : vtm_block_for<ValT, VecT>(A, wch != nullptr);
+    const int block = MULTI ? VTM_BLOCK : vtm_block_for<ITEMS, ValT, VecT>(A, wch != nullptr);
     const int vhot = (int)std::min<int64_t>(A.rows, hot_rows_limit(sizeof(VecT), k, block));
     const size_t lds = (size_t)vtm_stage_bytes(sizeof(VecT), block) + (size_t)vhot * k * sizeof(VecT);
     auto run = [&](auto kernel) -> int {
@@ -510,7 +518,7 @@ int launch_vtm_wave_items(const spw_matrix_s &A, const VecT *vin, int k, const C
                            out, A.scratch.carry);
         return (int)hipGetLastError();
     };
-    if constexpr (!MULTI && sizeof(VecT) == 4 && sizeof(ValT) <= 4) {
+    if constexpr (!MULTI && vtm_fits_1024<ITEMS, ValT, VecT>()) {
         if (block == 1024) {
             static const bool attr_w = allow_full_lds(vtm_wave<1024, ITEMS, IdxT, ValT, VecT, MULTI>);
             (void)attr_w;

@@ -121,8 +121,46 @@ template <typename ValT> struct ValB<ValT, 16> {
     __device__ __forceinline__ double get(int j) const { return a.get(j); }
 };
 
-template <typename VecT, int BS> struct TileGather {
-    VecT gv[BS];                // v at the rows of the batch's items
+// CW consecutive entries of a row of V, read by one load (16 bytes for
+// CW = 2 binary64 or CW = 4 binary32 entries).
+template <typename VecT, int CW> struct VecRow;
+template <typename VecT> struct VecRow<VecT, 1> {
+    VecT v[1];
+    __device__ __forceinline__ void load(const VecT *p) { v[0] = *p; }
+};
+template <> struct VecRow<double, 2> {
+    double v[2];
+    __device__ __forceinline__ void load(const double *p)
+    {
+        const f64x2_t w = *reinterpret_cast<const f64x2_t *>(p);
+        v[0] = w.x;
+        v[1] = w.y;
+    }
+};
+template <> struct VecRow<float, 2> {
+    float v[2];
+    __device__ __forceinline__ void load(const float *p)
+    {
+        typedef float f32x2_t __attribute__((ext_vector_type(2)));
+        const f32x2_t w = *reinterpret_cast<const f32x2_t *>(p);
+        v[0] = w.x;
+        v[1] = w.y;
+    }
+};
+template <> struct VecRow<float, 4> {
+    float v[4];
+    __device__ __forceinline__ void load(const float *p)
+    {
+        const f32x4_t w = *reinterpret_cast<const f32x4_t *>(p);
+        v[0] = w.x;
+        v[1] = w.y;
+        v[2] = w.z;
+        v[3] = w.w;
+    }
+};
+
+template <typename VecT, int BS, int CW> struct TileGather {
+    VecRow<VecT, CW> gv[BS];    // v at the rows of the batch's items, CW columns each
     uint32_t m;                 // column-start bits of the batch's items
 };
 
@@ -133,7 +171,14 @@ constexpr int TILE_BS = SPW_TILE_BS;            // positions per batch
 
 constexpr int TILE_BLOCK = 256;
 
-template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int BS = TILE_BS>
+// CW columns per lane: column lane cl holds columns cl*CW .. cl*CW+CW-1 and
+// gathers them with one load; V's rows must then start on CW-entry
+// boundaries (ldv a multiple of CW, V 16-byte aligned) and hold at least
+// L*CW entries, or k must be a multiple of CW.  Every column is computed with
+// the same operations in the same order whatever CW is.
+// ACC: add the results into U (U += C^T V) instead of overwriting it.
+template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, bool ACC = false,
+          int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
@@ -150,8 +195,10 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int g = lane / L, cl = lane % L;
-    const bool colok = cl < k;
-    const int vc = min(cl, k - 1);                // idle lanes read a valid column
+    const int c0 = cl * CW;                       // first column of this lane
+    const bool colok = c0 < k;
+    // idle lanes read a valid group of columns (the last one)
+    const int vc = min(c0, ((k - 1) / CW) * CW);
     const int64_t nw = (int64_t)gridDim.x * NW;
     const int64_t chunk0 = (int64_t)blockIdx.x * NW + wave;
     if (chunk0 >= nchunks) return;
@@ -173,9 +220,9 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         const int b = (int)(q % NB);
         A.load(val + cc * WCH, g * L + b / PPL, b % PPL);
     };
-    auto gather = [&](TileGather<VecT, BS> &G, const IdxB<IdxT, BS> &R, uint32_t m) __attribute__((always_inline)) {
+    auto gather = [&](TileGather<VecT, BS, CW> &G, const IdxB<IdxT, BS> &R, uint32_t m) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < BS; ++j) G.gv[j] = V[(int64_t)R.get(j) * ldv + vc];
+        for (int j = 0; j < BS; ++j) G.gv[j].load(V + (int64_t)R.get(j) * ldv + vc);
         G.m = m;
     };
 
@@ -184,20 +231,27 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     int4 ci = make_int4(0, 0, 0, 0), ci_n = cinfo[chunk0];
     uint32_t mask_n = heads[chunk0 * WAVE + lane];
     int base = 0, rel = 0, hk = 0, my_n = 0, s = 0, e = 0;
-    double run = 0.0, head_sum = 0.0;
+    double run[CW], head_sum[CW];
+#pragma unroll
+    for (int w = 0; w < CW; ++w) run[w] = head_sum[w] = 0.0;
     bool multi = false;
     int64_t cc = chunk0;
 
     auto column = [&](int q) __attribute__((always_inline)) -> int64_t {
         return (ci.w & CHUNK_DENSE) ? (int64_t)ci.x + q : (int64_t)segcol[ci.y + q];
     };
-    auto emit = [&](int q, double value) __attribute__((always_inline)) {
-        if (!colok) return;
+    // column c0 + w of segment q: to a carry slot when the chunk cuts it, else to U
+    auto emit = [&](int q, int w, double value) __attribute__((always_inline)) {
+        const int col = c0 + w;
+        if (col >= k) return;
         const bool before = q == 0 && !(ci.w & CHUNK_START_HEAD);
         const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
-        if (before) carry[(2 * cc) * k + cl] = value;
-        else if (after) carry[(2 * cc + 1) * k + cl] = value;
-        else U[column(q) * ldu + cl] = (VecT)value;
+        if (before) carry[(2 * cc) * k + col] = value;
+        else if (after) carry[(2 * cc + 1) * k + col] = value;
+        else {
+            VecT *o = U + column(q) * ldu + col;
+            *o = ACC ? (VecT)((double)*o + value) : (VecT)value;
+        }
     };
     auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
         cc = c;
@@ -226,37 +280,52 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         base = excl + (g > 0 ? (int)(m0 & 1u) : 0);
         my_n = max(0, min(SPAN, e - (s + g * SPAN)));
         rel = 0;
-        run = 0.0;
-        head_sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < CW; ++w) run[w] = head_sum[w] = 0.0;
         multi = false;
     };
     auto chunk_end = [&]() __attribute__((always_inline)) {
         const int klast = my_n > 0 ? base + rel : -2 - g;
         const int hkey = my_n > 0 ? (multi ? base + hk : klast) : -2 - g;
-        SegPair x{run, klast};
+        // one segmented scan per column; every column has the same keys
+        SegPair x[CW];
+#pragma unroll
+        for (int w = 0; w < CW; ++w) x[w] = SegPair{run[w], klast};
 #pragma unroll
         for (int off = 1; off < S; off <<= 1) {
-            const double ps = __shfl_up(x.s, off * L, WAVE);
-            const int pk = __shfl_up(x.k, off * L, WAVE);
-            if (g >= off) x = seg_op(SegPair{ps, pk}, x);
+            const int pk = __shfl_up(x[0].k, off * L, WAVE);
+#pragma unroll
+            for (int w = 0; w < CW; ++w) {
+                const double ps = __shfl_up(x[w].s, off * L, WAVE);
+                if (g >= off) x[w] = seg_op(SegPair{ps, pk}, x[w]);
+            }
         }
-        double prev_s = 0.0;
+        double prev_s[CW];
         int prev_k = -1, next_hk = -1;
+#pragma unroll
+        for (int w = 0; w < CW; ++w) prev_s[w] = 0.0;
         if (S > 1) {
-            prev_s = __shfl_up(x.s, L, WAVE);
-            prev_k = __shfl_up(x.k, L, WAVE);
+#pragma unroll
+            for (int w = 0; w < CW; ++w) prev_s[w] = __shfl_up(x[w].s, L, WAVE);
+            prev_k = __shfl_up(x[0].k, L, WAVE);
             next_hk = __shfl_down(hkey, L, WAVE);
         }
-        if (my_n > 0) {
+        if (my_n > 0 && colok) {
             if (multi) {
-                double tot = head_sum;
-                if (g > 0 && prev_k == hkey) tot = prev_s + head_sum;
-                emit(hkey, tot);
+#pragma unroll
+                for (int w = 0; w < CW; ++w) {
+                    double tot = head_sum[w];
+                    if (g > 0 && prev_k == hkey) tot = prev_s[w] + head_sum[w];
+                    emit(hkey, w, tot);
+                }
             }
-            if (g == S - 1 || next_hk != klast) emit(klast, x.s);
+            if (g == S - 1 || next_hk != klast) {
+#pragma unroll
+                for (int w = 0; w < CW; ++w) emit(klast, w, x[w].s);
+            }
         }
     };
-    auto compute = [&](int64_t q, const ValB<ValT, BS> &A, const TileGather<VecT, BS> &G) __attribute__((always_inline)) {
+    auto compute = [&](int64_t q, const ValB<ValT, BS> &A, const TileGather<VecT, BS, CW> &G) __attribute__((always_inline)) {
         const int b = (int)(q % NB);
         if (b == 0) chunk_start(chunk_of(q));
 #pragma unroll
@@ -265,16 +334,27 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
             if (t < my_n) {
                 if (t > 0 && ((G.m >> j) & 1u)) {
                     if (!multi) {
-                        head_sum = run;
+#pragma unroll
+                        for (int w = 0; w < CW; ++w) head_sum[w] = run[w];
                         hk = rel;
                         multi = true;
                     } else {
-                        if (colok) U[column(base + rel) * ldu + cl] = (VecT)run;   // column wholly inside
+                        // a column wholly inside this sub-group's positions
+                        const int64_t row = column(base + rel) * ldu;
+#pragma unroll
+                        for (int w = 0; w < CW; ++w)
+                            if (c0 + w < k) {
+                                VecT *o = U + row + c0 + w;
+                                *o = ACC ? (VecT)((double)*o + run[w]) : (VecT)run[w];
+                            }
                     }
                     ++rel;
-                    run = 0.0;
+#pragma unroll
+                    for (int w = 0; w < CW; ++w) run[w] = 0.0;
                 }
-                run = __fma_rn(A.get(j), (double)G.gv[j], run);
+                const double a = A.get(j);
+#pragma unroll
+                for (int w = 0; w < CW; ++w) run[w] = __fma_rn(a, (double)G.gv[j].v[w], run[w]);
             }
         }
         if (b == NB - 1) chunk_end();
@@ -283,7 +363,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     ValB<ValT, BS> A0, A1;
     IdxB<IdxT, BS> R0, R1;
     uint32_t m0 = 0, m1 = 0;
-    TileGather<VecT, BS> G0, G1;
+    TileGather<VecT, BS, CW> G0, G1;
     load_idx(R0, m0, 0);
     load_val(A0, 0);
     load_idx(R1, m1, 1);
@@ -303,8 +383,9 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     }
 }
 
-// Multi-RHS zone reduction: one lane per (zone, right-hand side).
-template <typename VoutT>
+// Multi-RHS zone reduction: one lane per (zone, right-hand side); ACC adds
+// the zone's sum into U.
+template <typename VoutT, bool ACC = false>
 __global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
                                  const int32_t *__restrict__ zlast, int64_t nz, int k,
                                  const double *__restrict__ carry, VoutT *__restrict__ U, int64_t ldu)
@@ -316,7 +397,8 @@ __global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t
     const int a = zfirst[z], b = zlast[z];
     double s = carry[(2 * (int64_t)a + 1) * k + cc];
     for (int c = a + 1; c <= b; ++c) s += carry[(2 * (int64_t)c) * k + cc];
-    U[(int64_t)zcol[z] * ldu + cc] = (VoutT)s;
+    VoutT *o = U + (int64_t)zcol[z] * ldu + cc;
+    *o = ACC ? (VoutT)((double)*o + s) : (VoutT)s;
 }
 
 template <typename VoutT>
@@ -344,12 +426,26 @@ __global__ void gather_rows(const int32_t *__restrict__ inv, int64_t rows, int k
 }  // namespace
 
 namespace {
-template <int ITEMS, typename IdxT, typename ValT, typename VecT>
-int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U,
-                      int64_t ldu, hipStream_t stream)
+// The tile shape for k columns: CW columns per lane (one 16-byte gather of
+// 2 binary64 or 4 binary32 entries, when `wide`) and L column lanes, the
+// power of two >= ceil(k / CW); narrow tiles keep L >= 2.
+template <typename VecT>
+void tile_shape(int k, bool wide, int *L, int *CW)
 {
-    int L = 2;
-    while (L < k) L <<= 1;
+    int cw = 1;
+    if (wide) cw = sizeof(VecT) == 8 ? (k >= 2 ? 2 : 1) : (k >= 4 ? 4 : (k >= 2 ? 2 : 1));
+    int l = cw == 1 ? 2 : 1;
+    while (l * cw < k) l <<= 1;
+    *L = l;
+    *CW = cw;
+}
+
+template <int ITEMS, bool ACC, typename IdxT, typename ValT, typename VecT>
+int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U,
+                      int64_t ldu, bool wide, hipStream_t stream)
+{
+    int L = 2, CW = 1;
+    tile_shape<VecT>(k, wide, &L, &CW);
     const int cus = device_cu_count(A.device);
     const int64_t want = (C.zp.n_chunks + TILE_BLOCK / WAVE - 1) / (TILE_BLOCK / WAVE);
     // persistent: as many workgroups as the chip keeps resident
@@ -361,44 +457,48 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
         }
         return nb;
     };
-#define SPW_TILE_CASE(LL)                                                                                           \
-    case LL: {                                                                                                      \
-        static const int nb = per_cu((const void *)cdot_tile<IdxT, ValT, VecT, LL, ITEMS>);                        \
-        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));        \
-        hipLaunchKernelGGL((cdot_tile<IdxT, ValT, VecT, LL, ITEMS>), dim3(grid), dim3(TILE_BLOCK), 0, stream,       \
-                           (const IdxT *)C.d_idx, (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo,         \
-                           C.d_segcol, C.nnz, C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);                   \
-        break;                                                                                                      \
+    auto go = [&](auto kern) -> int {
+        static const int nb = per_cu((const void *)kern);
+        const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE_BLOCK), 0, stream, (const IdxT *)C.d_idx,
+                           (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo, C.d_segcol, C.nnz,
+                           C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);
+        return (int)hipGetLastError();
+    };
+#define SPW_TILE(LL, WW) \
+    if (L == LL && CW == WW) return go(cdot_tile<IdxT, ValT, VecT, LL, ITEMS, WW, ACC>);
+    SPW_TILE(2, 1) SPW_TILE(4, 1) SPW_TILE(8, 1) SPW_TILE(16, 1) SPW_TILE(32, 1) SPW_TILE(64, 1)
+    SPW_TILE(1, 2) SPW_TILE(2, 2) SPW_TILE(4, 2) SPW_TILE(8, 2) SPW_TILE(16, 2) SPW_TILE(32, 2)
+    if constexpr (sizeof(VecT) == 4) {
+        SPW_TILE(1, 4) SPW_TILE(2, 4) SPW_TILE(4, 4) SPW_TILE(8, 4) SPW_TILE(16, 4)
     }
-    switch (L) {
-        SPW_TILE_CASE(2)
-        SPW_TILE_CASE(4)
-        SPW_TILE_CASE(8)
-        SPW_TILE_CASE(16)
-        SPW_TILE_CASE(32)
-        SPW_TILE_CASE(64)
-    default: return (int)hipErrorInvalidValue;
-    }
-#undef SPW_TILE_CASE
-    return (int)hipGetLastError();
+#undef SPW_TILE
+    return (int)hipErrorInvalidValue;
 }
 
 // Chunks of 1,024 or 512 nonzeros (16 or 8 positions per layout lane).
+// Chunks of 1,024 or 512 nonzeros; acc (the blocks after the first of a
+// blocked transpose, whose chunks are always 1,024 nonzeros) adds into U.
 template <typename IdxT, typename ValT, typename VecT>
 int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
-                hipStream_t stream)
+                bool wide, bool acc, hipStream_t stream)
 {
-    if (C.zp.chunk == 1024) return launch_tile_items<16, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, stream);
-    if (C.zp.chunk == 512) return launch_tile_items<8, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, stream);
+    if (acc) {
+        if (C.zp.chunk == 1024)
+            return launch_tile_items<16, true, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
+        return (int)hipErrorNotSupported;
+    }
+    if (C.zp.chunk == 1024) return launch_tile_items<16, false, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
+    if (C.zp.chunk == 512) return launch_tile_items<8, false, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
     return (int)hipErrorNotSupported;
 }
 
 template <typename ValT, typename VecT>
 int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VecT *V,
-                       int64_t ldv, VecT *U, int64_t ldu, hipStream_t stream)
+                       int64_t ldv, VecT *U, int64_t ldu, bool acc, hipStream_t stream)
 {
     int e;
-    if (C.n_empty > 0) {
+    if (C.n_empty > 0 && !acc) {       // adding zero changes nothing
         ProfScope ps(stream, "zero_cols_batch");
         hipLaunchKernelGGL(zero_cols_batch<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
                            C.d_empty, C.n_empty, k, U, ldu);
@@ -422,14 +522,28 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
             Vin = vp;
             ldin = L;
         }
-        e = C.idx_kind == IdxKind::U16 ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream)
-                                       : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, stream);
+        // wide gathers (CW columns in one 16-byte load) need rows that start on
+        // CW-entry boundaries; the renumbered copy's rows are padded to the
+        // tile width, the caller's block must hold whole groups of CW columns
+        int Lw = 1, CWw = 1;
+        tile_shape<VecT>(k, true, &Lw, &CWw);
+        const bool wide = inv != nullptr ||
+                          (k % CWw == 0 && ldin % CWw == 0 && ((uintptr_t)Vin % 16) == 0);
+        e = C.idx_kind == IdxKind::U16
+                ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, acc, stream)
+                : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, acc, stream);
         if (e) return e;
     }
     if (C.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup_batch");
-        hipLaunchKernelGGL(zone_fixup_batch<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
-                           C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
+        if (acc)
+            hipLaunchKernelGGL((zone_fixup_batch<VecT, true>), dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0,
+                               stream, C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U,
+                               ldu);
+        else
+            hipLaunchKernelGGL((zone_fixup_batch<VecT, false>), dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0,
+                               stream, C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U,
+                               ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
     return 0;
@@ -437,14 +551,14 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
 }  // namespace
 
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream)
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream, bool acc)
 {
     if (k < 1 || k > 64) return (int)hipErrorNotSupported;
     if (C.cols == 0) return 0;
     return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
         using ValT = decltype(vt);
         using VecT = decltype(xt);
-        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
+        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu, acc,
                                               (hipStream_t)stream);
     });
 }

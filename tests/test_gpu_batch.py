@@ -81,8 +81,39 @@ def run_case(spw, A, fmt, k, dtype, pad, seed, name, opts=None, reps=1):
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 9, 16, 24, 33, 64])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_small_config(spw, fmt, k, dtype):
+    # the transpose is kept, so the scatter direction takes the tiles over it from k = 16
     A = synth.config_matrix("c0", scale=0.2 if k < 64 else 0.05)
-    run_case(spw, A, fmt, k, dtype, pad=1 if k % 2 else 0, seed=k, name="c0", reps=2)
+    run_case(spw, A, fmt, k, dtype, pad=1 if k % 2 else 0, seed=k, name="c0", reps=2, opts={"transpose": 1})
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+@pytest.mark.parametrize("k", [16, 33, 64])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_over_blocked_transpose(spw, fmt, k, dtype):
+    # 600,000 long-side entries: the kept transpose is three blocks of 2^18 of
+    # them, summed into the output in block order; some rows of the long side
+    # hold no nonzero in a block (the output keeps the earlier blocks' sums)
+    A = synth.random_csc(150, 600000, 1.5, 60 + k, values="lognormal", empty_frac=0.3)
+    m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
+    M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=1)
+    assert M.info()["has_transpose"] == 1
+    op = spw.SPW_OP_MV if fmt == 0 else spw.SPW_OP_VTM            # the scatter direction
+    vdt = spw.SPW_F64 if dtype == torch.float64 else spw.SPW_F32
+    M.set_batch_plan(op, vdt, k, spw.SPW_PLAN_TILE)
+    in_len, out_len = (n, m) if op == spw.SPW_OP_MV else (m, n)
+    X, Xd = block(in_len, k, 70 + k, 1, dtype, 0)
+    Y = torch.full((out_len, k), float("nan"), dtype=dtype, device="cuda")
+    print("blocked transpose fmt=%d k=%d %s" % (fmt, k, dtype), flush=True)
+    (M.mv_batch if op == spw.SPW_OP_MV else M.vtm_batch)(Xd, Y)
+    Y2 = (M.mv_batch if op == spw.SPW_OP_MV else M.vtm_batch)(Xd)
+    torch.cuda.synchronize()
+    assert torch.equal(Y, Y2), "not bit-identical on repeat"
+    if fmt == 0:
+        Yr, D = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
+    else:
+        Yr, D = oracle.vtm_csr_batch(A.n, A.m, A.ptr, A.idx, A.val, X, with_d=True)
+    check(Y.double().cpu().numpy(), Yr, D, "blocked transpose", 1e-13 if dtype == torch.float64 else 1e-5)
+    M.close()
 
 
 @pytest.mark.parametrize("fmt", [0, 1])
@@ -106,8 +137,8 @@ def test_batch_structures(spw, fmt, case):
 def test_batch_scaled_batching_config(spw):
     A = synth.config_matrix("c2", scale=0.05)
     for k in (4, 16):
-        run_case(spw, A, 0, k, torch.float64, pad=0, seed=k, name="c2x0.05")
-    run_case(spw, A, 0, 16, torch.float32, pad=0, seed=3, name="c2x0.05")
+        run_case(spw, A, 0, k, torch.float64, pad=0, seed=k, name="c2x0.05", opts={"transpose": 1})
+    run_case(spw, A, 0, 16, torch.float32, pad=0, seed=3, name="c2x0.05", opts={"transpose": 1})
 
 
 def test_plain_binary32_vectors(spw):
@@ -202,5 +233,6 @@ def test_column_dots_with_output_leading_dimension_past_chunk_views(spw, fmt, k)
 @pytest.mark.parametrize("k, dtype", [(64, torch.float64), (16, torch.float32)])
 def test_batching_matrix_full_size(spw, k, dtype):
     # the 5e7-nonzero batching matrix at full size, at widths the benchmark times
+    # (the transpose kept: A x of k >= 16 columns runs over its 20 blocks)
     A = synth.config_matrix("c2")
-    run_case(spw, A, 0, k, dtype, 0, 50 + k, "c2 full")
+    run_case(spw, A, 0, k, dtype, 0, 50 + k, "c2 full", opts={"transpose": 1})
