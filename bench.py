@@ -22,11 +22,14 @@ the same matrix (binary32 / bfloat16 values, binary32 vectors, with their
 error against binary64 products), multi-RHS blocks on the 5e7-nonzero
 batching matrix, and the CPU oracle timed on the host.
 
-`--pmc-summary DIR` turns rocprofv3 counter output (FETCH_SIZE / WRITE_SIZE
-runs of `--profile-run`) into the traffic summary under profiles/, and
-`--stats-summary DIR` a `rocprofv3 --kernel-trace --stats` run of the main
-benchmark into the kernel statistics summary there, and `--cache-summary DIR`
-a run with the cache and LDS counters (CACHE_COUNTERS) into the cache summary.
+`--counter-summary WORKLOAD DIR...` folds the rocprofv3 --pmc runs of
+`--profile-run` (WORKLOAD wide) or `--profile-batched` (WORKLOAD batched), one
+run per counter pass of PMC_PASSES, into the counter summary under profiles/:
+HBM bytes per launch from the 32-, 64- and 128-byte request counts, cache hit
+rates, LDS and wave-state figures.  `--stats-summary DIR` turns a
+`rocprofv3 --kernel-trace --stats` run of the main benchmark into the kernel
+statistics summary there (`--batched-stats-summary DIR` the same for
+`--batched-only`).
 """
 from __future__ import annotations
 
@@ -45,12 +48,25 @@ sys.path.insert(0, ROOT)
 METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 NROT = 4          # input vectors the timed pairs rotate through
-KERNEL_SRC = os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_wide_2e8.txt")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00904_amd", "csrc", f)
+               for f in ("spw_device.h", "spw_kernels.hip", "spw_tile.hip")]
+COUNTER_FILES = {"wide": os.path.join(ROOT, "profiles", "pmc_counters_wide_2e8.txt"),
+                 "batched": os.path.join(ROOT, "profiles", "pmc_counters_batched_5e7.txt")}
+TRAFFIC_FILE = COUNTER_FILES["wide"]
 STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_wide_2e8.txt")
-CACHE_FILE = os.path.join(ROOT, "profiles", "pmc_cache_lds_wide_2e8.txt")
-CACHE_COUNTERS = ("TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum "
-                  "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_WAIT_INST_LDS")
+BATCHED_STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_batched_5e7.txt")
+BATCHED_STATS_COMMAND = "rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --batched-only"
+# One rocprofv3 --pmc run per pass (each within the per-block counter limits).
+PMC_PASSES = {
+    "read": "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum",
+    "write": "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum",
+    "cache": ("TCC_HIT_sum TCC_MISS_sum TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum SQ_LDS_BANK_CONFLICT "
+              "SQ_LDS_IDX_ACTIVE SQ_INSTS_LDS SQ_INSTS_LDS_ATOMIC SQ_ACTIVE_INST_LDS SQ_WAIT_INST_LDS"),
+    "waves": ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CU_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY "
+              "SQ_ACTIVE_INST_VMEM SQ_INSTS_VMEM_RD TA_TA_BUSY_sum TA_ADDR_STALLED_BY_TC_CYCLES_sum "
+              "TCP_TCC_READ_REQ_LATENCY_sum TCP_TCC_READ_REQ_sum"),
+    "latency": "TCC_EA0_RDREQ_LEVEL_sum TCC_EA0_RDREQ_sum GRBM_GUI_ACTIVE",
+}
 STATS_COMMAND = ("rocprofv3 --kernel-trace --stats -f csv -d <dir> -- python3 bench.py --steps 20 --warmup 3 "
                  "--no-cpu-baseline --no-tall --no-batch --no-precision --no-serving --no-partition --no-solver --no-small")
 SOLVER_STATS_FILE = os.path.join(ROOT, "profiles", "kernel_stats_cgls_wide_2e8.txt")
@@ -67,8 +83,13 @@ def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, 
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the device sources of the product kernels: a counter summary
+    is used only while it matches."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
@@ -155,6 +176,53 @@ def read_stream_ceiling(dev, gib: int = 4, reps: int = 5):
             "copy_GBps_read_plus_write": round(2 * nbytes / (c_ms * 1e-3) / 1e9, 1)}
 
 
+def profile_probe(dev):
+    """Known traffic for the counter runs: the probe's read-only stream over
+    exactly 1 GiB (1 GiB read) and its copy of 1 GiB (1 GiB read, 1 GiB
+    written), each launched twice."""
+    import torch
+    from paper_1812_00904_amd.spw import spw_probe_bandwidth
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    spw_probe_bandwidth(src, dst, 1)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def profile_batched(args):
+    """Launches for the counter runs on the batching matrix (m=20,000, n=5e6,
+    ~5e7 nonzeros): binary64 at k = 4 (column passes), 16 and 64 (tiles; the
+    scatter direction over the kept transpose), binary32 at k = 16 and 64,
+    three calls of each direction, then the probe's known traffic."""
+    import torch
+    import synth
+    from paper_1812_00904_amd import (SPW_CSC, SPW_F32, SPW_F64, SPW_OP_MV, SPW_OP_VTM, SPW_PLAN_PASSES,
+                                      SPW_PLAN_TILE, SpwMatrix)
+    A = synth.config_matrix("c2", scale=args.scale)
+    for dtype, vdt, ks in ((torch.float64, SPW_F64, (4, 16, 64)), (torch.float32, SPW_F32, (16, 64))):
+        M = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, transpose=1,
+                      **({} if vdt == SPW_F64 else {"value_storage": SPW_F32}))
+        for k in ks:
+            plan = SPW_PLAN_PASSES if k <= 8 else SPW_PLAN_TILE
+            M.set_batch_plan(SPW_OP_MV, vdt, k, plan)
+            M.set_batch_plan(SPW_OP_VTM, vdt, k, plan)
+            X = torch.rand((A.n, k), dtype=dtype, device="cuda") * 2 - 1
+            V = torch.rand((A.m, k), dtype=dtype, device="cuda") * 2 - 1
+            Y = torch.empty((A.m, k), dtype=dtype, device="cuda")
+            U = torch.empty((A.n, k), dtype=dtype, device="cuda")
+            for _ in range(3):
+                M.mv_batch(X, Y)
+                M.vtm_batch(V, U)
+            torch.cuda.synchronize()
+            print("[bench] profiled %s k=%d" % (dtype, k), file=sys.stderr, flush=True)
+            del X, V, Y, U
+        M.close()
+        torch.cuda.empty_cache()
+    profile_probe("cuda")
+    print("[bench] profile run done", file=sys.stderr, flush=True)
+
+
 def time_pairs(M, xd, vd, yd, ud, steps, warmup, per_step=True):
     """Event-timed y=Ax / u^T=v^T A pairs.  xd and vd may be lists of vectors,
     which step i takes in turn (i mod len): inputs whose total exceeds the
@@ -214,10 +282,13 @@ def main():
                     help="comma-separated offered loads, as fractions of the plain path's capacity")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few pairs plus a calibration copy, for rocprofv3 counter runs")
-    ap.add_argument("--pmc-summary", metavar="DIR", nargs=2,
-                    help="FETCH_SIZE and WRITE_SIZE rocprofv3 output directories -> traffic summary")
-    ap.add_argument("--cache-summary", metavar="DIR",
-                    help="summarize a rocprofv3 --pmc run with CACHE_COUNTERS of --profile-run and exit")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="only launch the batched products for rocprofv3 counter runs and exit")
+    ap.add_argument("--counter-summary", metavar="ARG", nargs="+",
+                    help="WORKLOAD (wide or batched) and the rocprofv3 --pmc output directories of its "
+                         "passes -> counter summary")
+    ap.add_argument("--batched-stats-summary", metavar="DIR",
+                    help="summarize a rocprofv3 --kernel-trace --stats run of --batched-only and exit")
     ap.add_argument("--solver-stats-summary", metavar="DIR",
                     help="summarize a rocprofv3 --kernel-trace --stats run of SOLVER_STATS_COMMAND and exit")
     ap.add_argument("--batched-only", action="store_true",
@@ -230,14 +301,14 @@ def main():
                     help="rocprofv3 --kernel-trace --stats output directory -> kernel statistics summary")
     args = ap.parse_args()
 
-    if args.pmc_summary:
-        return summarize_pmc(*args.pmc_summary)
+    if args.counter_summary:
+        return summarize_counters(args.counter_summary[0], args.counter_summary[1:])
     if args.stats_summary:
         return summarize_stats(args.stats_summary)
     if args.solver_stats_summary:
         return summarize_stats(args.solver_stats_summary, solver=True)
-    if args.cache_summary:
-        return summarize_cache(args.cache_summary)
+    if args.batched_stats_summary:
+        return summarize_stats(args.batched_stats_summary, batched=True)
     if args.serving_busy_summary:
         return summarize_serving_busy(args.serving_busy_summary)
     if args.gpus != 1:
@@ -260,6 +331,8 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": bench_batched(args)}), flush=True)
         return
+    if args.profile_batched:
+        return profile_batched(args)
     t = time.perf_counter()
     A = synth.config_matrix("c1", scale=args.scale)
     x, v = synth.config_vectors("c1", A.m, A.n)
@@ -281,13 +354,18 @@ def main():
         for _ in range(3):
             M.mv(xd, yd)
             M.vtm(vd, ud)
-        # calibration: a plain copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        # binary32 and bfloat16 value storage, binary32 vectors
+        x32, v32 = xd.float(), vd.float()
+        y32 = torch.empty(A.m, dtype=torch.float32, device=dev)
+        u32 = torch.empty(A.n, dtype=torch.float32, device=dev)
+        for code in (1, 2):
+            S = SpwMatrix(SPW_CSC, A.m, A.n, A.ptr, A.idx, A.val, value_storage=code, transpose=0)
+            for _ in range(3):
+                S.mv(x32, y32)
+                S.vtm(v32, u32)
+            torch.cuda.synchronize()
+            S.close()
+        profile_probe(dev)
         print("[bench] profile run done", file=sys.stderr, flush=True)
         return
 
@@ -926,91 +1004,166 @@ def batch_plan(info, k, plan_mv, plan_vtm, sx):
             "chunk_nnz": chunk, "coldot_wg_size": wg, "tuned": bool(info["tuned"])}
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str):
-    """Fold rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs of a --profile-run
-    into per-launch HBM bytes for the product kernels, calibrated by the 1 GiB copy."""
-    def load(d, counter):
-        rows = []
-        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+def kernel_label(name: str) -> str:
+    """Short kernel name with its template arguments, types abbreviated."""
+    n = name.replace("spw::(anonymous namespace)::", "").replace("spw::", "").replace("void ", "").strip()
+    depth, end = 0, len(n)
+    for i, ch in enumerate(n):              # cut the parameter list after the template arguments
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            end = i
+            break
+    n = n[:end].replace(" ", "")
+    for a, b in (("unsignedshort", "u16"), ("unsignedint", "u32"), ("__hip_bfloat16", "bf16"),
+                 ("hip_bfloat16", "bf16"), ("double", "f64"), ("float", "f32")):
+        n = n.replace(a, b)
+    n = n.replace("<int,", "<i32,")
+    return n
+
+
+COUNTER_WORKLOADS = {
+    "wide": ("`bench.py --profile-run`: the wide CSC matrix m=50000 n=2e7 nnz=200201679 (k=1): three y=Ax / "
+             "u^T=v^T A pairs with binary64 values and vectors, three with binary32 and three with bfloat16 "
+             "storage (binary32 vectors); then the probe's known traffic", "--profile-run"),
+    "batched": ("`bench.py --profile-batched`: the batching matrix m=20000 n=5e6 nnz=50425484, three calls of "
+                "each direction at binary64 k=4 (column passes), k=16 and 64 (tiles, the scatter direction over "
+                "the kept transpose) and binary32 k=16 and 64; then the probe's known traffic",
+                "--profile-batched"),
+}
+
+
+def summarize_counters(workload: str, dirs):
+    """Fold the rocprofv3 --pmc runs of one profiling mode (one run per pass
+    of PMC_PASSES, in any order) into per-kernel figures, each the median over
+    that kernel's dispatches:
+    - HBM-side bytes: reads = 32 B x TCC_EA0_RDREQ_32B + 64 B x _64B + 128 B x
+      _128B, writes = 64 B x TCC_EA0_WRREQ_64B + 32 B x the rest of
+      TCC_EA0_WRREQ; the request totals check the split, and the probe's
+      read stream and copy of exactly 1 GiB check the byte count;
+    - the share of those requests sent to DRAM, the L2 hit rate, the share
+      of L1 accesses sent on to L2, LDS bank-conflict cycles per LDS-active
+      cycle;
+    - wave-state ratios (all in quad-cycles: waiting / resident, VMEM issue /
+      resident; resident wave-cycles per busy CU-cycle, which reads as waves
+      per SIMD: 1.00 for a launch of one 4-wave workgroup per CU), the
+      average L1-to-L2 and L2-to-memory read latencies in cycles.  The DRAM
+      request counters see the Infinity Cache as memory: they do not split
+      its hits from HBM reads."""
+    if workload not in COUNTER_WORKLOADS:
+        raise SystemExit("workload must be one of %s" % sorted(COUNTER_WORKLOADS))
+    vals = {}
+    for d in dirs:
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit("no counter_collection.csv under %s" % d)
+        for f in files:
             with open(f) as fh:
                 for r in csv.DictReader(fh):
-                    if r.get("Counter_Name") == counter:
-                        rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
-        return rows
-
-    out = ["# HBM traffic per launch, from rocprofv3 --pmc runs of `bench.py --profile-run`",
-           "# FETCH_SIZE and WRITE_SIZE are KiB per dispatch; each is scaled by the factor that maps",
-           "# the same counter on a 1 GiB device copy (copy_ kernel) to exactly 1 GiB.",
-           "# command: rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch_dir> -- python3 bench.py --profile-run ; "
-           "rocprofv3 --pmc WRITE_SIZE -f csv -d <write_dir> -- python3 bench.py --profile-run ; "
-           "python3 bench.py --pmc-summary <fetch_dir> <write_dir>",
-           "# workload: wide CSC m=50000 n=2e7 nnz=200201679 (the benchmark matrix), binary64 values and "
-           "vectors, k=1",
-           "kernel_source_sha256_16=%s" % kernel_hash()]
+                    key = (kernel_label(r["Kernel_Name"]), r["Counter_Name"].replace("_sum", ""))
+                    vals.setdefault(key, {})[r.get("Dispatch_Id", str(len(vals)))] = float(r["Counter_Value"])
     per = {}
-    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        rows = load(d, counter)
-        copy = [v for k, v in rows if "copy" in k.lower() or "elementwise" in k.lower()]
-        cal = None
-        if copy:
-            cal = (1 << 20) / (sorted(copy)[len(copy) // 2])   # KiB expected / KiB read
-        out.append("%s_copy_calibration=%s" % (counter, "%.4f" % cal if cal else "none"))
-        for name in ("mv_bucket", "vtm_wave", "mv_reduce", "zone_fixup", "gather_vec", "zero_cols"):
-            vals = [v for k, v in rows if name in k]
-            if vals:
-                med = sorted(vals)[len(vals) // 2] * 1024.0 * (cal or 1.0)
-                per.setdefault(name, {})[counter] = med
-                out.append("%s_%s_bytes=%.0f" % (name, counter, med))
-    for name, d in per.items():
-        if "FETCH_SIZE" in d and "WRITE_SIZE" in d:
-            out.append("%s_bytes_per_launch=%.0f" % (name, d["FETCH_SIZE"] + d["WRITE_SIZE"]))
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as f:
-        f.write("\n".join(out) + "\n")
-    print("\n".join(out))
-
-
-def summarize_cache(pmc_dir: str):
-    """Fold one rocprofv3 --pmc run with CACHE_COUNTERS of a --profile-run into
-    per-launch cache and LDS figures for the product kernels: L2 hit rate,
-    the share of L1 accesses sent on to L2, and LDS bank-conflict cycles
-    against LDS-active cycles."""
-    vals = {}
-    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
-        with open(f) as fh:
-            for r in csv.DictReader(fh):
-                vals.setdefault((r["Kernel_Name"], r["Counter_Name"]), []).append(float(r["Counter_Value"]))
-    if not vals:
-        raise SystemExit("no counter_collection.csv under %s" % pmc_dir)
-    out = ["# Cache and LDS counters per launch (median over launches), from one rocprofv3 --pmc run of",
-           "# `bench.py --profile-run` on the wide CSC matrix m=50000 n=2e7 nnz=200201679, binary64, k=1",
-           "# command: rocprofv3 --pmc %s -f csv -d <dir> -- python3 bench.py --profile-run ; "
-           "python3 bench.py --cache-summary <dir>" % CACHE_COUNTERS,
+    for (kern, cn), by_dispatch in vals.items():
+        xs = sorted(by_dispatch.values())
+        per.setdefault(kern, {})[cn] = (xs[len(xs) // 2], len(xs))
+    desc, mode = COUNTER_WORKLOADS[workload]
+    cmds = ["rocprofv3 --pmc %s -f csv -d <dir_%s> -- python3 bench.py %s" % (c, name, mode)
+            for name, c in PMC_PASSES.items()]
+    out = ["# rocprofv3 counters per kernel launch (median over launches), from %s." % desc,
+           "# Bytes come from the request counts by size (32, 64, 128 B); no scale factor is applied.",
+           "# commands: " + " ; ".join(cmds) + " ; python3 bench.py --counter-summary %s %s"
+           % (workload, " ".join("<dir_%s>" % n for n in PMC_PASSES)),
            "kernel_source_sha256_16=%s" % kernel_hash()]
-    counters = CACHE_COUNTERS.split()
-    for name in ("vtm_wave", "mv_bucket", "mv_reduce", "zone_fixup", "gather_vec"):
-        med = {}
-        for c in counters:
-            xs = sorted(v for (k, cn), vs in vals.items() if name in k and (cn == c or cn == c.replace("_sum", ""))
-                        for v in vs)
-            if xs:
-                med[c] = xs[len(xs) // 2]
-        if not med:
+
+    def g(c, name):
+        v = c.get(name)
+        return None if v is None else v[0]
+
+    order = sorted(per, key=lambda k: (not k.startswith(("vtm_wave", "mv_bucket", "cdot_tile")), k))
+    for kern in order:
+        c = per[kern]
+        if kern.startswith(("at::", "__amd")):
             continue
-        for c in counters:
-            if c in med:
-                out.append("%s_%s=%.0f" % (name, c, med[c]))
-        hit, miss = med.get("TCC_HIT_sum"), med.get("TCC_MISS_sum")
+        launches = max(n for _, n in c.values())
+        out.append("# %s (%d launches)" % (kern, launches))
+        line = lambda key, v, fmt="%.0f": out.append(("%s.%s=" + fmt) % (kern, key, v))
+        r32, r64, r128, rq = (g(c, "TCC_EA0_RDREQ_32B"), g(c, "TCC_EA0_RDREQ_64B"), g(c, "TCC_EA0_RDREQ_128B"),
+                              g(c, "TCC_EA0_RDREQ"))
+        rd = wr = None
+        if None not in (r32, r64, r128):
+            rd = 32 * r32 + 64 * r64 + 128 * r128
+            line("read_bytes", rd)
+            line("read_requests_32_64_128", "%d/%d/%d" % (r32, r64, r128), "%s")
+            if rq:
+                line("read_size_split_covers", (r32 + r64 + r128) / rq, "%.4f")
+        w64, wq = g(c, "TCC_EA0_WRREQ_64B"), g(c, "TCC_EA0_WRREQ")
+        if None not in (w64, wq):
+            wr = 64 * w64 + 32 * (wq - w64)
+            line("write_bytes", wr)
+        if rd is not None and wr is not None:
+            line("bytes_per_launch", rd + wr)
+        if rq and g(c, "TCC_EA0_RDREQ_DRAM") is not None:
+            line("read_requests_to_dram_pct", 100.0 * g(c, "TCC_EA0_RDREQ_DRAM") / rq, "%.1f")
+        if wq and g(c, "TCC_EA0_WRREQ_DRAM") is not None:
+            line("write_requests_to_dram_pct", 100.0 * g(c, "TCC_EA0_WRREQ_DRAM") / wq, "%.1f")
+        hit, miss = g(c, "TCC_HIT"), g(c, "TCC_MISS")
         if hit is not None and miss is not None and hit + miss > 0:
-            out.append("%s_L2_hit_pct=%.1f" % (name, 100.0 * hit / (hit + miss)))
-        acc, req = med.get("TCP_TOTAL_CACHE_ACCESSES_sum"), med.get("TCP_TCC_READ_REQ_sum")
+            line("L2_hit_pct", 100.0 * hit / (hit + miss), "%.1f")
+        acc, req = g(c, "TCP_TOTAL_CACHE_ACCESSES"), g(c, "TCP_TCC_READ_REQ")
         if acc and req is not None:
-            out.append("%s_L1_reads_sent_to_L2_pct=%.1f" % (name, 100.0 * req / acc))
-        bc, act = med.get("SQ_LDS_BANK_CONFLICT"), med.get("SQ_LDS_IDX_ACTIVE")
+            line("L1_accesses_sent_to_L2_pct", 100.0 * req / acc, "%.1f")
+        bc, act = g(c, "SQ_LDS_BANK_CONFLICT"), g(c, "SQ_LDS_IDX_ACTIVE")
         if act and bc is not None:
-            out.append("%s_LDS_bank_conflict_pct_of_active=%.1f" % (name, 100.0 * bc / act))
-    os.makedirs(os.path.dirname(CACHE_FILE), exist_ok=True)
-    with open(CACHE_FILE, "w") as f:
+            line("LDS_bank_conflict_pct_of_active", 100.0 * bc / act, "%.1f")
+        for raw in ("SQ_INSTS_LDS", "SQ_INSTS_LDS_ATOMIC", "SQ_INSTS_VMEM_RD", "SQ_WAVES"):
+            if g(c, raw) is not None:
+                line(raw, g(c, raw))
+        wc = g(c, "SQ_WAVE_CYCLES")
+        if wc:
+            for num, key in (("SQ_WAIT_ANY", "waiting_pct_of_resident"),
+                             ("SQ_WAIT_INST_ANY", "waiting_on_issue_pct_of_resident"),
+                             ("SQ_ACTIVE_INST_ANY", "issuing_pct_of_resident"),
+                             ("SQ_ACTIVE_INST_VMEM", "vmem_issue_pct_of_resident"),
+                             ("SQ_ACTIVE_INST_LDS", "lds_issue_pct_of_resident")):
+                if g(c, num) is not None:
+                    line(key, 100.0 * g(c, num) / wc, "%.1f")
+            if g(c, "SQ_BUSY_CU_CYCLES"):
+                line("resident_waves_per_simd", wc / g(c, "SQ_BUSY_CU_CYCLES"), "%.2f")
+        lat, lreq = g(c, "TCP_TCC_READ_REQ_LATENCY"), g(c, "TCP_TCC_READ_REQ")
+        if lat is not None and lreq:
+            line("L1_to_L2_read_latency_cycles", lat / lreq, "%.0f")
+        lev = g(c, "TCC_EA0_RDREQ_LEVEL")
+        if lev is not None and rq:
+            line("L2_to_memory_read_latency_cycles", lev / rq, "%.0f")
+        if lev is not None and g(c, "GRBM_GUI_ACTIVE"):
+            line("L2_to_memory_reads_in_flight", lev / g(c, "GRBM_GUI_ACTIVE"), "%.0f")
+        if g(c, "TA_TA_BUSY") is not None and g(c, "TA_ADDR_STALLED_BY_TC_CYCLES") is not None and g(c, "TA_TA_BUSY"):
+            line("TA_addr_stalled_by_L1_pct_of_busy", 100.0 * g(c, "TA_ADDR_STALLED_BY_TC_CYCLES")
+                 / g(c, "TA_TA_BUSY"), "%.1f")
+    # the probe's known traffic: reads 1 GiB (read stream), reads and writes 1 GiB (copy)
+    for kern, want_rd, want_wr in (("bw_probe_read", 1 << 30, 0), ("bw_probe_copy", 1 << 30, 1 << 30)):
+        got = [line for line in out if line.startswith(kern + ".read_bytes=")]
+        if got:
+            rd = float(got[0].split("=")[1])
+            out.append("check.%s_read_bytes_over_1GiB=%.4f" % (kern, rd / want_rd))
+        gw = [line for line in out if line.startswith(kern + ".write_bytes=")]
+        if gw and want_wr:
+            out.append("check.%s_write_bytes_over_1GiB=%.4f" % (kern, float(gw[0].split("=")[1]) / want_wr))
+    if workload == "wide":
+        # the headline kernels (binary64 values and vectors, one right-hand side)
+        for base in ("vtm_wave", "mv_bucket", "mv_reduce", "zone_fixup", "gather_vec"):
+            for kern in order:
+                if kern.startswith(base + "<") and "f64" in kern and not kern.endswith(",true>") \
+                        and "f32" not in kern and "bf16" not in kern:
+                    hit = [line for line in out if line.startswith(kern + ".bytes_per_launch=")]
+                    if hit:
+                        out.append("%s_bytes_per_launch=%s" % (base, hit[0].split("=")[1]))
+                    break
+    path = COUNTER_FILES[workload]
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -1067,7 +1220,7 @@ def summarize_serving_busy(trace_dir: str):
     print("\n".join(out))
 
 
-def summarize_stats(stats_dir: str, solver: bool = False):
+def summarize_stats(stats_dir: str, solver: bool = False, batched: bool = False):
     """Fold the kernel_stats.csv of a `rocprofv3 --kernel-trace --stats` run of
     the main benchmark (STATS_COMMAND), or of the run that adds the solver
     section (SOLVER_STATS_COMMAND), into its kernel statistics summary."""
@@ -1080,7 +1233,13 @@ def summarize_stats(stats_dir: str, solver: bool = False):
             rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
                          float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     rows.sort(key=lambda t: -t[5])
-    if solver:
+    if batched:
+        head = ["# rocprofv3 kernel statistics for `bench.py --batched-only`: the batching matrix m=20000 n=5e6",
+                "# nnz=50425484 with the autotuner on (creation and the first call of each (direction, k) time",
+                "# candidates), binary64 then binary32, k = 1, 4, 16, 64: 3 timed fused calls and 3 x k plain",
+                "# calls per direction and k.",
+                "# command: %s ; python3 bench.py --batched-stats-summary <dir>" % BATCHED_STATS_COMMAND]
+    elif solver:
         head = ["# rocprofv3 kernel statistics for the CGLS loop on the wide CSC matrix m=50000 n=2e7",
                 "# nnz=200201679, binary64: 1 + 3 profiled and 2 + 3 timed pairs on rotating x and v, 2 + 3 on one",
                 "# x and v, then spw_cgls calls of 2, 3 x 0, 4 x 20 iterations (90 of the 104 product pairs).",
@@ -1093,10 +1252,8 @@ def summarize_stats(stats_dir: str, solver: bool = False):
     out = head + ["kernel_source_sha256_16=%s" % kernel_hash(),
                   "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
     for name, calls, avg, mn, mx, pct in rows:
-        short = name.replace("spw::(anonymous namespace)::", "").replace("void ", "")
-        short = short.split("(")[0][:56]
-        out.append("%-56s %5d %10.2f %10.2f %10.2f %7.2f%%" % (short, calls, avg, mn, mx, pct))
-    with open(SOLVER_STATS_FILE if solver else STATS_FILE, "w") as f:
+        out.append("%-56s %5d %10.2f %10.2f %10.2f %7.2f%%" % (kernel_label(name)[:56], calls, avg, mn, mx, pct))
+    with open(BATCHED_STATS_FILE if batched else SOLVER_STATS_FILE if solver else STATS_FILE, "w") as f:
         f.write("\n".join(out) + "\n")
     print("\n".join(out))
 

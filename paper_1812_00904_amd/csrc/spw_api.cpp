@@ -860,8 +860,7 @@ spw_status grow_scratch(spw_matrix_s &A, int32_t k)
         if ((st = dev_alloc(A, &A.scratch.partial, std::max<int64_t>(A.mv_wgs, 1) * A.panel_rows, "partial sums")))
             return st;
     }
-    int64_t nch = A.cd.zp.n_chunks;
-    for (const ColDot &T : A.cdt) nch = std::max<int64_t>(nch, T.zp.n_chunks);
+    const int64_t nch = std::max<int64_t>(A.cd.zp.n_chunks, A.cdt.zp.n_chunks);
     if (A.scratch.kcap >= k && A.scratch.carry_chunks >= nch) return SPW_OK;
     k = std::max<int32_t>(k, A.scratch.kcap);
     // grow the k-wide buffers: free the old ones once the device is idle
@@ -1334,37 +1333,25 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
     if ((st = plan_workers(*A, A->cd, ptr, A->partition))) return st;
 
     // The transpose (caller's numbering), used by the tiled multi-RHS scatter
-    // products: its column dots are the rows of B.  It is kept in blocks of
-    // TRANSPOSE_BLOCK_ROWS of B's columns; block b is the CSC of the rows of
-    // B restricted to its columns, with column indices relative to the block.
+    // products: its column dots are the rows of B.
     if ((opts.transpose > 0 || (opts.transpose < 0 && opts.autotune)) && nnz > 0) {
-        const int64_t TBR = TRANSPOSE_BLOCK_ROWS;
-        const int64_t nb = (cols + TBR - 1) / TBR;
-        A->cdt.resize((size_t)nb);
-        A->cdt_row0.assign((size_t)nb + 1, 0);
-        for (int64_t b = 0; b < nb; ++b) {
-            const int64_t j0 = b * TBR, j1 = std::min(cols, j0 + TBR);
-            A->cdt_row0[(size_t)b] = j0;
-            A->cdt_row0[(size_t)b + 1] = j1;
-            const int64_t bnnz = ptr[j1] - ptr[j0];
-            std::vector<int64_t> tptr((size_t)rows + 1, 0);
-            for (int64_t p = ptr[j0]; p < ptr[j1]; ++p) tptr[(size_t)idx[p] + 1]++;
-            for (int64_t r = 0; r < rows; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
-            std::vector<int32_t> tidx((size_t)std::max<int64_t>(bnnz, 1));
-            std::vector<double> tval((size_t)std::max<int64_t>(bnnz, 1));
-            {
-                std::vector<int64_t> cur(tptr.begin(), tptr.end() - 1);
-                for (int64_t j = j0; j < j1; ++j)
-                    for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
-                        const int64_t dst = cur[(size_t)idx[p]]++;
-                        tidx[(size_t)dst] = (int32_t)(j - j0);
-                        tval[(size_t)dst] = val[p];
-                    }
-            }
-            if ((st = build_coldot(*A, A->cdt[(size_t)b], j1 - j0, rows, tptr.data(), tidx.data(), tval.data(),
-                                   A->value_storage, vtm_chunk_default())))
-                return st;
+        std::vector<int64_t> tptr((size_t)rows + 1, 0);
+        for (int64_t p = 0; p < nnz; ++p) tptr[(size_t)idx[p] + 1]++;
+        for (int64_t r = 0; r < rows; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
+        std::vector<int32_t> tidx((size_t)nnz);
+        std::vector<double> tval((size_t)nnz);
+        {
+            std::vector<int64_t> cur(tptr.begin(), tptr.end() - 1);
+            for (int64_t j = 0; j < cols; ++j)
+                for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
+                    const int64_t dst = cur[(size_t)idx[p]]++;
+                    tidx[(size_t)dst] = (int32_t)j;
+                    tval[(size_t)dst] = val[p];
+                }
         }
+        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data(), A->value_storage,
+                               vtm_chunk_default())))
+            return st;
     }
 
     // Scatter-product storage.
@@ -1504,7 +1491,7 @@ static spw_status spw_info_impl(spw_matrix A, spw_matrix_info *o)
     o->panel_rows = A->panel_rows;
     o->mv_workgroups = A->mv_wgs;
     o->index_bytes = A->cd.idx_kind == IdxKind::U16 ? 2 : 4;
-    o->has_transpose = A->cdt.empty() ? 0 : 1;
+    o->has_transpose = A->cdt.built ? 1 : 0;
     o->partition = A->partition;
     o->workers = A->cd.n_workers;
     o->worker_max_nnz = A->cd.worker_max_nnz;
@@ -1539,14 +1526,14 @@ namespace {
 // read once and reduced per column up to 6 columns, tiles from about 7 on.
 int32_t rule_plan(const spw_matrix_s &A, bool scatter, int32_t k, int64_t ldo)
 {
-    if (scatter) return (k < 16 || A.cdt.empty()) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
+    if (scatter) return (k < 16 || !A.cdt.built) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
     return (k <= 6 && ldo < CHUNK_OUT_LD_LIMIT) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
 }
 
 bool plan_runs(const spw_matrix_s &A, bool scatter, int32_t plan, int64_t ldo)
 {
     if (plan < SPW_PLAN_SINGLE || plan > SPW_PLAN_TILE) return false;
-    if (scatter) return plan != SPW_PLAN_TILE || !A.cdt.empty();
+    if (scatter) return plan != SPW_PLAN_TILE || A.cdt.built;
     // the chunk-per-wave column dots address outputs through a 2^31-byte view
     return plan == SPW_PLAN_TILE || ldo < CHUNK_OUT_LD_LIMIT;
 }
@@ -1569,13 +1556,7 @@ int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t
     if (plan == SPW_PLAN_TILE) {
         if (scatter) {
             if (A.nnz == 0) return launch_zero_fill(vdt, k, out, ldo, A.rows, stream);   // all outputs are zero
-            // block b reads rows cdt_row0[b] .. of X and adds into Y after the first
-            for (size_t b = 0; b < A.cdt.size(); ++b) {
-                const void *xb = (const char *)in + (size_t)A.cdt_row0[b] * (size_t)ldi * es;
-                const int e = launch_coldot_batch(A, A.cdt[b], nullptr, vdt, k, xb, ldi, out, ldo, stream, b > 0);
-                if (e) return e;
-            }
-            return 0;
+            return launch_coldot_batch(A, A.cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
         }
         return launch_coldot_batch(A, A.cd, A.relabeled ? A.d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
     }
@@ -1721,7 +1702,7 @@ static spw_status set_batch_plan_impl(spw_matrix A, spw_op op, spw_dtype vdt, in
         plan < SPW_PLAN_AUTO || plan > SPW_PLAN_TILE)
         return fail(SPW_ERR_INVALID_ARG, "spw_set_batch_plan: bad op, vector type, k (2..64) or plan");
     const bool scatter = (A->format == SPW_CSC) == (op == SPW_OP_MV);
-    if (plan == SPW_PLAN_TILE && scatter && A->cdt.empty())
+    if (plan == SPW_PLAN_TILE && scatter && !A->cdt.built)
         return fail(SPW_ERR_UNSUPPORTED, "spw_set_batch_plan: the tiled plan of this direction needs the kept transpose");
     std::lock_guard<std::mutex> lk(A->plan_mu);
     if (plan == SPW_PLAN_AUTO) A->plans.erase(plan_slot(scatter, vdt, k));

@@ -122,12 +122,7 @@ struct spw_matrix_s {
     // caller or the tuner (spw_plan values); absent = the fixed rule.
     std::mutex plan_mu;
     std::map<int64_t, int32_t> plans;
-    // B^T (caller's numbering), for the tiled multi-RHS scatter products, in
-    // blocks of at most TRANSPOSE_BLOCK_ROWS of its rows (B's columns): block b
-    // holds B's columns cdt_row0[b] .. cdt_row0[b+1]-1, so that the rows of X a
-    // block gathers stay within a cache-sized slice.
-    std::vector<spw::ColDot> cdt;
-    std::vector<int64_t> cdt_row0;
+    spw::ColDot cdt;                    // B^T (caller's numbering), for multi-RHS scatter products
 
     // scatter-product storage: row panels; inside a panel, per workgroup column
     // range and per wave (a set of the panel's rows), blocks of 512 nonzeros
@@ -196,13 +191,8 @@ inline int32_t coldot_tile_width(int32_t k)
 }
 // Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
 // inv renumbers the rows of V (NULL when C uses the caller's numbering).
-// acc = true adds the results into U instead of overwriting it (columns of
-// C with no nonzero leave U unchanged): the blocks of a blocked transpose are
-// summed into U in block order.
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream, bool acc = false);
-// Rows of B^T per block of the kept transpose (a power of two).
-constexpr int64_t TRANSPOSE_BLOCK_ROWS = (int64_t)1 << 18;
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream);
 // Fills rows x k of a row-major block (leading dimension ld) with zeros.
 int launch_zero_fill(spw_dtype vdt, int32_t k, void *out, int64_t ld, int64_t rows, void *stream);
 // Device-side limits the host plan must respect.

@@ -176,9 +176,7 @@ constexpr int TILE_BLOCK = 256;
 // boundaries (ldv a multiple of CW, V 16-byte aligned) and hold at least
 // L*CW entries, or k must be a multiple of CW.  Every column is computed with
 // the same operations in the same order whatever CW is.
-// ACC: add the results into U (U += C^T V) instead of overwriting it.
-template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, bool ACC = false,
-          int BS = TILE_BS>
+template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
@@ -248,10 +246,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
         if (before) carry[(2 * cc) * k + col] = value;
         else if (after) carry[(2 * cc + 1) * k + col] = value;
-        else {
-            VecT *o = U + column(q) * ldu + col;
-            *o = ACC ? (VecT)((double)*o + value) : (VecT)value;
-        }
+        else U[column(q) * ldu + col] = (VecT)value;
     };
     auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
         cc = c;
@@ -343,10 +338,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
                         const int64_t row = column(base + rel) * ldu;
 #pragma unroll
                         for (int w = 0; w < CW; ++w)
-                            if (c0 + w < k) {
-                                VecT *o = U + row + c0 + w;
-                                *o = ACC ? (VecT)((double)*o + run[w]) : (VecT)run[w];
-                            }
+                            if (c0 + w < k) U[row + c0 + w] = (VecT)run[w];
                     }
                     ++rel;
 #pragma unroll
@@ -383,9 +375,8 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     }
 }
 
-// Multi-RHS zone reduction: one lane per (zone, right-hand side); ACC adds
-// the zone's sum into U.
-template <typename VoutT, bool ACC = false>
+// Multi-RHS zone reduction: one lane per (zone, right-hand side).
+template <typename VoutT>
 __global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t *__restrict__ zfirst,
                                  const int32_t *__restrict__ zlast, int64_t nz, int k,
                                  const double *__restrict__ carry, VoutT *__restrict__ U, int64_t ldu)
@@ -397,8 +388,7 @@ __global__ void zone_fixup_batch(const int32_t *__restrict__ zcol, const int32_t
     const int a = zfirst[z], b = zlast[z];
     double s = carry[(2 * (int64_t)a + 1) * k + cc];
     for (int c = a + 1; c <= b; ++c) s += carry[(2 * (int64_t)c) * k + cc];
-    VoutT *o = U + (int64_t)zcol[z] * ldu + cc;
-    *o = ACC ? (VoutT)((double)*o + s) : (VoutT)s;
+    U[(int64_t)zcol[z] * ldu + cc] = (VoutT)s;
 }
 
 template <typename VoutT>
@@ -440,7 +430,7 @@ void tile_shape(int k, bool wide, int *L, int *CW)
     *CW = cw;
 }
 
-template <int ITEMS, bool ACC, typename IdxT, typename ValT, typename VecT>
+template <int ITEMS, typename IdxT, typename ValT, typename VecT>
 int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U,
                       int64_t ldu, bool wide, hipStream_t stream)
 {
@@ -466,7 +456,7 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
         return (int)hipGetLastError();
     };
 #define SPW_TILE(LL, WW) \
-    if (L == LL && CW == WW) return go(cdot_tile<IdxT, ValT, VecT, LL, ITEMS, WW, ACC>);
+    if (L == LL && CW == WW) return go(cdot_tile<IdxT, ValT, VecT, LL, ITEMS, WW>);
     SPW_TILE(2, 1) SPW_TILE(4, 1) SPW_TILE(8, 1) SPW_TILE(16, 1) SPW_TILE(32, 1) SPW_TILE(64, 1)
     SPW_TILE(1, 2) SPW_TILE(2, 2) SPW_TILE(4, 2) SPW_TILE(8, 2) SPW_TILE(16, 2) SPW_TILE(32, 2)
     if constexpr (sizeof(VecT) == 4) {
@@ -477,28 +467,22 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
 }
 
 // Chunks of 1,024 or 512 nonzeros (16 or 8 positions per layout lane).
-// Chunks of 1,024 or 512 nonzeros; acc (the blocks after the first of a
-// blocked transpose, whose chunks are always 1,024 nonzeros) adds into U.
+// Chunks of 1,024 or 512 nonzeros.
 template <typename IdxT, typename ValT, typename VecT>
 int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
-                bool wide, bool acc, hipStream_t stream)
+                bool wide, hipStream_t stream)
 {
-    if (acc) {
-        if (C.zp.chunk == 1024)
-            return launch_tile_items<16, true, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
-        return (int)hipErrorNotSupported;
-    }
-    if (C.zp.chunk == 1024) return launch_tile_items<16, false, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
-    if (C.zp.chunk == 512) return launch_tile_items<8, false, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
+    if (C.zp.chunk == 1024) return launch_tile_items<16, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
+    if (C.zp.chunk == 512) return launch_tile_items<8, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
     return (int)hipErrorNotSupported;
 }
 
 template <typename ValT, typename VecT>
 int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VecT *V,
-                       int64_t ldv, VecT *U, int64_t ldu, bool acc, hipStream_t stream)
+                       int64_t ldv, VecT *U, int64_t ldu, hipStream_t stream)
 {
     int e;
-    if (C.n_empty > 0 && !acc) {       // adding zero changes nothing
+    if (C.n_empty > 0) {
         ProfScope ps(stream, "zero_cols_batch");
         hipLaunchKernelGGL(zero_cols_batch<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
                            C.d_empty, C.n_empty, k, U, ldu);
@@ -530,20 +514,14 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
         const bool wide = inv != nullptr ||
                           (k % CWw == 0 && ldin % CWw == 0 && ((uintptr_t)Vin % 16) == 0);
         e = C.idx_kind == IdxKind::U16
-                ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, acc, stream)
-                : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, acc, stream);
+                ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, stream)
+                : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, stream);
         if (e) return e;
     }
     if (C.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup_batch");
-        if (acc)
-            hipLaunchKernelGGL((zone_fixup_batch<VecT, true>), dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0,
-                               stream, C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U,
-                               ldu);
-        else
-            hipLaunchKernelGGL((zone_fixup_batch<VecT, false>), dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0,
-                               stream, C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U,
-                               ldu);
+        hipLaunchKernelGGL(zone_fixup_batch<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+                           C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
     return 0;
@@ -551,14 +529,14 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
 }  // namespace
 
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream, bool acc)
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream)
 {
     if (k < 1 || k > 64) return (int)hipErrorNotSupported;
     if (C.cols == 0) return 0;
     return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
         using ValT = decltype(vt);
         using VecT = decltype(xt);
-        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu, acc,
+        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
                                               (hipStream_t)stream);
     });
 }

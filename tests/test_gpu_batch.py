@@ -89,10 +89,9 @@ def test_batch_small_config(spw, fmt, k, dtype):
 @pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("k", [16, 33, 64])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_batch_over_blocked_transpose(spw, fmt, k, dtype):
-    # 600,000 long-side entries: the kept transpose is three blocks of 2^18 of
-    # them, summed into the output in block order; some rows of the long side
-    # hold no nonzero in a block (the output keeps the earlier blocks' sums)
+def test_batch_tiles_over_long_transpose(spw, fmt, k, dtype):
+    # 600,000 long-side entries, 30 % of them empty: the tiled plan of the
+    # scatter direction over the kept transpose (int32 indices there)
     A = synth.random_csc(150, 600000, 1.5, 60 + k, values="lognormal", empty_frac=0.3)
     m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
     M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=1)
@@ -103,7 +102,7 @@ def test_batch_over_blocked_transpose(spw, fmt, k, dtype):
     in_len, out_len = (n, m) if op == spw.SPW_OP_MV else (m, n)
     X, Xd = block(in_len, k, 70 + k, 1, dtype, 0)
     Y = torch.full((out_len, k), float("nan"), dtype=dtype, device="cuda")
-    print("blocked transpose fmt=%d k=%d %s" % (fmt, k, dtype), flush=True)
+    print("tiles over the transpose fmt=%d k=%d %s" % (fmt, k, dtype), flush=True)
     (M.mv_batch if op == spw.SPW_OP_MV else M.vtm_batch)(Xd, Y)
     Y2 = (M.mv_batch if op == spw.SPW_OP_MV else M.vtm_batch)(Xd)
     torch.cuda.synchronize()
@@ -112,7 +111,7 @@ def test_batch_over_blocked_transpose(spw, fmt, k, dtype):
         Yr, D = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
     else:
         Yr, D = oracle.vtm_csr_batch(A.n, A.m, A.ptr, A.idx, A.val, X, with_d=True)
-    check(Y.double().cpu().numpy(), Yr, D, "blocked transpose", 1e-13 if dtype == torch.float64 else 1e-5)
+    check(Y.double().cpu().numpy(), Yr, D, "tiles over the transpose", 1e-13 if dtype == torch.float64 else 1e-5)
     M.close()
 
 
@@ -233,6 +232,6 @@ def test_column_dots_with_output_leading_dimension_past_chunk_views(spw, fmt, k)
 @pytest.mark.parametrize("k, dtype", [(64, torch.float64), (16, torch.float32)])
 def test_batching_matrix_full_size(spw, k, dtype):
     # the 5e7-nonzero batching matrix at full size, at widths the benchmark times
-    # (the transpose kept: A x of k >= 16 columns runs over its 20 blocks)
+    # (the transpose kept: A x of k >= 16 columns runs the tiles over it)
     A = synth.config_matrix("c2")
     run_case(spw, A, 0, k, dtype, 0, 50 + k, "c2 full", opts={"transpose": 1})
