@@ -1333,25 +1333,37 @@ static spw_status spw_create_impl(spw_matrix *out, spw_format fmt, int64_t m, in
     if ((st = plan_workers(*A, A->cd, ptr, A->partition))) return st;
 
     // The transpose (caller's numbering), used by the tiled multi-RHS scatter
-    // products: its column dots are the rows of B.
+    // products: its column dots are the rows of B.  It is kept in blocks of
+    // TRANSPOSE_BLOCK_ROWS of B's columns: column b*rows + i holds B's row i
+    // within block b, so the chunks of one block, which the workgroups take
+    // about together, gather only that block's rows of the input.
     if ((opts.transpose > 0 || (opts.transpose < 0 && opts.autotune)) && nnz > 0) {
-        std::vector<int64_t> tptr((size_t)rows + 1, 0);
-        for (int64_t p = 0; p < nnz; ++p) tptr[(size_t)idx[p] + 1]++;
-        for (int64_t r = 0; r < rows; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
+        const int64_t R = TRANSPOSE_BLOCK_ROWS;
+        const int64_t nb = std::max<int64_t>(1, (cols + R - 1) / R);
+        const int64_t vcols = nb * rows;
+        std::vector<int64_t> tptr((size_t)vcols + 1, 0);
+        for (int64_t j = 0; j < cols; ++j) {
+            const int64_t off = (j / R) * rows + 1;
+            for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) tptr[(size_t)(off + idx[p])]++;
+        }
+        for (int64_t r = 0; r < vcols; ++r) tptr[(size_t)r + 1] += tptr[(size_t)r];
         std::vector<int32_t> tidx((size_t)nnz);
         std::vector<double> tval((size_t)nnz);
         {
             std::vector<int64_t> cur(tptr.begin(), tptr.end() - 1);
-            for (int64_t j = 0; j < cols; ++j)
+            for (int64_t j = 0; j < cols; ++j) {
+                const int64_t off = (j / R) * rows;
                 for (int64_t p = ptr[j]; p < ptr[j + 1]; ++p) {
-                    const int64_t dst = cur[(size_t)idx[p]]++;
+                    const int64_t dst = cur[(size_t)(off + idx[p])]++;
                     tidx[(size_t)dst] = (int32_t)j;
                     tval[(size_t)dst] = val[p];
                 }
+            }
         }
-        if ((st = build_coldot(*A, A->cdt, cols, rows, tptr.data(), tidx.data(), tval.data(), A->value_storage,
+        if ((st = build_coldot(*A, A->cdt, cols, vcols, tptr.data(), tidx.data(), tval.data(), A->value_storage,
                                vtm_chunk_default())))
             return st;
+        A->cdt_blocks = nb;
     }
 
     // Scatter-product storage.
@@ -1548,6 +1560,29 @@ std::string plan_cache_key(bool scatter, spw_dtype vdt, int32_t k)
     return std::string("plan.") + (scatter ? "sc." : "cd.") + vdt_tag(vdt) + ".k" + std::to_string(k);
 }
 
+// The binary64 partial sums of the blocked transpose for k columns; grown
+// once the device is idle.  Returns a HIP error code.
+int grow_cdt_partial(spw_matrix_s &A, int32_t k)
+{
+    const int64_t need = A.cdt.cols * (int64_t)k;
+    if (A.cdt_partial_elems >= need) return 0;
+    if (A.cdt_partial) {
+        if (hipDeviceSynchronize() != hipSuccess) return (int)hipGetLastError();
+        for (size_t i = 0; i < A.allocations.size(); ++i)
+            if (A.allocations[i].first == A.cdt_partial) {
+                A.device_bytes -= A.allocations[i].second;
+                A.allocations.erase(A.allocations.begin() + (long)i);
+                break;
+            }
+        (void)hipFree(A.cdt_partial);
+        A.cdt_partial = nullptr;
+        A.cdt_partial_elems = 0;
+    }
+    if (dev_alloc(A, &A.cdt_partial, need, "partial sums of the blocked transpose")) return (int)hipErrorOutOfMemory;
+    A.cdt_partial_elems = need;
+    return 0;
+}
+
 // Runs a k-column product with one plan; returns a HIP error code.
 int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
              void *out, int64_t ldo, void *stream)
@@ -1556,7 +1591,12 @@ int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t
     if (plan == SPW_PLAN_TILE) {
         if (scatter) {
             if (A.nnz == 0) return launch_zero_fill(vdt, k, out, ldo, A.rows, stream);   // all outputs are zero
-            return launch_coldot_batch(A, A.cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
+            if (A.cdt_blocks <= 1) return launch_coldot_batch(A, A.cdt, nullptr, vdt, k, in, ldi, out, ldo, stream);
+            // one launch over every block into binary64 partial sums, then their sum in block order
+            int e = grow_cdt_partial(A, k);
+            if (!e) e = launch_coldot_batch(A, A.cdt, nullptr, vdt, k, in, ldi, A.cdt_partial, k, stream, true);
+            if (!e) e = launch_sum_blocks(vdt, A.cdt_blocks, A.rows, k, A.cdt_partial, out, ldo, stream);
+            return e;
         }
         return launch_coldot_batch(A, A.cd, A.relabeled ? A.d_inv : nullptr, vdt, k, in, ldi, out, ldo, stream);
     }

@@ -122,7 +122,13 @@ struct spw_matrix_s {
     // caller or the tuner (spw_plan values); absent = the fixed rule.
     std::mutex plan_mu;
     std::map<int64_t, int32_t> plans;
-    spw::ColDot cdt;                    // B^T (caller's numbering), for multi-RHS scatter products
+    // B^T (caller's numbering), for multi-RHS scatter products, in blocks of
+    // TRANSPOSE_BLOCK_ROWS of its rows: column b*rows + i of cdt holds the
+    // entries of B's row i in B's columns b*R .. (b+1)*R-1
+    spw::ColDot cdt;
+    int64_t cdt_blocks = 1;
+    double *cdt_partial = nullptr;      // cdt.cols x k binary64 partial sums (cdt_blocks > 1)
+    int64_t cdt_partial_elems = 0;
 
     // scatter-product storage: row panels; inside a panel, per workgroup column
     // range and per wave (a set of the panel's rows), blocks of 512 nonzeros
@@ -191,8 +197,16 @@ inline int32_t coldot_tile_width(int32_t k)
 }
 // Multi-RHS column dots over C (U = C^T V): V is C.rows x k, U is C.cols x k.
 // inv renumbers the rows of V (NULL when C uses the caller's numbering).
+// out_f64: U holds binary64 whatever vdt is (the blocked transpose's partial sums).
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream);
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream, bool out_f64 = false);
+// out (rows x k, leading dimension ldo, type vdt) = the sum of nb binary64 blocks
+// of rows x k partial sums (block b at P + b*rows*k, row stride k), in block order.
+int launch_sum_blocks(spw_dtype vdt, int64_t nb, int64_t rows, int32_t k, const double *P, void *out, int64_t ldo,
+                      void *stream);
+// Rows of the long side per block of the kept transpose: a block's slice of a
+// 64-column binary64 input is 128 MiB, which the Infinity Cache holds.
+constexpr int64_t TRANSPOSE_BLOCK_ROWS = (int64_t)1 << 18;
 // Fills rows x k of a row-major block (leading dimension ld) with zeros.
 int launch_zero_fill(spw_dtype vdt, int32_t k, void *out, int64_t ld, int64_t rows, void *stream);
 // Device-side limits the host plan must respect.

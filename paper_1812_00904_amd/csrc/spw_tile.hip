@@ -2,6 +2,8 @@
 // column lanes x position sub-groups), its zone reduction and the launch glue
 // of the k-column products that run it (spw_mv_batch / spw_vtm_batch with
 // the tiled plan).  Shared helpers: spw_device.h.
+#include <type_traits>
+
 #include "spw_device.h"
 
 namespace spw {
@@ -176,11 +178,13 @@ constexpr int TILE_BLOCK = 256;
 // boundaries (ldv a multiple of CW, V 16-byte aligned) and hold at least
 // L*CW entries, or k must be a multiple of CW.  Every column is computed with
 // the same operations in the same order whatever CW is.
-template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, int BS = TILE_BS>
+// OutT: the type of U (binary64 partial sums for binary32 inputs, or VecT).
+template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, typename OutT = VecT,
+          int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
-    const VecT *__restrict__ V, int64_t ldv, VecT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
+    const VecT *__restrict__ V, int64_t ldv, OutT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
 {
     constexpr int S = WAVE / L;                   // sub-groups per wave
     constexpr int PPL = ITEMS / BS;               // batches per layout lane
@@ -246,7 +250,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
         if (before) carry[(2 * cc) * k + col] = value;
         else if (after) carry[(2 * cc + 1) * k + col] = value;
-        else U[column(q) * ldu + col] = (VecT)value;
+        else U[column(q) * ldu + col] = (OutT)value;
     };
     auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
         cc = c;
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
                         const int64_t row = column(base + rel) * ldu;
 #pragma unroll
                         for (int w = 0; w < CW; ++w)
-                            if (c0 + w < k) U[row + c0 + w] = (VecT)run[w];
+                            if (c0 + w < k) U[row + c0 + w] = (OutT)run[w];
                     }
                     ++rel;
 #pragma unroll
@@ -430,8 +434,8 @@ void tile_shape(int k, bool wide, int *L, int *CW)
     *CW = cw;
 }
 
-template <int ITEMS, typename IdxT, typename ValT, typename VecT>
-int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U,
+template <int ITEMS, typename IdxT, typename ValT, typename VecT, typename OutT>
+int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, OutT *U,
                       int64_t ldu, bool wide, hipStream_t stream)
 {
     int L = 2, CW = 1;
@@ -456,7 +460,7 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
         return (int)hipGetLastError();
     };
 #define SPW_TILE(LL, WW) \
-    if (L == LL && CW == WW) return go(cdot_tile<IdxT, ValT, VecT, LL, ITEMS, WW>);
+    if (L == LL && CW == WW) return go(cdot_tile<IdxT, ValT, VecT, LL, ITEMS, WW, OutT>);
     SPW_TILE(2, 1) SPW_TILE(4, 1) SPW_TILE(8, 1) SPW_TILE(16, 1) SPW_TILE(32, 1) SPW_TILE(64, 1)
     SPW_TILE(1, 2) SPW_TILE(2, 2) SPW_TILE(4, 2) SPW_TILE(8, 2) SPW_TILE(16, 2) SPW_TILE(32, 2)
     if constexpr (sizeof(VecT) == 4) {
@@ -468,23 +472,24 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
 
 // Chunks of 1,024 or 512 nonzeros (16 or 8 positions per layout lane).
 // Chunks of 1,024 or 512 nonzeros.
-template <typename IdxT, typename ValT, typename VecT>
-int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, VecT *U, int64_t ldu,
+template <typename IdxT, typename ValT, typename VecT, typename OutT>
+int launch_tile(const spw_matrix_s &A, const ColDot &C, int k, const VecT *V, int64_t ldv, OutT *U, int64_t ldu,
                 bool wide, hipStream_t stream)
 {
-    if (C.zp.chunk == 1024) return launch_tile_items<16, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
-    if (C.zp.chunk == 512) return launch_tile_items<8, IdxT, ValT, VecT>(A, C, k, V, ldv, U, ldu, wide, stream);
+    if (C.zp.chunk == 1024)
+        return launch_tile_items<16, IdxT, ValT, VecT, OutT>(A, C, k, V, ldv, U, ldu, wide, stream);
+    if (C.zp.chunk == 512) return launch_tile_items<8, IdxT, ValT, VecT, OutT>(A, C, k, V, ldv, U, ldu, wide, stream);
     return (int)hipErrorNotSupported;
 }
 
-template <typename ValT, typename VecT>
+template <typename ValT, typename VecT, typename OutT>
 int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, int k, const VecT *V,
-                       int64_t ldv, VecT *U, int64_t ldu, hipStream_t stream)
+                       int64_t ldv, OutT *U, int64_t ldu, hipStream_t stream)
 {
     int e;
     if (C.n_empty > 0) {
         ProfScope ps(stream, "zero_cols_batch");
-        hipLaunchKernelGGL(zero_cols_batch<VecT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(zero_cols_batch<OutT>, dim3(blocks_for(C.n_empty * k, 256)), dim3(256), 0, stream,
                            C.d_empty, C.n_empty, k, U, ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
@@ -513,14 +518,20 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
         tile_shape<VecT>(k, true, &Lw, &CWw);
         const bool wide = inv != nullptr ||
                           (k % CWw == 0 && ldin % CWw == 0 && ((uintptr_t)Vin % 16) == 0);
-        e = C.idx_kind == IdxKind::U16
-                ? launch_tile<uint16_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, stream)
-                : launch_tile<int32_t, ValT, VecT>(A, C, k, Vin, ldin, U, ldu, wide, stream);
+        if constexpr (std::is_same<OutT, VecT>::value) {
+            e = C.idx_kind == IdxKind::U16
+                    ? launch_tile<uint16_t, ValT, VecT, OutT>(A, C, k, Vin, ldin, U, ldu, wide, stream)
+                    : launch_tile<int32_t, ValT, VecT, OutT>(A, C, k, Vin, ldin, U, ldu, wide, stream);
+        } else {
+            // binary64 partial sums of binary32 inputs: the blocked transpose (4-byte indices) only
+            if (C.idx_kind == IdxKind::U16 || inv) return (int)hipErrorNotSupported;
+            e = launch_tile<int32_t, ValT, VecT, OutT>(A, C, k, Vin, ldin, U, ldu, wide, stream);
+        }
         if (e) return e;
     }
     if (C.n_zones > 0) {
         ProfScope ps(stream, "zone_fixup_batch");
-        hipLaunchKernelGGL(zone_fixup_batch<VecT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(zone_fixup_batch<OutT>, dim3(blocks_for(C.n_zones * k, 256)), dim3(256), 0, stream,
                            C.d_zone_col, C.d_zone_first, C.d_zone_last, C.n_zones, k, A.scratch.carry, U, ldu);
         if ((e = (int)hipGetLastError())) return e;
     }
@@ -529,16 +540,49 @@ int coldot_batch_typed(const spw_matrix_s &A, const ColDot &C, const int32_t *in
 }  // namespace
 
 int launch_coldot_batch(const spw_matrix_s &A, const ColDot &C, const int32_t *inv, spw_dtype vdt, int32_t k,
-                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream)
+                        const void *V, int64_t ldv, void *U, int64_t ldu, void *stream, bool out_f64)
 {
     if (k < 1 || k > 64) return (int)hipErrorNotSupported;
     if (C.cols == 0) return 0;
     return with_types(A.value_storage, vdt, [&](auto vt, auto xt) {
         using ValT = decltype(vt);
         using VecT = decltype(xt);
-        return coldot_batch_typed<ValT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
-                                              (hipStream_t)stream);
+        if (out_f64 && !std::is_same<VecT, double>::value)
+            return coldot_batch_typed<ValT, VecT, double>(A, C, inv, k, (const VecT *)V, ldv, (double *)U, ldu,
+                                                          (hipStream_t)stream);
+        return coldot_batch_typed<ValT, VecT, VecT>(A, C, inv, k, (const VecT *)V, ldv, (VecT *)U, ldu,
+                                                    (hipStream_t)stream);
     });
+}
+
+// Y = the sum over blocks of the partial sums P (nb blocks of rows x k, row
+// stride k), in ascending block order, each output rounded once.
+template <typename VoutT>
+__global__ void sum_blocks(const double *__restrict__ P, int64_t nb, int64_t rows, int k, VoutT *__restrict__ Y,
+                           int64_t ldy)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= rows * k) return;
+    const int64_t r = g / k;
+    const int c = (int)(g - r * k);
+    double s = P[g];
+    for (int64_t b = 1; b < nb; ++b) s += P[(b * rows + r) * k + c];
+    Y[r * ldy + c] = (VoutT)s;
+}
+
+int launch_sum_blocks(spw_dtype vdt, int64_t nb, int64_t rows, int32_t k, const double *P, void *out, int64_t ldo,
+                      void *stream_)
+{
+    hipStream_t stream = (hipStream_t)stream_;
+    if (rows <= 0) return 0;
+    ProfScope ps(stream, "sum_blocks");
+    if (vdt == SPW_F64)
+        hipLaunchKernelGGL(sum_blocks<double>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, P, nb, rows,
+                           (int)k, (double *)out, ldo);
+    else
+        hipLaunchKernelGGL(sum_blocks<float>, dim3(blocks_for(rows * k, 256)), dim3(256), 0, stream, P, nb, rows,
+                           (int)k, (float *)out, ldo);
+    return (int)hipGetLastError();
 }
 
 template <typename T>

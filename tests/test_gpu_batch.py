@@ -91,7 +91,9 @@ def test_batch_small_config(spw, fmt, k, dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_batch_tiles_over_long_transpose(spw, fmt, k, dtype):
     # 600,000 long-side entries, 30 % of them empty: the tiled plan of the
-    # scatter direction over the kept transpose (int32 indices there)
+    # scatter direction over the kept transpose (int32 indices there), which
+    # is kept in three blocks of 2^18 long-side entries whose binary64 partial
+    # sums are added in block order
     A = synth.random_csc(150, 600000, 1.5, 60 + k, values="lognormal", empty_frac=0.3)
     m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
     M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=1)
@@ -111,7 +113,12 @@ def test_batch_tiles_over_long_transpose(spw, fmt, k, dtype):
         Yr, D = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
     else:
         Yr, D = oracle.vtm_csr_batch(A.n, A.m, A.ptr, A.idx, A.val, X, with_d=True)
-    check(Y.double().cpu().numpy(), Yr, D, "tiles over the transpose", 1e-13 if dtype == torch.float64 else 1e-5)
+    got = Y.double().cpu().numpy()
+    check(got, Yr, D, "tiles over the transpose", 1e-13 if dtype == torch.float64 else 1e-5)
+    if dtype == torch.float32:
+        # binary64 partial sums, each output rounded once to binary32
+        bad = np.abs(got - Yr) > 2.0 ** -24 * np.abs(Yr) + 1e-13 * D
+        assert not bad.any(), "binary32 outputs rounded more than once: %d entries" % int(bad.sum())
     M.close()
 
 
