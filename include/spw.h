@@ -105,7 +105,11 @@ typedef struct spw_matrix_s *spw_matrix;
  *                   which the tiled multi-RHS plan of the long-to-short direction
  *                   (CSC A x, CSR v^T A) reads; 0 does not; -1 (default) keeps it
  *                   only with autotune (so the tuner can choose that plan).
- *                   Without it those blocks run scatter passes.
+ *                   Without it those blocks run scatter passes.  It is stored in
+ *                   blocks of 2^18 long-side indices; a tiled call over more
+ *                   than one block allocates (once, on first use) binary64
+ *                   partial sums of blocks x short side x k entries and adds
+ *                   them in block order.
  *   canonicalize  : 0 (default) rejects indices that are not strictly increasing
  *                   inside a column (row) and, in spw_create_coo, repeated
  *                   (row, column) pairs; 1 sorts each column (row) by index and
