@@ -48,8 +48,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 NROT = 4          # input vectors the timed pairs rotate through
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00904_amd", "csrc", f)
-               for f in ("spw_device.h", "spw_kernels.hip", "spw_tile.hip")]
+# the sources of the single-vector kernels the headline roofline is taken on
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00904_amd", "csrc", f) for f in ("spw_device.h", "spw_kernels.hip")]
 COUNTER_FILES = {"wide": os.path.join(ROOT, "profiles", "pmc_counters_wide_2e8.txt"),
                  "batched": os.path.join(ROOT, "profiles", "pmc_counters_batched_5e7.txt")}
 TRAFFIC_FILE = COUNTER_FILES["wide"]
