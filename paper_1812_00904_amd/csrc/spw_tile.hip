@@ -178,13 +178,36 @@ constexpr int TILE_BLOCK = 256;
 // boundaries (ldv a multiple of CW, V 16-byte aligned) and hold at least
 // L*CW entries, or k must be a multiple of CW.  Every column is computed with
 // the same operations in the same order whatever CW is.
+// Stores the CW sums of one lane into a row of U with one store of the whole
+// group (two for four binary64 values).  p is aligned to the group.
+template <typename OutT, int CW>
+__device__ __forceinline__ void put_group(OutT *p, const double *v)
+{
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    if constexpr (sizeof(OutT) == 8 && CW >= 2) {
+#pragma unroll
+        for (int h = 0; h < CW / 2; ++h) reinterpret_cast<f64x2_t *>(p)[h] = f64x2_t{v[2 * h], v[2 * h + 1]};
+    } else if constexpr (sizeof(OutT) == 4 && CW == 4) {
+        *reinterpret_cast<f32x4_t *>(p) = f32x4_t{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else if constexpr (sizeof(OutT) == 4 && CW == 2) {
+        *reinterpret_cast<f32x2_t *>(p) = f32x2_t{(float)v[0], (float)v[1]};
+    } else {
+        *p = (OutT)v[0];
+    }
+}
+
 // OutT: the type of U (binary64 partial sums for binary32 inputs, or VecT).
+// ugroups: U's rows take whole groups of CW entries (ldu a multiple of CW, U
+// aligned to a group), so a lane writes its CW sums with one store: a store
+// instruction then covers whole 16-byte pieces of a row instead of every
+// CW-th entry.
 template <typename IdxT, typename ValT, typename VecT, int L, int ITEMS, int CW = 1, typename OutT = VecT,
           int BS = TILE_BS>
 __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     const IdxT *__restrict__ idx, const ValT *__restrict__ val, const uint16_t *__restrict__ heads,
     const int4 *__restrict__ cinfo, const int32_t *__restrict__ segcol, int64_t nnz, int64_t nchunks, int k,
-    const VecT *__restrict__ V, int64_t ldv, OutT *__restrict__ U, int64_t ldu, double *__restrict__ carry)
+    const VecT *__restrict__ V, int64_t ldv, OutT *__restrict__ U, int64_t ldu, double *__restrict__ carry,
+    int ugroups)
 {
     constexpr int S = WAVE / L;                   // sub-groups per wave
     constexpr int PPL = ITEMS / BS;               // batches per layout lane
@@ -242,15 +265,30 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
     auto column = [&](int q) __attribute__((always_inline)) -> int64_t {
         return (ci.w & CHUNK_DENSE) ? (int64_t)ci.x + q : (int64_t)segcol[ci.y + q];
     };
-    // column c0 + w of segment q: to a carry slot when the chunk cuts it, else to U
-    auto emit = [&](int q, int w, double value) __attribute__((always_inline)) {
-        const int col = c0 + w;
-        if (col >= k) return;
+    // the lane's CW sums of one column of U (row `row` of U)
+    const bool grp = ugroups && c0 + CW <= k;
+    auto put_row = [&](int64_t row, const double *v) __attribute__((always_inline)) {
+        if (grp) {
+            put_group<OutT, CW>(U + row * ldu + c0, v);
+        } else {
+#pragma unroll
+            for (int w = 0; w < CW; ++w)
+                if (c0 + w < k) U[row * ldu + c0 + w] = (OutT)v[w];
+        }
+    };
+    // columns c0 .. c0+CW-1 of segment q: to carry slots when the chunk cuts it, else to U
+    auto emit = [&](int q, const double *v) __attribute__((always_inline)) {
         const bool before = q == 0 && !(ci.w & CHUNK_START_HEAD);
         const bool after = q == ci.z - 1 && (ci.w & CHUNK_END_CONT);
-        if (before) carry[(2 * cc) * k + col] = value;
-        else if (after) carry[(2 * cc + 1) * k + col] = value;
-        else U[column(q) * ldu + col] = (OutT)value;
+        if (before || after) {
+            // a segment cut on both sides (the chunk lies inside one column) is the left carry
+            double *cr = carry + (2 * cc + (before ? 0 : 1)) * k;
+#pragma unroll
+            for (int w = 0; w < CW; ++w)
+                if (c0 + w < k) cr[c0 + w] = v[w];
+        } else {
+            put_row(column(q), v);
+        }
     };
     auto chunk_start = [&](int64_t c) __attribute__((always_inline)) {
         cc = c;
@@ -311,16 +349,19 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
         }
         if (my_n > 0 && colok) {
             if (multi) {
+                double tot[CW];
 #pragma unroll
                 for (int w = 0; w < CW; ++w) {
-                    double tot = head_sum[w];
-                    if (g > 0 && prev_k == hkey) tot = prev_s[w] + head_sum[w];
-                    emit(hkey, w, tot);
+                    tot[w] = head_sum[w];
+                    if (g > 0 && prev_k == hkey) tot[w] = prev_s[w] + head_sum[w];
                 }
+                emit(hkey, tot);
             }
             if (g == S - 1 || next_hk != klast) {
+                double last[CW];
 #pragma unroll
-                for (int w = 0; w < CW; ++w) emit(klast, w, x[w].s);
+                for (int w = 0; w < CW; ++w) last[w] = x[w].s;
+                emit(klast, last);
             }
         }
     };
@@ -339,10 +380,7 @@ __global__ __launch_bounds__(TILE_BLOCK) void cdot_tile(
                         multi = true;
                     } else {
                         // a column wholly inside this sub-group's positions
-                        const int64_t row = column(base + rel) * ldu;
-#pragma unroll
-                        for (int w = 0; w < CW; ++w)
-                            if (c0 + w < k) U[row + c0 + w] = (OutT)run[w];
+                        put_row(column(base + rel), run);
                     }
                     ++rel;
 #pragma unroll
@@ -440,6 +478,9 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
 {
     int L = 2, CW = 1;
     tile_shape<VecT>(k, wide, &L, &CW);
+    // whole groups of CW entries per store when U's rows and base allow them
+    const int64_t gbytes = (int64_t)CW * (int64_t)sizeof(OutT);
+    const bool ugroups = ldu % CW == 0 && (uintptr_t)U % (uintptr_t)gbytes == 0;
     const int cus = device_cu_count(A.device);
     const int64_t want = (C.zp.n_chunks + TILE_BLOCK / WAVE - 1) / (TILE_BLOCK / WAVE);
     // persistent: as many workgroups as the chip keeps resident
@@ -456,7 +497,7 @@ int launch_tile_items(const spw_matrix_s &A, const ColDot &C, int k, const VecT 
         const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * nb, want));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(TILE_BLOCK), 0, stream, (const IdxT *)C.d_idx,
                            (const ValT *)C.d_val, C.d_heads, (const int4 *)C.d_cinfo, C.d_segcol, C.nnz,
-                           C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry);
+                           C.zp.n_chunks, k, V, ldv, U, ldu, A.scratch.carry, ugroups ? 1 : 0);
         return (int)hipGetLastError();
     };
 #define SPW_TILE(LL, WW) \
