@@ -48,8 +48,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Ax / vᵀA effective HBM GB/s (% of peak); batched vs plain; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 NROT = 4          # input vectors the timed pairs rotate through
-# the sources of the single-vector kernels the headline roofline is taken on
+# the sources of the single-vector kernels the headline roofline is taken on, and of the tiles
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00904_amd", "csrc", f) for f in ("spw_device.h", "spw_kernels.hip")]
+TILE_SRCS = [os.path.join(ROOT, "paper_1812_00904_amd", "csrc", "spw_tile.hip")]
 COUNTER_FILES = {"wide": os.path.join(ROOT, "profiles", "pmc_counters_wide_2e8.txt"),
                  "batched": os.path.join(ROOT, "profiles", "pmc_counters_batched_5e7.txt")}
 TRAFFIC_FILE = COUNTER_FILES["wide"]
@@ -82,11 +83,11 @@ def model_bytes(m: int, n: int, nnz: int, k: int = 1, sv: int = 8, sx: int = 8, 
     return nnz * (sv + si) + sp * (n + 1) + k * sx * n + k * sx * m
 
 
-def kernel_hash() -> str:
-    """Hash of the device sources of the product kernels: a counter summary
-    is used only while it matches."""
+def kernel_hash(extra=()) -> str:
+    """Hash of the device sources of the product kernels (and of `extra`
+    sources): a counter summary is used only while it matches."""
     h = hashlib.sha256()
-    for p in KERNEL_SRCS:
+    for p in list(KERNEL_SRCS) + list(extra):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -1075,7 +1076,7 @@ def summarize_counters(workload: str, dirs):
            "# Bytes come from the request counts by size (32, 64, 128 B); no scale factor is applied.",
            "# commands: " + " ; ".join(cmds) + " ; python3 bench.py --counter-summary %s %s"
            % (workload, " ".join("<dir_%s>" % n for n in PMC_PASSES)),
-           "kernel_source_sha256_16=%s" % kernel_hash()]
+           "kernel_source_sha256_16=%s" % kernel_hash(TILE_SRCS if workload == "batched" else ())]
 
     def g(c, name):
         v = c.get(name)
@@ -1249,7 +1250,7 @@ def summarize_stats(stats_dir: str, solver: bool = False, batched: bool = False)
                 "# nnz=200201679, binary64 values and vectors, y=Ax / u^T=v^T A pairs on 4 rotating x and v:",
                 "# 3 + 20 profiled, 2 + 20 timed; then 2 + 20 on one x and v.",
                 "# command: %s ; python3 bench.py --stats-summary <dir>" % STATS_COMMAND]
-    out = head + ["kernel_source_sha256_16=%s" % kernel_hash(),
+    out = head + ["kernel_source_sha256_16=%s" % kernel_hash(TILE_SRCS if batched else ()),
                   "# columns: kernel | calls | average us | min us | max us | share of GPU time"]
     for name, calls, avg, mn, mx, pct in rows:
         out.append("%-56s %5d %10.2f %10.2f %10.2f %7.2f%%" % (kernel_label(name)[:56], calls, avg, mn, mx, pct))
