@@ -122,6 +122,26 @@ def test_batch_tiles_over_long_transpose(spw, fmt, k, dtype):
     M.close()
 
 
+@pytest.mark.parametrize("n", [1 << 18, (1 << 18) + 1])
+def test_batch_transpose_block_boundary(spw, n):
+    # a long side of exactly one block of the kept transpose, and one entry more
+    # (a second block holding a single long-side entry); each of the 64 short-side
+    # rows holds about 4,700 nonzeros, so its virtual columns span several chunks
+    L = np.full(n, 1, dtype=np.int64)
+    L[::7] = 2
+    A = synth.from_lengths(64, L, 90, values="lognormal")
+    k = 16
+    M = spw.SpwMatrix(0, A.m, A.n, A.ptr, A.idx, A.val, transpose=1)
+    M.set_batch_plan(spw.SPW_OP_MV, spw.SPW_F64, k, spw.SPW_PLAN_TILE)
+    X, Xd = block(A.n, k, 91, 1, torch.float64, 0)
+    print("transpose block boundary n=%d" % n, flush=True)
+    Y = M.mv_batch(Xd)
+    torch.cuda.synchronize()
+    Yr, D = oracle.mv_csc_batch(A.m, A.n, A.ptr, A.idx, A.val, X, with_d=True)
+    check(Y.cpu().numpy(), Yr, D, "transpose block boundary", 1e-13)
+    M.close()
+
+
 @pytest.mark.parametrize("fmt", [0, 1])
 @pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "wide_index"])
 def test_batch_structures(spw, fmt, case):
