@@ -276,10 +276,16 @@ __device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, co
     // b+1 and the words/values of block b+2 are being fetched.
     MvBlk<ValT> B0, B1;
     VecT x0[MV_ITEMS], x1[MV_ITEMS];
-    // padding slots hold word 0, so their gather reads x[column base]: no branch
+    // padding slots hold word 0, so their gather reads x[column base]: no branch.
+    // A unit-stride x (every single-vector call) takes 32-bit column offsets.
     auto gather = [&](const MvBlk<ValT> &B, VecT *xv) {
+        if (ldx == 1) {
 #pragma unroll
-        for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[(int64_t)(B.bd.x + (int)(B.w[j] & 0xFFFFu)) * ldx];
+            for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[B.bd.x + (int)(B.w[j] & 0xFFFFu)];
+        } else {
+#pragma unroll
+            for (int j = 0; j < MV_ITEMS; ++j) xv[j] = x[(int64_t)(B.bd.x + (int)(B.w[j] & 0xFFFFu)) * ldx];
+        }
     };
     auto add_block = [&](const MvBlk<ValT> &B, const VecT *xv, double *p, uint32_t *row) {
 #pragma unroll
@@ -289,6 +295,12 @@ __device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, co
         }
     };
     auto commit = [&](int count, const double *p, const uint32_t *row) {
+        if (count == MV_BLK) {                    // a full block: every item is a nonzero
+#pragma unroll
+            for (int j = 0; j < MV_ITEMS; ++j)
+                __hip_atomic_fetch_add(&ypan[row[j]], p[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
         const int lim = count - lane;             // item j is a nonzero when j*64 < lim
 #pragma unroll
         for (int j = 0; j < MV_ITEMS; ++j)
