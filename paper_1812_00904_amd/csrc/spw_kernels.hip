@@ -306,29 +306,30 @@ __device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, co
         for (int j = 0; j < MV_ITEMS; ++j)
             if (j * WAVE < lim) __hip_atomic_fetch_add(&ypan[row[j]], p[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
+    // The loads and gathers are issued on every path, of the last block again
+    // past the end of the range (so each buffer is written on every path and
+    // the compiler keeps the two in place instead of copying between them).
     if (b0 < b1) {
+        const int last = b1 - 1;
         mv_load<NT>(B0, packed, val, blocks, b0, lane);
         gather(B0, x0);
-        if (b0 + 1 < b1) mv_load<NT>(B1, packed, val, blocks, b0 + 1, lane);
-    }
-    for (int b = b0; b < b1; b += 2) {
-        double p[MV_ITEMS];
-        uint32_t row[MV_ITEMS];
-        add_block(B0, x0, p, row);
-        int cnt = B0.bd.y;
-        if (b + 1 < b1) {
+        mv_load<NT>(B1, packed, val, blocks, min(b0 + 1, last), lane);
+        for (int b = b0;; b += 2) {
+            double p[MV_ITEMS];
+            uint32_t row[MV_ITEMS];
+            add_block(B0, x0, p, row);
+            int cnt = B0.bd.y;
             gather(B1, x1);
-            if (b + 2 < b1) mv_load<NT>(B0, packed, val, blocks, b + 2, lane);
-        }
-        commit(cnt, p, row);
-        if (b + 1 >= b1) break;
-        add_block(B1, x1, p, row);
-        cnt = B1.bd.y;
-        if (b + 2 < b1) {
+            mv_load<NT>(B0, packed, val, blocks, min(b + 2, last), lane);
+            commit(cnt, p, row);
+            if (b + 1 >= b1) break;
+            add_block(B1, x1, p, row);
+            cnt = B1.bd.y;
             gather(B0, x0);
-            if (b + 3 < b1) mv_load<NT>(B1, packed, val, blocks, b + 3, lane);
+            mv_load<NT>(B1, packed, val, blocks, min(b + 3, last), lane);
+            commit(cnt, p, row);
+            if (b + 2 >= b1) break;
         }
-        commit(cnt, p, row);
     }
     __syncthreads();
     for (int i = tid; i < panel_rows; i += BLOCK) out[i] = ypan[i];
