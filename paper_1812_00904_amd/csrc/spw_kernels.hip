@@ -309,7 +309,21 @@ __device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, co
     // The loads and gathers are issued on every path, of the last block again
     // past the end of the range (so each buffer is written on every path and
     // the compiler keeps the two in place instead of copying between them).
-    if (b0 < b1) {
+    // Ranges of one or two blocks (small matrices) skip those repeats.
+    if (b0 < b1 && b1 - b0 <= 2) {
+        mv_load<NT>(B0, packed, val, blocks, b0, lane);
+        gather(B0, x0);
+        if (b1 - b0 == 2) mv_load<NT>(B1, packed, val, blocks, b0 + 1, lane);
+        double p[MV_ITEMS];
+        uint32_t row[MV_ITEMS];
+        add_block(B0, x0, p, row);
+        if (b1 - b0 == 2) gather(B1, x1);
+        commit(B0.bd.y, p, row);
+        if (b1 - b0 == 2) {
+            add_block(B1, x1, p, row);
+            commit(B1.bd.y, p, row);
+        }
+    } else if (b0 < b1) {
         const int last = b1 - 1;
         mv_load<NT>(B0, packed, val, blocks, b0, lane);
         gather(B0, x0);
