@@ -115,6 +115,11 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
             // later wait on either counter has to cover), and all LDS reads are
             // issued before the first global read, so none waits for another.
             VecT lv[ITEMS], gv[ITEMS];
+            // The wave issues its reads at raised priority and drops back for
+            // the product and the reduction: a wave with reads to issue then
+            // wins the issue slot over one that is reducing, which keeps more
+            // reads in flight per CU.
+            __builtin_amdgcn_s_setprio(3);
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) lv[i] = vh3[min(C.r.get(i), vhot - 1) * k + col];
 #pragma unroll
@@ -134,6 +139,7 @@ __global__ __launch_bounds__(BLOCK) void vtm_wave(
                 load_chunk(N, cn < cend ? cn : cc);
                 __builtin_amdgcn_sched_barrier(0);
             }
+            __builtin_amdgcn_s_setprio(0);
             // a select of the two loaded values, not of two addresses: the
             // gathers stay ahead of the prefetch
 #pragma unroll
