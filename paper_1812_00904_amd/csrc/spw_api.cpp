@@ -1536,13 +1536,13 @@ namespace {
 // transpose there, whose gathers of the caller's k-wide rows of X cross cache
 // lines unless k is a power of two), tiles from 16.  Column dots: each chunk
 // read once and reduced per column up to 6 columns, tiles from about 7 on.
-int32_t rule_plan(const spw_matrix_s &A, bool scatter, int32_t k, int64_t ldo)
+static int32_t rule_plan(const spw_matrix_s &A, bool scatter, int32_t k, int64_t ldo)
 {
     if (scatter) return (k < 16 || !A.cdt.built) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
     return (k <= 6 && ldo < CHUNK_OUT_LD_LIMIT) ? SPW_PLAN_PASSES : SPW_PLAN_TILE;
 }
 
-bool plan_runs(const spw_matrix_s &A, bool scatter, int32_t plan, int64_t ldo)
+static bool plan_runs(const spw_matrix_s &A, bool scatter, int32_t plan, int64_t ldo)
 {
     if (plan < SPW_PLAN_SINGLE || plan > SPW_PLAN_TILE) return false;
     if (scatter) return plan != SPW_PLAN_TILE || A.cdt.built;
@@ -1550,19 +1550,19 @@ bool plan_runs(const spw_matrix_s &A, bool scatter, int32_t plan, int64_t ldo)
     return plan == SPW_PLAN_TILE || ldo < CHUNK_OUT_LD_LIMIT;
 }
 
-int64_t plan_slot(bool scatter, spw_dtype vdt, int32_t k)
+static int64_t plan_slot(bool scatter, spw_dtype vdt, int32_t k)
 {
     return ((int64_t)(scatter ? 1 : 0) << 40) | ((int64_t)vdt << 32) | (int64_t)k;
 }
 
-std::string plan_cache_key(bool scatter, spw_dtype vdt, int32_t k)
+static std::string plan_cache_key(bool scatter, spw_dtype vdt, int32_t k)
 {
     return std::string("plan.") + (scatter ? "sc." : "cd.") + vdt_tag(vdt) + ".k" + std::to_string(k);
 }
 
 // The binary64 partial sums of the blocked transpose for k columns; grown
 // once the device is idle.  Returns a HIP error code.
-int grow_cdt_partial(spw_matrix_s &A, int32_t k)
+static int grow_cdt_partial(spw_matrix_s &A, int32_t k)
 {
     const int64_t need = A.cdt.cols * (int64_t)k;
     if (A.cdt_partial_elems >= need) return 0;
@@ -1584,8 +1584,8 @@ int grow_cdt_partial(spw_matrix_s &A, int32_t k)
 }
 
 // Runs a k-column product with one plan; returns a HIP error code.
-int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
-             void *out, int64_t ldo, void *stream)
+static int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t k, const void *in,
+                    int64_t ldi, void *out, int64_t ldo, void *stream)
 {
     const size_t es = vdt == SPW_F64 ? 8 : 4;
     if (plan == SPW_PLAN_TILE) {
@@ -1616,8 +1616,8 @@ int run_plan(spw_matrix_s &A, int32_t plan, bool scatter, spw_dtype vdt, int32_t
 
 // Times every plan that can run on the caller's buffers and stream (the
 // output is overwritten by each) and returns the fastest; 0 on a kernel error.
-int32_t tune_plan(spw_matrix_s &A, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi, void *out,
-                  int64_t ldo, void *stream, int *err)
+static int32_t tune_plan(spw_matrix_s &A, bool scatter, spw_dtype vdt, int32_t k, const void *in, int64_t ldi,
+                         void *out, int64_t ldo, void *stream, int *err)
 {
     double best = -1.0;
     int32_t choice = 0;
