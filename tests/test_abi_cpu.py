@@ -38,6 +38,27 @@ def test_every_declared_symbol_is_exported(spw):
     assert set(names) <= set(spw.SIGNATURES), set(names) - set(spw.SIGNATURES)
 
 
+def test_only_declared_c_symbols_are_exported(spw):
+    """Internal helpers keep internal linkage: every exported function with
+    an unmangled (C) name is one that include/spw.h declares."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm is not installed")
+    out = subprocess.run([nm, "-D", "--defined-only", spw.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set()
+    for line in out.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[1] in ("T", "W"):
+            name = parts[2]
+            if not name.startswith(("_Z", "__hip", "_init", "_fini")):
+                exported.add(name)
+    assert exported, "no exported C functions found"
+    assert exported <= set(declared_symbols()), sorted(exported - set(declared_symbols()))
+
+
 def test_status_strings(spw):
     lib = spw.load()
     for i, name in enumerate(spw.STATUS_NAMES):
