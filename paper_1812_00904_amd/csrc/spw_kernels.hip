@@ -277,9 +277,11 @@ __device__ __forceinline__ void mv_range(const uint32_t *__restrict__ packed, co
 
     const int32_t *wb = wg_blk + (int64_t)range * (NW + 1);
     const int b0 = wb[wave], b1 = wb[wave + 1];
-    // Two block buffers used alternately (no register copies, so no wait for
-    // data still in flight): while block b is added, the x entries of block
-    // b+1 and the words/values of block b+2 are being fetched.
+    // Two block buffers used alternately: while block b is added, the x
+    // entries of block b+1 and the words/values of block b+2 are being
+    // fetched.  (The compiler issues block b+1's gathers ahead of block b's
+    // products, so each step first waits for the words those gathers index;
+    // a form of this loop without that wait, tried, was no faster.)
     MvBlk<ValT> B0, B1;
     VecT x0[MV_ITEMS], x1[MV_ITEMS];
     // padding slots hold word 0, so their gather reads x[column base]: no branch.
