@@ -100,3 +100,16 @@ def test_counter_summary_bytes_by_request_size(tmp_path, monkeypatch):
 def test_counter_summary_rejects_unknown_workload(tmp_path):
     with pytest.raises(SystemExit):
         bench.summarize_counters("nonsense", [str(tmp_path)])
+
+
+def test_traffic_is_read_only_for_the_current_kernel_source(tmp_path, monkeypatch):
+    f = tmp_path / "counters.txt"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.read_traffic() is None                      # no summary at all
+    f.write_text("# header\nkernel_source_sha256_16=%s\nvtm_wave_bytes_per_launch=1234\n" % bench.kernel_hash())
+    kv = bench.read_traffic()
+    assert kv is not None and kv["vtm_wave_bytes_per_launch"] == "1234"
+    # a summary taken on another kernel source is not used
+    f.write_text("kernel_source_sha256_16=0000000000000000\nvtm_wave_bytes_per_launch=1234\n")
+    assert bench.read_traffic() is None
+
