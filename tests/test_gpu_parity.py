@@ -103,7 +103,8 @@ def test_small_config_full(spw, fmt):
 
 
 @pytest.mark.parametrize("fmt", FMTS)
-@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "single_col", "one_row"])
+@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "single_col", "one_row",
+                                  "far_apart"])
 def test_structures(spw, fmt, case):
     if case == "ragged":
         A = synth.random_csc(37, 5000, 5.0, 3, values="lognormal")
@@ -116,6 +117,14 @@ def test_structures(spw, fmt, case):
         A = synth.random_csc(3, 4, 2.0, 6)
     elif case == "single_col":
         A = synth.from_lengths(20000, np.array([20000]), 7)
+    elif case == "far_apart":
+        # 40 full columns 70,000 columns apart: scatter ranges that straddle
+        # two of them give a wave nonzeros of both, so its block must end
+        # (column offsets are 16 bits), and column-dot chunks hold runs of
+        # 69,999 empty columns
+        L = np.zeros(40 * 70000, dtype=np.int64)
+        L[::70000] = 64
+        A = synth.from_lengths(64, L, 10, values="lognormal")
     else:
         A = synth.from_lengths(1, np.r_[np.ones(9000, dtype=np.int64), np.zeros(100, dtype=np.int64)], 8)
     parity(spw, A, fmt, seed=2, reps=2, name=case)
