@@ -143,7 +143,7 @@ def test_batch_transpose_block_boundary(spw, n):
 
 
 @pytest.mark.parametrize("fmt", [0, 1])
-@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "wide_index"])
+@pytest.mark.parametrize("case", ["ragged", "many_empty", "dense_cols", "tiny", "wide_index", "far_apart"])
 def test_batch_structures(spw, fmt, case):
     if case == "ragged":
         A = synth.random_csc(37, 5000, 5.0, 3, values="lognormal")
@@ -154,10 +154,19 @@ def test_batch_structures(spw, fmt, case):
         A = synth.from_lengths(6000, L, 5, row_alpha=0.8, values="lognormal")
     elif case == "tiny":
         A = synth.random_csc(3, 4, 2.0, 6)
+    elif case == "far_apart":
+        # 40 full columns 70,000 columns apart (2.8M columns)
+        L = np.zeros(40 * 70000, dtype=np.int64)
+        L[::70000] = 64
+        A = synth.from_lengths(64, L, 10, values="lognormal")
     else:
         A = synth.random_csc(70000, 3000, 12.0, 10, values="lognormal", row_alpha=0.8)
     run_case(spw, A, fmt, 5, torch.float64, pad=3, seed=7, name=case)
     run_case(spw, A, fmt, 8, torch.float32, pad=0, seed=8, name=case)
+    if case == "far_apart":
+        # 16 columns take the tiles; the scatter direction runs over the kept
+        # transpose, whose 11 blocks of 2^18 columns are mostly empty
+        run_case(spw, A, fmt, 16, torch.float64, pad=1, seed=9, name=case, opts=dict(transpose=1))
 
 
 def test_batch_scaled_batching_config(spw):
