@@ -166,6 +166,11 @@ def test_batch_structures(spw, fmt, case):
     if case == "far_apart":
         # 16 columns take the tiles; the scatter direction runs over the kept
         # transpose, whose 11 blocks of 2^18 columns are mostly empty
+        m, n = (A.m, A.n) if fmt == 0 else (A.n, A.m)
+        M = spw.SpwMatrix(fmt, m, n, A.ptr, A.idx, A.val, transpose=1)
+        for op in (spw.SPW_OP_MV, spw.SPW_OP_VTM):
+            assert M.batch_plan(op, spw.SPW_F64, 16)[0] == spw.SPW_PLAN_TILE
+        M.close()
         run_case(spw, A, fmt, 16, torch.float64, pad=1, seed=9, name=case, opts=dict(transpose=1))
 
 
