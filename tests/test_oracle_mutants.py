@@ -45,6 +45,11 @@ MUTANTS = {
     "nzp_vtm_overwrites_zone": ("if (g > 0 && off[g] > ptr[j]) u[j] = u[j] + part;", "if (0) u[j] = u[j] + part;"),
     "nzp_mv_skips_first_group": ("for (int64_t r = 0; r < m; ++r) y[r] = y[r] + yi[r];",
                                  "for (int64_t r = 0; r < m; ++r) y[r] = g ? y[r] + yi[r] : y[r];"),
+    "colp_without_part_count": ("return (double)P * (double)(mx - mn) / (double)Z;",
+                                "return (double)(mx - mn) / (double)Z;"),
+    "colp_min_never_updated": ("if (mn < 0 || cnt < mn) mn = cnt;", "if (mn < 0) mn = cnt;"),
+    "colp_long_spans_last": ("int64_t j1 = j0 + (i < big ? q + 1 : q);",
+                             "int64_t j1 = j0 + (i >= P - big ? q + 1 : q);"),
     "cgls_residual_sign": ("r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
     "cgls_steepest_descent": ("const double beta = gamma > 0.0 ? gamma_new / gamma : 0.0;",
                               "const double beta = 0.0 * gamma_new;"),

@@ -404,6 +404,9 @@ def test_colp_imbalance_closed_form():
     assert oracle.colp_imbalance(8, ptr, 1) == 0.0
     # eight single-column spans: max 5, min 1
     assert oracle.colp_imbalance(8, ptr, 8) == pytest.approx(8 * (5 - 1) / 21)
+    # three spans, the first 8 mod 3 = 2 one column longer: columns 0-2, 3-5,
+    # 6-7 hold 8, 10 and 3 nonzeros
+    assert oracle.colp_imbalance(8, ptr, 3) == pytest.approx(3 * (10 - 3) / 21)
 
 
 # ---------------------------------------------------------------------------
