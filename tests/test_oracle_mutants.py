@@ -45,6 +45,7 @@ MUTANTS = {
     "nzp_vtm_overwrites_zone": ("if (g > 0 && off[g] > ptr[j]) u[j] = u[j] + part;", "if (0) u[j] = u[j] + part;"),
     "nzp_mv_skips_first_group": ("for (int64_t r = 0; r < m; ++r) y[r] = y[r] + yi[r];",
                                  "for (int64_t r = 0; r < m; ++r) y[r] = g ? y[r] + yi[r] : y[r];"),
+    "cover_last_is_first": ("jl[i] = col[off[i + 1] - 1];", "jl[i] = col[off[i]];"),
     "fixed_split_drops_short_chunk": ("int64_t G = (Z + C - 1) / C;", "int64_t G = Z / C;"),
     "colp_without_part_count": ("return (double)P * (double)(mx - mn) / (double)Z;",
                                 "return (double)(mx - mn) / (double)Z;"),
